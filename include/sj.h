@@ -1,0 +1,178 @@
+/*
+ * sj.h -- C ABI of the MI355X (gfx950) spatial-join library.
+ *
+ * The library computes the filter step of the spatial intersection join of
+ * Tsitsigkos, Bouros, Mamoulis and Terrovitis, "Parallel In-Memory Evaluation
+ * of Spatial Joins" (SIGSPATIAL 2019, arXiv 1908.11740):
+ *
+ *   given two collections R and S of axis-aligned rectangles (object MBRs),
+ *   return every pair (r, s), r in R, s in S, whose rectangles share at least
+ *   one point (Sec. 1, problem statement; Algorithm 1 input/output).
+ *
+ * It follows the paper's partition-based method (PBSM, Sec. 2.2): both inputs
+ * are assigned to every tile of a uniform K x K grid they intersect
+ * (partitioning phase, Sec. 3.4 steps 1-4), each tile's two lists are sorted
+ * by lower x-endpoint and joined with the forward-scan plane sweep of
+ * Algorithm 1 (joining phase, Sec. 3.4 steps 5-6), and a pair found in
+ * several tiles is reported only in the tile that holds the reference point
+ * of its intersection (Eq. (1)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Rectangles   n x 4 float32, array-of-structs (x_l, y_l, x_u, y_u), in
+ *              DEVICE memory, 16-byte aligned.  Every value must be finite and
+ *              x_l <= x_u, y_l <= y_u; otherwise the call returns SJ_ERR_RECT.
+ *              Intersection is closed: touching edges and corners count, and
+ *              zero-width or zero-height rectangles are allowed.  -0.0 is
+ *              treated as +0.0.
+ * Sizes        n < 2^30 rectangles per input; at most 2^31 - 1 tile entries
+ *              (rectangles times the tiles each one covers) per input.
+ * Pairs        sj_pair {r, s}: 0-based positions in the caller's R and S.
+ *              Each intersecting pair is reported exactly once.  The order is
+ *              unspecified; the set does not depend on K, the split threshold
+ *              or any launch shape.
+ * Streams      `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *              enqueued on it.  Entry points that return a count synchronise
+ *              that stream once to read it.
+ * Ownership    Input pointers are borrowed for the duration of the call (the
+ *              caller may free them once the stream has synchronised).
+ *              Output buffers are caller-owned.  sj_part and sj_ctx handles
+ *              are library-owned and released with their _free function.
+ * Errors       No exception or abort crosses the ABI; every failure is a
+ *              negative sj_status.  Handles are not thread-safe: calls that
+ *              use the same handle, or that run on the same device, must not
+ *              overlap in time.
+ */
+#ifndef SJ_H
+#define SJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SJ_OK = 0,
+    SJ_ERR_ARG = -1,           /* bad argument: NULL pointer, negative size, K out of range */
+    SJ_ERR_RECT = -2,          /* an input rectangle is NaN / infinite / inverted            */
+    SJ_ERR_CAPACITY = -3,      /* output buffer too small; *n_pairs holds the needed count   */
+    SJ_ERR_GRID_MISMATCH = -4, /* R and S were partitioned on different grids               */
+    SJ_ERR_OOM = -5,           /* device allocation failed                                   */
+    SJ_ERR_DEVICE = -6,        /* HIP runtime error, or no usable GPU                        */
+    SJ_ERR_TOO_LARGE = -7      /* input beyond the size limits above                         */
+} sj_status;
+
+/* Largest grid: K x K tiles with K <= SJ_K_MAX. */
+#define SJ_K_MAX 16384
+
+/* sj_grid.flags */
+#define SJ_PLAIN 0x1u           /* baseline schedule: one workgroup per tile, no dense-tile
+                                   splitting, no batching of small tiles                   */
+#define SJ_RULE_ONLY 0x2u       /* sj_choose_grid: use the statistics rule even if a
+                                   learned picker is loaded                                */
+
+/*
+ * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.2.2).
+ *   k          cells per dimension, 1..SJ_K_MAX.  0 in sj_choose_grid's input
+ *              means "choose".
+ *   split_tau  dense-tile split threshold: a tile whose two lists together
+ *              hold more than split_tau entries is joined by several
+ *              workgroups, each taking a contiguous range of at most
+ *              split_tau sweep pivots.  0 = library default; INT32_MAX =
+ *              never split.  Never changes the result.
+ *   domain     x0, y0, x1, y1 of the gridded region; all zero = the unit
+ *              square [0,1)^2 (the paper normalises data to [0,1], Sec. 4.1).
+ *              Rectangles outside it are clamped into the border tiles.
+ *   flags      SJ_PLAIN, SJ_RULE_ONLY.
+ * Tile (tx, ty) holds the rectangles whose cell ranges
+ * [cell(x_l), cell(x_u)] x [cell(y_l), cell(y_u)] contain it, with
+ * cell(v) = clamp(floor((v - x0) * K / (x1 - x0)), 0, K - 1) in float32.
+ */
+typedef struct {
+    int32_t k;
+    int32_t split_tau;
+    float domain[4];
+    uint32_t flags;
+} sj_grid;
+
+typedef struct {
+    int32_t r, s;
+} sj_pair;
+
+typedef struct sj_part sj_part; /* one partitioned input (library-owned, device memory) */
+
+/*
+ * Partitioning phase for one input (Sec. 3.4 steps 1-4; PBSM assignment of
+ * Sec. 2.2): validate the rectangles, count the entries of every tile,
+ * prefix-sum the counts into per-tile segment offsets and scatter each
+ * rectangle into the segment of every tile it intersects.
+ *   rects  n x 4 float32 AoS, device.
+ *   g      grid with 1 <= k <= SJ_K_MAX and a non-degenerate domain.
+ *   out    *out == NULL: a new handle is created.  *out != NULL: that handle
+ *          is reused (its device buffers grow only when too small).
+ * Synchronises the stream once (to size the segments).  On error *out is
+ * left as it was on entry.
+ */
+sj_status sj_partition(const float* rects, int64_t n, const sj_grid* g, sj_part** out,
+                       void* stream);
+
+/*
+ * Joining phase (Sec. 3.4 steps 5-6): per tile, sort both lists by x_l and
+ * run the forward-scan plane sweep of Algorithm 1; keep a pair only if the
+ * reference point of Eq. (1) lies in the tile.
+ *   R, S      handles partitioned on the same grid (k and domain), else
+ *             SJ_ERR_GRID_MISMATCH.  The split threshold and flags of R's
+ *             grid select the schedule.
+ *   out       device buffer of `capacity` pairs (may be NULL if capacity 0).
+ *   n_pairs   host; receives |J|.  If |J| > capacity the call returns
+ *             SJ_ERR_CAPACITY and the buffer contents are unspecified.
+ */
+sj_status sj_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
+                  int64_t* n_pairs, void* stream);
+
+/* As sj_join, counting |J| without writing pairs. */
+sj_status sj_join_count(const sj_part* R, const sj_part* S, int64_t* n_pairs, void* stream);
+
+/* Entries (rectangle-tile assignments) and rectangles of a partitioned input. */
+sj_status sj_part_info(const sj_part* P, int64_t* n_rects, int64_t* n_entries, sj_grid* g);
+
+/*
+ * Copy a partitioned input back to the host (for inspection and tests):
+ *   offsets   k*k + 1 int64: segment of tile t is [offsets[t], offsets[t+1]).
+ *   ids       n_entries int32 rectangle positions, grouped by tile (order
+ *             within a tile unspecified).
+ * Either pointer may be NULL.  Synchronises the stream.
+ */
+sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, void* stream);
+
+void sj_part_free(sj_part* P);
+
+const char* sj_status_string(sj_status s);
+
+/* Version string of the library build. */
+const char* sj_version(void);
+
+/* Detail of the last failure on the calling thread (HIP error text or the
+ * device status word); empty if none.  The string is library-owned. */
+const char* sj_last_error(void);
+
+/*
+ * Opt-in per-kernel timer (tracing).  sj_prof_enable(1) clears the totals and
+ * brackets every subsequent kernel launch of the library with a pair of HIP
+ * events on the launch's stream; sj_prof_enable(0) stops it.  sj_prof_collect
+ * waits for the recorded events, adds their elapsed times to per-kernel
+ * totals and returns the number of kernels with totals; entry i is read with
+ * sj_prof_name (library-owned string), sj_prof_total_ms and sj_prof_calls.
+ */
+void sj_prof_enable(int on);
+int sj_prof_collect(void);
+const char* sj_prof_name(int i);
+double sj_prof_total_ms(int i);
+int64_t sj_prof_calls(int i);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SJ_H */

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP join (through the C ABI) returns exactly the oracle's
+pair set, element by element after sorting, on every workload, grid size and
+schedule; plus the error contract of the ABI."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_11740_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_11740_amd import sj  # noqa: E402
+from gpu_util import gpu_join, to_dev  # noqa: E402
+
+SCHEDULES = {"tuned": dict(), "plain": dict(flags=sj.SJ_PLAIN),
+             "tau1": dict(split_tau=1), "nosplit": dict(split_tau=sj.INT32_MAX)}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small():
+    R, S, K = datagen.small_case()
+    return R, S, K, oracle.bruteforce(R, S)
+
+
+@pytest.mark.parametrize("sched", sorted(SCHEDULES))
+def test_small_case_k64(small, sched):
+    R, S, K, ref = small
+    say("small case K=64", sched)
+    got = gpu_join(R, S, K, **SCHEDULES[sched])
+    assert np.array_equal(got, ref)
+    assert gpu_join(R, S, K, count=True, **SCHEDULES[sched]) == len(ref)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 7, 33, 200, 1000, 4096])
+@pytest.mark.parametrize("sched", ["tuned", "plain"])
+def test_small_case_every_grid(small, K, sched):
+    R, S, _, ref = small
+    say("small case K", K, sched)
+    assert np.array_equal(gpu_join(R, S, K, **SCHEDULES[sched]), ref)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_adversarial(seed):
+    from test_oracle import adversarial
+    rng = np.random.default_rng(500 + seed)
+    K = int(rng.choice([1, 2, 3, 5, 7, 16, 64]))
+    R = adversarial(int(rng.integers(1, 400)), 3 * seed, K)
+    S = adversarial(int(rng.integers(1, 400)), 3 * seed + 1, K)
+    ref = oracle.bruteforce(R, S)
+    for k in sorted({K, 1, 3, 64}):
+        for sched in ("tuned", "plain", "tau1"):
+            say("adversarial seed", seed, "K", k, sched)
+            assert np.array_equal(gpu_join(R, S, k, **SCHEDULES[sched]), ref), (k, sched)
+
+
+def test_hand_layout_and_lattices():
+    from test_oracle import HAND_J, HAND_R, HAND_S, lattice
+    for k in (1, 3, 8):
+        got = gpu_join(HAND_R, HAND_S, k)
+        assert {tuple(x) for x in got.tolist()} == HAND_J
+    L = lattice(16)
+    assert len(gpu_join(L, L, 8)) == (3 * 16 - 2) ** 2
+    assert len(gpu_join(L, lattice(16, 0.5), 5)) == (2 * 16 - 1) ** 2
+
+
+def test_empty_and_one_sided():
+    S = datagen.uniform(100, 0.01, 3)
+    E = np.zeros((0, 4), np.float32)
+    assert len(gpu_join(E, S, 16)) == 0
+    assert len(gpu_join(S, E, 16)) == 0
+    assert len(gpu_join(E, E, 16)) == 0
+    assert gpu_join(E, S, 16, count=True) == 0
+
+
+def test_dense_single_tile_large():
+    # K = 1 puts everything in one tile: exercises the global sort of lists
+    # longer than one LDS sort (8192) and the split sweep.
+    R = datagen.uniform(20000, 0.003, 71)
+    S = datagen.uniform(15000, 0.003, 72)
+    ref = oracle.pbsm(R, S, 16)
+    for sched in ("tuned", "plain", "tau1"):
+        say("single tile", sched)
+        assert np.array_equal(gpu_join(R, S, 1, **SCHEDULES[sched]), ref)
+
+
+def test_caller_domain():
+    R, S, _ = datagen.small_case()
+    ref = oracle.bruteforce(R, S)
+    for dom in ([-1.0, -1.0, 2.0, 2.0], [0.25, 0.25, 0.75, 0.75]):
+        assert np.array_equal(gpu_join(R, S, 37, domain=dom), ref)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 16, 64])
+def test_partition_membership_matches_oracle(K):
+    from test_oracle import adversarial
+    A = adversarial(3000, 900 + K, K)
+    off_o, ids_o = oracle.partition_ids(A, K)
+    P = sj.partition(to_dev(A), K)
+    off_g, ids_g = P.download()
+    P.free()
+    assert np.array_equal(off_o, off_g)
+    for t in range(K * K):
+        a, b = off_o[t], off_o[t + 1]
+        assert np.array_equal(np.sort(ids_o[a:b]), np.sort(ids_g[a:b]))
+
+
+@pytest.fixture(scope="module")
+def uniform1m():
+    R, S = datagen.uniform_1m()
+    return R, S, oracle.pbsm(R, S, 1024)
+
+
+@pytest.mark.parametrize("K", list(datagen.UNIFORM_1M_GRIDS))
+@pytest.mark.parametrize("sched", ["tuned", "plain"])
+def test_uniform_1m_every_grid(uniform1m, K, sched):
+    R, S, ref = uniform1m
+    say("uniform 1M K", K, sched)
+    assert np.array_equal(gpu_join(R, S, K, **SCHEDULES[sched]), ref)
+    assert gpu_join(R, S, K, count=True, **SCHEDULES[sched]) == len(ref)
+
+
+@pytest.fixture(scope="module")
+def skewed10m():
+    R, S = datagen.skewed_10m()
+    return R, S
+
+
+def test_skewed_10m_tuned_and_plain(skewed10m):
+    R, S = skewed10m
+    K = 1213
+    ref = oracle.pbsm(R, S, K)
+    for sched in ("tuned", "plain"):
+        say("skewed 10M", sched)
+        got = gpu_join(R, S, K, **SCHEDULES[sched])
+        assert len(got) == len(ref)
+        assert np.array_equal(got, ref)
+
+
+# ----------------------------------------------------------------------------
+# Error contract
+# ----------------------------------------------------------------------------
+def test_invalid_rectangles_rejected():
+    base = datagen.uniform(1000, 0.01, 5)
+    for bad in ([np.nan, 0.1, 0.2, 0.2], [0.1, 0.1, np.inf, 0.2], [0.5, 0.1, 0.4, 0.2],
+                [0.1, 0.5, 0.2, 0.4]):
+        A = base.copy()
+        A[137] = bad
+        with pytest.raises(sj.SjError) as ei:
+            sj.partition(to_dev(A), 16)
+        assert ei.value.status == sj.SJ_ERR_RECT
+    # the library is still consistent afterwards
+    R, S, K = datagen.small_case()
+    assert np.array_equal(gpu_join(R, S, K), oracle.bruteforce(R, S))
+
+
+def test_grid_mismatch_and_bad_k():
+    R = to_dev(datagen.uniform(100, 0.01, 1))
+    P1 = sj.partition(R, 16)
+    P2 = sj.partition(R, 17)
+    with pytest.raises(sj.SjError) as ei:
+        sj.join_count(P1, P2)
+    assert ei.value.status == sj.SJ_ERR_GRID_MISMATCH
+    for k in (0, -3, sj.SJ_K_MAX + 1):
+        with pytest.raises(sj.SjError) as ei:
+            sj.partition(R, k)
+        assert ei.value.status == sj.SJ_ERR_ARG
+
+
+def test_capacity_reports_required_count():
+    R, S, K = datagen.small_case()
+    ref = oracle.bruteforce(R, S)
+    PR, PS = sj.partition(to_dev(R), K), sj.partition(to_dev(S), K)
+    for cap in (0, 1, len(ref) - 1):
+        out = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+        st, n = sj.join_into(PR, PS, out)
+        assert st == sj.SJ_ERR_CAPACITY and n == len(ref)
+    out = torch.empty((len(ref), 2), dtype=torch.int32, device="cuda")
+    st, n = sj.join_into(PR, PS, out)
+    assert st == sj.SJ_OK and n == len(ref)
+
+
+def test_handle_reuse_across_grids():
+    R, S, _ = datagen.small_case()
+    ref = oracle.bruteforce(R, S)
+    Rd, Sd = to_dev(R), to_dev(S)
+    PR = sj.partition(Rd, 8)
+    PS = sj.partition(Sd, 8)
+    for k in (8, 300, 2, 64):
+        sj.partition(Rd, k, reuse=PR)
+        sj.partition(Sd, k, reuse=PS)
+        got = np.asarray(sj.join(PR, PS).cpu().numpy())
+        got = got[np.lexsort((got[:, 1], got[:, 0]))]
+        assert np.array_equal(got, ref), k
