@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--split-tau", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--count", action="store_true", help="count-only join mode")
     return ap.parse_args()
 
 
@@ -102,6 +103,8 @@ def main():
     def step():
         state["PR"] = sj.partition(Rd, K, split_tau=args.split_tau, flags=flags, reuse=state["PR"])
         state["PS"] = sj.partition(Sd, K, split_tau=args.split_tau, flags=flags, reuse=state["PS"])
+        if args.count:
+            return sj.join_count(state["PR"], state["PS"])
         st, n = sj.join_into(state["PR"], state["PS"], state["out"])
         if st == sj.SJ_ERR_CAPACITY:
             state["out"] = torch.empty((int(n * 1.1) + 1024, 2), dtype=torch.int32, device="cuda")
@@ -168,7 +171,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_r": nR, "n_s": nS, "grid_k": K,
-                   "schedule": "plain" if args.plain else "tuned", "mode": "pairs"},
+                   "schedule": "plain" if args.plain else "tuned",
+                   "mode": "count" if args.count else "pairs"},
         "pairs_per_s": round(n_pairs / (ms * 1e-3), 1),
         "n_pairs": int(n_pairs),
         "pairs_match_oracle_count": verified,

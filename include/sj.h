@@ -64,13 +64,16 @@ typedef enum {
 } sj_status;
 
 /* Largest grid: K x K tiles with K <= SJ_K_MAX. */
-#define SJ_K_MAX 16384
+#define SJ_K_MAX 8192
 
 /* sj_grid.flags */
 #define SJ_PLAIN 0x1u           /* baseline schedule: one workgroup per tile, no dense-tile
                                    splitting, no batching of small tiles                   */
 #define SJ_RULE_ONLY 0x2u       /* sj_choose_grid: use the statistics rule even if a
                                    learned picker is loaded                                */
+#define SJ_TWO_PASS 0x4u        /* sj_join: count, scan, then write the pairs in a second
+                                   sweep instead of one sweep into scratch + compaction;
+                                   never changes the result                                */
 
 /*
  * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.2.2).
@@ -84,7 +87,7 @@ typedef enum {
  *   domain     x0, y0, x1, y1 of the gridded region; all zero = the unit
  *              square [0,1)^2 (the paper normalises data to [0,1], Sec. 4.1).
  *              Rectangles outside it are clamped into the border tiles.
- *   flags      SJ_PLAIN, SJ_RULE_ONLY.
+ *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS.
  * Tile (tx, ty) holds the rectangles whose cell ranges
  * [cell(x_l), cell(x_u)] x [cell(y_l), cell(y_u)] contain it, with
  * cell(v) = clamp(floor((v - x0) * K / (x1 - x0)), 0, K - 1) in float32.

@@ -12,122 +12,256 @@
 // scanned candidate gets the closed y-interval test and the reference-point
 // test; the union over pivots is exactly Algorithm 1's output for the tile.
 //
-// Schedules
-//   tuned:  tiles with both lists non-empty and at most `small_cap` entries
-//           are batched into LDS units of about `unit_cap` entries (built by
-//           k_classify); a persistent workgroup pulls units off an atomic
-//           queue, stages the unit's tile slabs in LDS, sorts every tile
-//           segment in LDS and sweeps from LDS.  Larger ("dense") tiles are
-//           sorted into a global buffer and swept by units of at most
-//           `split_tau` pivots, so one dense tile is shared by many CUs.
-//   plain:  one workgroup per tile (grid = K*K); tiles that fit LDS are
-//           sorted and swept there, larger tiles are sorted globally and
-//           swept by one workgroup each (no splitting).
+// Work units
+//   small:   tiles with both lists non-empty and at most `small_cap` entries
+//            are batched into LDS units of about `unit_cap` entries; one
+//            workgroup stages the unit's tile slabs in LDS, sorts every tile
+//            segment in LDS and sweeps from LDS.
+//   medium:  tiles up to `med_cap` entries, one per workgroup, same code with
+//            a larger LDS slab.
+//   dense:   larger tiles are sorted into a global buffer and swept by units
+//            of at most `split_tau` pivots, so one tile is shared by many CUs.
+//   plain:   (baseline) one workgroup per tile for every tile, LDS up to
+//            1024 entries, larger tiles dense without splitting.
 //
-// Pairs leave through a per-wave LDS staging buffer: lanes with a hit take
-// slots by ballot + masked popcount, and a full buffer is flushed with one
-// global atomic per wave and coalesced 8-byte stores.
+// Output without a shared counter: a device-wide atomic on one address
+// serialises at roughly 80 M/s on this GPU, so the join runs in two passes.
+// The counting pass writes each unit's pair count to its own slot; an
+// exclusive scan of the slots gives every unit an exclusive output region;
+// the writing pass stages pairs per wave in LDS (ballot + masked popcount
+// for the slots) and flushes them into the unit's region, reserving space
+// with an LDS atomic.  Count-only joins stop after the scan.
+#include <algorithm>
+
 #include "sj_internal.hpp"
 #include "sj_prof.hpp"
 
 namespace sj {
 
+hipError_t scan_u32(uint32_t* data, int64_t len, uint32_t* bs, unsigned long long* total,
+                    DevStatus* st, hipStream_t s);
+
 namespace {
 
 enum Ctr : int {
-    kUnitsTaken = 0,
-    kDenseSortTaken = 1,
-    kDenseUnitsTaken = 2,
-    kTilesWritten = 3,
-    kUnitsWritten = 4,
-    kDenseEntries = 5,
-    kDenseUnits = 6,
-    kDenseCount = 7,
-    kNumCtr = 8
+    kTilesWritten = 0,
+    kUnitsWritten = 1,
+    kMedCount = 2,
+    kDenseCount = 3,
+    kDenseEntries = 4,
+    kDenseUnits = 5,
+    kNumCtr = 6
 };
 
-constexpr int kWaveBuf = 256;    // staged pairs per wave
+constexpr int kWaveBuf = 256;        // staged pairs per wave (>= 64 lanes x kCand)
+constexpr int kMedNT = 512;          // workgroup of the medium-tile kernel
+constexpr int kMedE = 2048;          // LDS entries of a medium tile
 constexpr int kDenseSortMax = 8192;  // entries sorted in LDS by the dense sort
+constexpr int kDenseSortNT = 1024;
+constexpr int kDenseNT = 256;
 
 struct Args {
     const uint32_t* offR;
     const uint32_t* offS;
-    const float4* boxR;
-    const uint32_t* idfR;
-    const float4* boxS;
-    const uint32_t* idfS;
-    int64_t C;
-    int small_cap;   // LDS tiles: nr + ns <= small_cap
-    int unit_cap;    // entries per LDS unit (target)
-    int split_tau;
+    float4* boxR;     // tile slabs; the counting pass writes each slab back sorted
+    uint32_t* idfR;
+    float4* boxS;
+    uint32_t* idfS;
+    int64_t C;        // blocked tiles
+    int small_cap;    // small tiles: nr + ns <= small_cap
+    int unit_cap;     // entries per small unit (target)
+    int med_cap;      // medium tiles: small_cap < nr + ns <= med_cap
+    int split_tau;    // pivots per dense unit
     int plain;
-    int count_only;
-    uint32_t* tiles;
-    uint2* units;
-    uint4* dense;
-    uint32_t* dprefix;
-    int64_t cap_tiles, cap_units, cap_dense, cap_dent;
+    uint4* tinfo;     // small tiles: (R start, nr, S start, ns), grouped by unit
+    uint2* units;     // small units: (first tinfo index, tile count)
+    uint4* med;       // medium tiles: (R start, nr, S start, ns)
+    uint4* dense;     // dense tiles: (tile, base in dense buffer, nr, ns)
+    uint32_t* dprefix;  // dense units before each dense tile
+    int64_t cap_tiles, cap_units, cap_med, cap_dense, cap_dent, cap_dunits;
     float4* dbox;
     uint32_t* didf;
     unsigned long long* dtmp;
+    uint32_t* ucnt;   // per-unit pair counts, then (scanned) output offsets
+    int64_t base_med;    // slot of medium tile m: base_med + m
+    int64_t base_dense;  // slot of dense unit u: base_dense + u
     uint32_t* ctr;
     DevStatus* st;
     const DevStatus* stR;  // partition-time status of the two inputs
     const DevStatus* stS;
     unsigned long long* out;  // pairs as (r | s << 32)
     int64_t capacity;
+    int writeback;            // counting pass leaves the slabs sorted for a second pass
+    unsigned long long* sc_buf;   // single-pass scratch: kRegions x sc_nch chunks of kChunkP
+    uint32_t* sc_fills;           // fill level of every chunk, then their exclusive prefix
+    uint32_t* sc_ctr;             // [kRegions] chunks reserved per region
+    unsigned long long* sc_total; // [kTotals] hit totals
+    int64_t sc_nch;               // chunks per region
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-}
+__device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
 
 // ---------------------------------------------------------------------------
-// Per-wave pair emitter (wave-uniform state; every lane calls emit()).
+// Pair sink.  Three modes:
+//   kCount   per-lane counters, reduced into the unit's slot of the count
+//            array (first pass of the two-pass output; count-only joins).
+//   kWrite   second pass: per-wave LDS staging flushed into the unit's own
+//            output region (exclusive prefix of the counts), space reserved
+//            with an LDS atomic.
+//   kSingle  one pass: per-wave LDS staging flushed into scratch chunks of
+//            kChunkP pairs that the wave reserves from one of kRegions
+//            counters (a spread of addresses: a single device-wide counter
+//            serialises); chunk fill levels are compacted into the caller's
+//            buffer afterwards.  Every hit is counted even if the scratch
+//            runs out, so the exact count is always known.
+// BLOCK: the unit is processed by a whole workgroup (end() has barriers);
+// otherwise by one wavefront.
 // ---------------------------------------------------------------------------
-struct Emitter {
-    unsigned long long* buf;  // this wave's LDS buffer
-    uint32_t n;               // staged pairs (uniform)
-    unsigned long long cnt;   // pairs counted in count-only mode (uniform)
+enum Mode : int { kCount = 0, kWrite = 1, kSingle = 2 };
+constexpr int kRegions = 32;    // scratch regions / reservation counters
+constexpr int kChunkP = 512;    // pairs per scratch chunk
+constexpr int kTotals = 64;     // spread counters of the per-wave hit totals
+
+template <int MODE, bool BLOCK>
+struct Sink {
+    unsigned long long* buf;  // this wave's LDS staging buffer
+    uint32_t* s_acc;          // LDS word: pair count (kCount) or fill counter (kWrite)
+    uint32_t bufcap;          // staging capacity
+    uint32_t n;               // staged pairs (wave-uniform)
+    uint32_t cnt;             // this lane's pair count (kCount)
+    unsigned long long base;  // first output slot of the unit (kWrite)
+    uint32_t region, chunk, cfill;  // current scratch chunk (kSingle)
+    bool have, ok;
+    unsigned long long total;       // hits seen by this wave (kSingle)
+
+    __device__ void init(uint32_t wave_gid) {
+        n = 0;
+        cnt = 0;
+        base = 0;
+        region = wave_gid % kRegions;
+        chunk = 0;
+        cfill = 0;
+        have = false;
+        ok = true;
+        total = 0;
+    }
+
+    __device__ void begin(const Args& a, int64_t slot) {
+        cnt = 0;
+        if (MODE != kSingle) n = 0;
+        if (MODE == kWrite) {
+            base = a.ucnt[slot];
+            cfill = 0;
+        }
+        if (MODE != kSingle && BLOCK && threadIdx.x == 0) *s_acc = 0u;
+    }
 
     __device__ void flush(const Args& a) {
-        wave_lds_fence();
-        unsigned long long base = 0;
-        if (lane_id() == 0) base = atomicAdd(&a.st->n_pairs, (unsigned long long)n);
-        base = __shfl(base, 0, kWave);
-        for (uint32_t q = lane_id(); q < n; q += kWave) {
-            unsigned long long idx = base + q;
-            if (idx < (unsigned long long)a.capacity) a.out[idx] = buf[q];
+        lds_fence();
+        if (MODE == kWrite) {
+            uint32_t b = cfill;  // one wave per unit: a register counter
+            if (BLOCK) {
+                if (lane_id() == 0) b = atomicAdd(s_acc, n);
+                b = __shfl(b, 0, kWave);
+            }
+            cfill += n;
+            for (uint32_t q = lane_id(); q < n; q += kWave) {
+                const unsigned long long idx = base + b + q;
+                if (idx < (unsigned long long)a.capacity) a.out[idx] = buf[q];
+            }
+        } else if (MODE == kSingle) {
+            uint32_t done = 0;
+            while (ok && done < n) {
+                if (!have || cfill == (uint32_t)kChunkP) {
+                    if (have && lane_id() == 0)
+                        a.sc_fills[(size_t)region * a.sc_nch + chunk] = (uint32_t)kChunkP;
+                    uint32_t k = 0;
+                    if (lane_id() == 0) k = atomicAdd(&a.sc_ctr[region], 1u);
+                    k = __shfl(k, 0, kWave);
+                    have = true;
+                    chunk = k;
+                    cfill = 0;
+                    if ((int64_t)k >= a.sc_nch) {
+                        ok = false;
+                        have = false;
+                        if (lane_id() == 0) atomicOr(&a.st->flags, kStatScratch);
+                        break;
+                    }
+                }
+                const uint32_t take = min(n - done, (uint32_t)kChunkP - cfill);
+                unsigned long long* dst =
+                    a.sc_buf + ((size_t)region * a.sc_nch + chunk) * kChunkP + cfill;
+                for (uint32_t q = lane_id(); q < take; q += kWave) dst[q] = buf[done + q];
+                cfill += take;
+                done += take;
+            }
         }
-        wave_lds_fence();
+        lds_fence();
         n = 0;
     }
 
-    __device__ __forceinline__ void emit(const Args& a, bool hit, uint32_t r, uint32_t s) {
-        unsigned long long m = __ballot(hit);
-        if (m == 0ull) return;
-        uint32_t c = (uint32_t)__popcll(m);
-        if (a.count_only) {
-            cnt += c;
+    // Emit up to N pairs per lane (hit k -> (r[k], s[k])).  Every lane calls
+    // it; one flush check per call.
+    template <int N>
+    __device__ __forceinline__ void emit(const Args& a, const bool (&hit)[N], const uint32_t (&r)[N],
+                                         const uint32_t (&s)[N]) {
+        if (MODE == kCount) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) cnt += hit[k] ? 1u : 0u;
             return;
         }
-        if (n + c > (uint32_t)kWaveBuf) flush(a);
-        if (hit) buf[n + lanes_below(m)] = (unsigned long long)r | ((unsigned long long)s << 32);
-        n += c;
+        unsigned long long m[N];
+        uint32_t nh = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            m[k] = __ballot(hit[k]);
+            nh += (uint32_t)__popcll(m[k]);
+        }
+        if (nh == 0u) return;
+        if (MODE == kSingle) total += nh;
+        if (n + nh > bufcap) flush(a);
+        uint32_t at = n;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (hit[k]) buf[at + lanes_below(m[k])] = (unsigned long long)r[k] | ((unsigned long long)s[k] << 32);
+            at += (uint32_t)__popcll(m[k]);
+        }
+        n += nh;
     }
 
-    __device__ void finish(const Args& a) {
-        if (a.count_only) {
-            if (cnt && lane_id() == 0) atomicAdd(&a.st->n_pairs, cnt);
-            cnt = 0;
-        } else if (n) {
-            flush(a);
+    __device__ void end(const Args& a, int64_t slot) {
+        if (MODE == kWrite) {
+            if (n) flush(a);
+        } else if (MODE == kCount) {
+            uint32_t v = cnt;
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+            if (BLOCK) {
+                if (lane_id() == 0 && v) atomicAdd(s_acc, v);
+            } else if (lane_id() == 0) {
+                a.ucnt[slot] = v;
+            }
+        }
+        if (BLOCK) {
+            __syncthreads();
+            if (MODE == kCount && threadIdx.x == 0) a.ucnt[slot] = *s_acc;
+            __syncthreads();
+        }
+    }
+
+    // kernel end, every lane: the last staged pairs and the wave's totals
+    __device__ void finish(const Args& a, uint32_t wave_gid) {
+        if (MODE != kSingle) return;
+        if (n) flush(a);
+        if (lane_id() == 0) {
+            if (have && ok) a.sc_fills[(size_t)region * a.sc_nch + chunk] = cfill;
+            if (total) atomicAdd(&a.sc_total[wave_gid % kTotals], total);
         }
     }
 };
@@ -137,50 +271,13 @@ __device__ __forceinline__ bool ref_point_here(uint32_t ida, uint32_t idb) {
     return ((ida | idb) & (kBx | kBy)) == (kBx | kBy);
 }
 
-// ---------------------------------------------------------------------------
-// The sweep over one batch of pivots.  Acc provides, for entry j of the
-// batch's storage: xl(j), xu(j), yl(j), yu(j), id(j); and for a pivot p its
-// setup (own rectangle, other list's segment).  Lanes that finish a scan pick
-// the next pivot (p += stride), so a wave keeps all 64 lanes busy until the
-// batch runs dry.
-// ---------------------------------------------------------------------------
-template <class Acc>
-__device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_end, int stride,
-                             Emitter& em) {
-    int p = p_begin;
-    bool alive = false, isR = false;
-    int j = 0, jend = 0;
-    float pxu = 0.f, pyl = 0.f, pyu = 0.f;
-    uint32_t pid = 0;
-    if (p < p_end) alive = acc.setup(p, isR, j, jend, pxu, pyl, pyu, pid);
-    while (true) {
-        bool hit = false;
-        uint32_t rr = 0, ss = 0;
-        if (alive) {
-            if (j < jend && acc.xl(j) <= pxu) {
-                float ql = acc.yl(j), qu = acc.yu(j);
-                uint32_t qid = acc.id(j);
-                hit = (pyl <= qu) && (ql <= pyu) && ref_point_here(pid, qid);
-                rr = (isR ? pid : qid) & kIdMask;
-                ss = (isR ? qid : pid) & kIdMask;
-                ++j;
-            } else {
-                p += stride;
-                alive = (p < p_end) && acc.setup(p, isR, j, jend, pxu, pyl, pyu, pid);
-            }
-        }
-        em.emit(a, hit, rr, ss);
-        if (__ballot(alive) == 0ull) break;
-    }
-}
-
 // First index in [lo, hi) whose x_l is > v (upper) or >= v (lower).
 template <class F>
 __device__ __forceinline__ int search_x(const F& xl, int lo, int hi, float v, bool upper) {
     while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        float x = xl(mid);
-        bool go_right = upper ? (x <= v) : (x < v);
+        const int mid = (lo + hi) >> 1;
+        const float x = xl(mid);
+        const bool go_right = upper ? (x <= v) : (x < v);
         if (go_right) lo = mid + 1;
         else hi = mid;
     }
@@ -188,93 +285,197 @@ __device__ __forceinline__ int search_x(const F& xl, int lo, int hi, float v, bo
 }
 
 // ---------------------------------------------------------------------------
+// The sweep over one batch of pivots [p_begin, p_end).  Acc provides the
+// candidate entries of the batch's storage (box(j) = (x_l, y_l, x_u, y_u),
+// id(j)) and, for a pivot p, its setup (own rectangle; start and end of its
+// scan in the other list).  Each iteration examines up to kCand consecutive
+// candidates per lane, so their loads are in flight together.  Idle lanes
+// claim the next pivots from a workgroup-wide LDS counter (*next, zero on
+// entry; one atomic per wave and round), so scans of very different lengths
+// spread over all lanes of the workgroup.
+// ---------------------------------------------------------------------------
+constexpr int kCand = 4;
+constexpr int kChunkC = 8;  // consecutive candidates per lane and round (LDS units)
+
+template <int MODE, bool BLOCK, class Acc>
+__device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_end, uint32_t* next,
+                             Sink<MODE, BLOCK>& sk) {
+    bool scanning = false, exhausted = false, isR = false;
+    int j = 0, jend = 0;
+    float pxu = 0.f, pyl = 0.f, pyu = 0.f;
+    uint32_t pid = 0;
+    const int lane = lane_id();
+    while (true) {
+        // idle lanes claim pivots and find where their scans start
+        const bool need = !scanning && !exhausted;
+        const unsigned long long m = __ballot(need);
+        if (m) {
+            const int leader = __builtin_ctzll(m);
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(next, (uint32_t)__popcll(m));
+            base = __shfl(base, leader, kWave);
+            if (need) {
+                const int p = p_begin + (int)(base + lanes_below(m));
+                if (p < p_end) {
+                    acc.setup(p, isR, j, jend, pxu, pyl, pyu, pid);
+                    scanning = j < jend;
+                } else {
+                    exhausted = true;
+                }
+            }
+        }
+        // every scanning lane tests its next kCand candidates
+        bool hit[kCand];
+        uint32_t er[kCand], es[kCand];
+#pragma unroll
+        for (int k = 0; k < kCand; ++k) {
+            hit[k] = false;
+            er[k] = 0;
+            es[k] = 0;
+        }
+        if (scanning) {
+            float4 c[kCand];
+            uint32_t qid[kCand];
+#pragma unroll
+            for (int k = 0; k < kCand; ++k) {
+                const int idx = min(j + k, jend - 1);
+                c[k] = acc.box(idx);
+                qid[k] = acc.id(idx);
+            }
+            bool go = true;
+            int used = 0;
+            const uint32_t me = pid & kIdMask;
+#pragma unroll
+            for (int k = 0; k < kCand; ++k) {
+                go = go && (j + k < jend) && (c[k].x <= pxu);
+                hit[k] = go && (pyl <= c[k].w) && (c[k].y <= pyu) && ref_point_here(pid, qid[k]);
+                used += go ? 1 : 0;
+                const uint32_t other = qid[k] & kIdMask;
+                er[k] = isR ? me : other;
+                es[k] = isR ? other : me;
+            }
+            j += used;
+            scanning = go && j < jend;  // a candidate beyond x_u ends the scan
+        }
+        sk.template emit<kCand>(a, hit, er, es);
+        if (__ballot(scanning || !exhausted) == 0ull) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS unit: a batch of tiles staged, sorted and swept in LDS.
 // ---------------------------------------------------------------------------
 struct LdsLayout {
     unsigned long long* wbuf;  // [nwaves * kWaveBuf]
+    uint32_t* acc;             // [0] sink accumulator, [1] next pivot to claim
     uint32_t* rg;  // [tc+1] global start of each tile's R segment
     uint32_t* rl;  // [tc+1] local start (prefix) of each tile's R segment
     uint32_t* sg;
     uint32_t* sl;
     uint32_t* key;  // [E] unsorted order keys
     uint16_t* tk;   // [E] local tile of each entry
-    float* xl;      // [E] sorted payload (R part first, then S part)
-    float* yl;
-    float* xu;
-    float* yu;
-    uint32_t* id;
+    float4* bx;     // [E] sorted boxes (R part first, then S part)
+    uint32_t* id;   // [E] sorted id words
 };
 
-__host__ __device__ inline size_t lds_bytes(int nt, int E) {
-    const int tc = E / 2 + 2;
+__host__ __device__ inline size_t lds_bytes(int nt, int E, int tc) {
     size_t b = 0;
     b += (size_t)(nt / kWave) * kWaveBuf * 8;
+    b += 16;
     b += (size_t)4 * (tc + 1) * 4;
-    b += (size_t)E * 4;                  // key
-    b += (size_t)((E * 2 + 7) / 8) * 8;  // tk
-    b += (size_t)5 * E * 4;              // payload
+    b = (b + 15) / 16 * 16;
+    b += (size_t)E * 16;                  // boxes
+    b += (size_t)E * 4;                   // ids
+    b += (size_t)(E + 8) * 4;             // keys (+8: 128-bit loads past the end)
+    b += (size_t)((E * 2 + 15) / 16) * 16;  // tile indices
     return b;
 }
 
-__device__ inline LdsLayout carve(unsigned char* p, int nt, int E) {
-    const int tc = E / 2 + 2;
+__device__ inline LdsLayout carve(unsigned char* p, int nt, int E, int tc) {
     LdsLayout L;
     L.wbuf = (unsigned long long*)p;
     p += (size_t)(nt / kWave) * kWaveBuf * 8;
+    L.acc = (uint32_t*)p; p += 16;
     L.rg = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
     L.rl = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
     L.sg = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
     L.sl = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
-    L.key = (uint32_t*)p; p += (size_t)E * 4;
-    L.tk = (uint16_t*)p; p += (size_t)((E * 2 + 7) / 8) * 8;
-    L.xl = (float*)p; p += (size_t)E * 4;
-    L.yl = (float*)p; p += (size_t)E * 4;
-    L.xu = (float*)p; p += (size_t)E * 4;
-    L.yu = (float*)p; p += (size_t)E * 4;
-    L.id = (uint32_t*)p;
+    {
+        const size_t used = (size_t)((nt / kWave) * kWaveBuf * 8 + 16 + 4 * (tc + 1) * 4);
+        p += ((used + 15) / 16 * 16) - used;  // 16-byte alignment of the boxes
+    }
+    L.bx = (float4*)p; p += (size_t)E * 16;
+    L.id = (uint32_t*)p; p += (size_t)E * 4;
+    L.key = (uint32_t*)p; p += (size_t)(E + 8) * 4;
+    L.tk = (uint16_t*)p;
     return L;
+}
+
+// tile-table capacity of an LDS unit of E entries (every tile has >= 2)
+__host__ __device__ constexpr int tc_for(int E, bool batched) { return batched ? E / 2 + 2 : 2; }
+
+template <int MODE>
+__device__ inline Sink<MODE, true> make_sink(const LdsLayout& L) {
+    Sink<MODE, true> sk;
+    sk.buf = L.wbuf + (threadIdx.x / kWave) * kWaveBuf;
+    sk.s_acc = L.acc;
+    sk.bufcap = kWaveBuf;
+    sk.init(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    return sk;
 }
 
 struct LdsAcc {
     const LdsLayout* L;
     int NR;  // R entries of the unit; S entries start at NR
-    __device__ float xl(int j) const { return L->xl[j]; }
-    __device__ float yl(int j) const { return L->yl[j]; }
-    __device__ float yu(int j) const { return L->yu[j]; }
+    __device__ float4 box(int j) const { return L->bx[j]; }
     __device__ uint32_t id(int j) const { return L->id[j]; }
     __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxu, float& pyl, float& pyu,
                           uint32_t& pid) const {
         const int k = L->tk[p];
-        pxu = L->xu[p];
-        pyl = L->yl[p];
-        pyu = L->yu[p];
+        const float4 b = L->bx[p];
+        pxu = b.z;
+        pyl = b.y;
+        pyu = b.w;
         pid = L->id[p];
-        const float px = L->xl[p];
-        auto X = [&](int q) { return L->xl[q]; };
-        if (p < NR) {  // R pivot: scan S from the first s with s.x_l > r.x_l
-            isR = true;
-            int lo = NR + (int)L->sl[k], hi = NR + (int)L->sl[k + 1];
-            j = search_x(X, lo, hi, px, true);
-            jend = hi;
-        } else {  // S pivot: scan R from the first r with r.x_l >= s.x_l
-            isR = false;
-            int lo = (int)L->rl[k], hi = (int)L->rl[k + 1];
-            j = search_x(X, lo, hi, px, false);
-            jend = hi;
-        }
+        auto X = [&](int q) { return L->bx[q].x; };
+        // R pivot: scan S from the first s with s.x_l > r.x_l;
+        // S pivot: scan R from the first r with r.x_l >= s.x_l
+        isR = p < NR;
+        const int lo = isR ? NR + (int)L->sl[k] : (int)L->rl[k];
+        const int hi = isR ? NR + (int)L->sl[k + 1] : (int)L->rl[k + 1];
+        j = search_x(X, lo, hi, b.x, isR);
+        jend = hi;
         return true;
     }
 };
 
-// Stage tiles [0, c) -- given by tile_of(k) -- in LDS, sort every tile
-// segment by x_l and sweep.  Returns false if the unit did not fit (cannot
-// happen for units built by k_classify / the plain kernel).
-template <int NT, int Q, class TileOf>
+// Rank of (key[e], e) among the entries [lo, hi): the sorted position of e
+// within its segment (ties broken by position).  Eight keys per two 128-bit
+// LDS loads; key[] is 16-byte aligned and readable 8 entries past the end.
+__device__ __forceinline__ int seg_rank(const uint32_t* key, int lo, int hi, int e) {
+    const uint32_t my = key[e];
+    const uint4* k4 = (const uint4*)key;
+    int rank = 0;
+    for (int jb = lo & ~3; jb < hi; jb += 8) {
+        const uint4 A = k4[jb >> 2], B = k4[(jb >> 2) + 1];
+        const uint32_t kk[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int jj = jb + u;
+            rank += (jj >= lo && jj < hi) && (kk[u] < my || (kk[u] == my && jj < e));
+        }
+    }
+    return rank;
+}
+
+// Stage tiles [0, c) -- segment bounds from tile_of(k) -- in LDS, sort every
+// tile segment by x_l and sweep.  Every thread of the workgroup calls it.
+template <int NT, int Q, int TC, int MODE, class TileOf>
 __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const TileOf& tile_of,
-                             Emitter& em) {
+                             Sink<MODE, true>& sk) {
     constexpr int E = NT * Q;
     const int tid = threadIdx.x;
-    if (c > E / 2 + 1) {  // more tiles than the LDS tile table holds: cannot happen
+    if (c > TC) {  // more tiles than the LDS tile table holds: cannot happen
         if (tid == 0) atomicOr(&a.st->flags, kStatInternal);
         return;
     }
@@ -286,29 +487,37 @@ __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const Til
         const int k = k0 + tid;
         uint32_t nr = 0, ns = 0, r0 = 0, s0 = 0;
         if (k < c) {
-            const uint32_t t = tile_of(k);
-            r0 = a.offR[t];
-            nr = a.offR[t + 1] - r0;
-            s0 = a.offS[t];
-            ns = a.offS[t + 1] - s0;
+            const uint4 ti = tile_of(k);  // (R start, nr, S start, ns)
+            r0 = ti.x;
+            nr = ti.y;
+            s0 = ti.z;
+            ns = ti.w;
         }
-        // block exclusive scan of (nr, ns)
         const int lane = lane_id(), w = tid / kWave;
         uint32_t ir = nr, is = ns;
         for (int d = 1; d < kWave; d <<= 1) {
-            uint32_t tr = __shfl_up(ir, d, kWave), ts = __shfl_up(is, d, kWave);
-            if (lane >= d) { ir += tr; is += ts; }
+            const uint32_t tr = __shfl_up(ir, d, kWave), ts = __shfl_up(is, d, kWave);
+            if (lane >= d) {
+                ir += tr;
+                is += ts;
+            }
         }
-        if (lane == kWave - 1) { s_wsum[0][w] = ir; s_wsum[1][w] = is; }
+        if (lane == kWave - 1) {
+            s_wsum[0][w] = ir;
+            s_wsum[1][w] = is;
+        }
         __syncthreads();
         if (tid == 0) {
             uint32_t ar = 0, as = 0;
             for (int q = 0; q < NT / kWave; ++q) {
-                uint32_t vr = s_wsum[0][q], vs = s_wsum[1][q];
-                s_wsum[0][q] = ar; s_wsum[1][q] = as;
-                ar += vr; as += vs;
+                const uint32_t vr = s_wsum[0][q], vs = s_wsum[1][q];
+                s_wsum[0][q] = ar;
+                s_wsum[1][q] = as;
+                ar += vr;
+                as += vs;
             }
-            s_tot[0] = ar; s_tot[1] = as;
+            s_tot[0] = ar;
+            s_tot[1] = as;
         }
         __syncthreads();
         if (k < c) {
@@ -325,136 +534,591 @@ __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const Til
     if (tid == 0) {
         L.rl[c] = NR;
         L.sl[c] = NS;
+        L.acc[1] = 0u;  // pivot counter of the sweep
     }
     if (NE > E) {  // cannot happen for units built with unit_cap + small_cap <= E
         if (tid == 0) atomicOr(&a.st->flags, kStatInternal);
         __syncthreads();
         return;
     }
+    // 1b. local tile of every entry: mark each segment's first entry with its
+    //     tile (R part: k, S part: c + k, so the values rise along the array),
+    //     then an inclusive max-scan fills the segments
+#pragma unroll
+    for (int q = 0; q < Q; ++q) L.tk[tid * Q + q] = 0;
     __syncthreads();
-    // 2. load entries (coalesced within each tile segment), keep payload in
-    //    registers, publish keys and tile indices
+    for (int k = tid; k < c; k += NT) {
+        if (L.rl[k + 1] > L.rl[k]) L.tk[L.rl[k]] = (uint16_t)k;
+        if (L.sl[k + 1] > L.sl[k]) L.tk[NR + L.sl[k]] = (uint16_t)(c + k);
+    }
+    __syncthreads();
+    {
+        uint32_t v[Q];
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t x = L.tk[tid * Q + q];
+            run = x > run ? x : run;
+            v[q] = run;
+        }
+        const int lane = lane_id(), w = tid / kWave;
+        uint32_t inc = run;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc = t > inc ? t : inc;
+        }
+        if (lane == kWave - 1) s_wsum[0][w] = inc;
+        uint32_t ex = __shfl_up(inc, 1, kWave);
+        if (lane == 0) ex = 0;
+        __syncthreads();
+        for (int q = 0; q < w; ++q) ex = s_wsum[0][q] > ex ? s_wsum[0][q] : ex;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = tid * Q + q;
+            const uint32_t t = v[q] > ex ? v[q] : ex;
+            if (i < NE) L.tk[i] = (uint16_t)(i < NR ? t : t - (uint32_t)c);
+        }
+    }
+    __syncthreads();
+    // 2. load entries (coalesced within each tile segment)
     float4 pb[Q];
-    uint32_t pi[Q];
-    int pk[Q];
+    uint32_t pi[Q], pg[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int e = tid + q * NT;
-        pk[q] = -1;
+        pg[q] = 0xFFFFFFFFu;
         if (e < NE) {
             const bool isR = e < NR;
-            const int le = isR ? e : e - NR;
-            const uint32_t* loc = isR ? L.rl : L.sl;
-            // tile k: last k with loc[k] <= le
-            int lo = 0, hi = c;  // loc[c] = total > le
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (loc[mid] <= (uint32_t)le) lo = mid;
-                else hi = mid;
-            }
-            const int k = lo;
-            const uint32_t g = (isR ? L.rg[k] : L.sg[k]) + (uint32_t)le - loc[k];
+            const int k = L.tk[e];
+            const uint32_t g = isR ? L.rg[k] + (uint32_t)e - L.rl[k]
+                                   : L.sg[k] + (uint32_t)(e - NR) - L.sl[k];
             pb[q] = isR ? a.boxR[g] : a.boxS[g];
             pi[q] = isR ? a.idfR[g] : a.idfS[g];
-            pk[q] = k;
-            L.key[e] = order_key(pb[q].x);
-            L.tk[e] = (uint16_t)k;
+            pg[q] = g;
+            if (MODE == kWrite) {  // the counting pass left every slab sorted
+                L.bx[e] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
+                L.id[e] = pi[q];
+            } else {
+                L.key[e] = order_key(pb[q].x);
+            }
         }
     }
     __syncthreads();
-    // 3. rank sort within each tile segment, write sorted payload
+    if (MODE != kWrite) {
+        // 3. rank sort within each tile segment, write the sorted payload to
+        //    LDS and back to the slab in global memory
+        int pos[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = tid + q * NT;
+            pos[q] = -1;
+            if (e < NE) {
+                const bool isR = e < NR;
+                const int k = L.tk[e];
+                const int lo = isR ? (int)L.rl[k] : NR + (int)L.sl[k];
+                const int hi = isR ? (int)L.rl[k + 1] : NR + (int)L.sl[k + 1];
+                pos[q] = lo + seg_rank(L.key, lo, hi, e);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (pos[q] >= 0) {
+                L.bx[pos[q]] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
+                L.id[pos[q]] = pi[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = tid + q * NT;
+            if (MODE == kCount && a.writeback && e < NE) {
+                const float4 b = L.bx[e];
+                if (e < NR) {
+                    a.boxR[pg[q]] = b;
+                    a.idfR[pg[q]] = L.id[e];
+                } else {
+                    a.boxS[pg[q]] = b;
+                    a.idfS[pg[q]] = L.id[e];
+                }
+            }
+        }
+    }
+    // 4. sweep
+    __syncthreads();
+    // 4a. exact forward-scan range [j0, j1) of every pivot p in the other
+    //     list of its tile: R pivot: the s with  r.x_l < s.x_l <= r.x_u,
+    //     S pivot: the r with  s.x_l <= r.x_l <= s.x_u.  The range length
+    //     goes to cnt[p] (in place of the sort keys), j0 to js[p] (in place
+    //     of the tile index, read first by the same thread).
+    uint32_t* cnt = L.key;
+    uint16_t* js = L.tk;
+    auto X = [&](int q) { return L.bx[q].x; };
+    uint32_t v[Q];
+    uint32_t sum = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int e = tid + q * NT;
-        if (e < NE) {
-            const bool isR = e < NR;
-            const int k = pk[q];
-            const int lo = isR ? (int)L.rl[k] : NR + (int)L.sl[k];
-            const int hi = isR ? (int)L.rl[k + 1] : NR + (int)L.sl[k + 1];
-            const uint32_t my = L.key[e];
-            int rank = 0;
-            for (int j = lo; j < hi; ++j) {
-                const uint32_t kj = L.key[j];
-                rank += (kj < my) || (kj == my && j < e);
-            }
-            const int pos = lo + rank;
-            L.xl[pos] = pb[q].x;
-            L.yl[pos] = pb[q].y;
-            L.xu[pos] = pb[q].z;
-            L.yu[pos] = pb[q].w;
-            L.id[pos] = pi[q];
+        const int p = tid * Q + q;
+        v[q] = 0;
+        if (p < NE) {
+            const int k = L.tk[p];
+            const float4 b = L.bx[p];
+            const bool isR = p < NR;
+            const int lo = isR ? NR + (int)L.sl[k] : (int)L.rl[k];
+            const int hi = isR ? NR + (int)L.sl[k + 1] : (int)L.rl[k + 1];
+            const int j0 = search_x(X, lo, hi, b.x, isR);
+            const int j1 = search_x(X, j0, hi, b.z, true);
+            v[q] = (uint32_t)(j1 - j0);
+            js[p] = (uint16_t)j0;
         }
+        sum += v[q];
+    }
+    // 4b. exclusive prefix of the range lengths (candidate index space)
+    {
+        const int lane = lane_id(), w = tid / kWave;
+        uint32_t inc = sum;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += t;
+        }
+        if (lane == kWave - 1) s_wsum[1][w] = inc;
+        __syncthreads();
+        uint32_t ex = inc - sum, total = 0;
+        for (int q = 0; q < NT / kWave; ++q) {
+            if (q < w) ex += s_wsum[1][q];
+            total += s_wsum[1][q];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int p = tid * Q + q;
+            if (p < NE) cnt[p] = ex;
+            ex += v[q];
+        }
+        if (tid == 0) cnt[NE] = total;
     }
     __syncthreads();
-    // 4. sweep: one lane per pivot, pivots = all entries of the unit
-    LdsAcc acc{&L, NR};
-    sweep_pivots(a, acc, tid, NE, NT, em);
-    __syncthreads();
+    // 4c. every lane takes chunks of kChunkC consecutive candidates, so long
+    //     scans are shared by many lanes; each candidate gets the closed
+    //     y-test and the reference-point test of Eq. (1)
+    const uint32_t T = cnt[NE];
+    // the trip count is uniform over the workgroup (the sink needs all lanes)
+    for (uint32_t it = 0; it * (uint32_t)(NT * kChunkC) < T; ++it) {
+        const uint32_t c0 = it * (uint32_t)(NT * kChunkC) + (uint32_t)tid * kChunkC;
+        const uint32_t cs = c0 < T ? c0 : T - 1u;
+        int lo = 0, hi = NE;  // pivot of candidate cs: last p with cnt[p] <= cs
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cnt[mid] <= cs) lo = mid;
+            else hi = mid;
+        }
+        int p = lo;
+        uint32_t pend = cnt[p + 1];
+        float4 pb4 = L.bx[p];
+        uint32_t pid = L.id[p];
+#pragma unroll
+        for (int i = 0; i < kChunkC; ++i) {
+            const uint32_t cc = c0 + (uint32_t)i;
+            const bool valid = cc < T;
+            if (valid && cc >= pend) {
+                do {
+                    ++p;
+                    pend = cnt[p + 1];
+                } while (cc >= pend);
+                pb4 = L.bx[p];
+                pid = L.id[p];
+            }
+            bool hit[1] = {false};
+            uint32_t er[1] = {0}, es[1] = {0};
+            if (valid) {
+                const int j = (int)js[p] + (int)(cc - cnt[p]);
+                const float4 q4 = L.bx[j];
+                const uint32_t qid = L.id[j];
+                hit[0] = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
+                const bool isR = p < NR;
+                er[0] = (isR ? pid : qid) & kIdMask;
+                es[0] = (isR ? qid : pid) & kIdMask;
+            }
+            sk.template emit<1>(a, hit, er, es);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// k_classify (tuned schedule): find active tiles, batch the small ones into
-// LDS units, list the dense ones.  One block covers kClassChunk tiles; units
-// never cross block chunks.
+// Wave units: small tiles are batched into units of at most kWE entries and
+// every wavefront processes its own units in a private LDS region, with
+// wave-level fences only.  Without workgroup barriers the waves of a CU
+// overlap one another's memory waits.  Same steps as run_lds_unit: stage the
+// unit's tile slabs, sort each tile segment by x_l (counting pass, written
+// back sorted), then the load-balanced candidate ranges of the sweep.
+// ---------------------------------------------------------------------------
+constexpr int kWNT = 256;               // threads per workgroup (4 independent waves)
+constexpr int kWQ = 4;                  // entries per lane
+constexpr int kWE = kWave * kWQ;        // entries per wave unit
+constexpr int kWTC = kWE / 2 + 1;       // tiles per wave unit (each has >= 2 entries)
+constexpr int kWBuf = 128;              // staged pairs per wave
+
+struct WaveLds {
+    float4 bx[kWE];                     // sorted boxes (R part, then S part)
+    uint32_t id[kWE];                   // sorted id words
+    uint32_t key[kWE + 8];              // sort keys, then candidate-range prefix
+    uint32_t rg[kWTC + 1], rl[kWTC + 1], sg[kWTC + 1], sl[kWTC + 1];
+    unsigned long long wbuf[kWBuf];     // pair staging (writing pass)
+    uint16_t tk[kWE];                   // local tile of each entry, then scan starts
+};
+
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, int lane) {
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v, int lane) {
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v = t > v ? t : v;
+    }
+    return v;
+}
+
+template <int MODE>
+__device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, false>& sk) {
+    const int lane = lane_id();
+    const uint2 ud = a.units[u];
+    const int c = (int)ud.y;
+    if (c > kWTC) {  // cannot happen for units built by k_classify
+        if (lane == 0) atomicOr(&a.st->flags, kStatInternal);
+        return;
+    }
+    // 1. tile table: lane l holds tiles 2l and 2l+1
+    uint4 t0 = make_uint4(0, 0, 0, 0), t1 = make_uint4(0, 0, 0, 0);
+    if (2 * lane < c) t0 = a.tinfo[ud.x + 2 * lane];
+    if (2 * lane + 1 < c) t1 = a.tinfo[ud.x + 2 * lane + 1];
+    const uint32_t ir = wave_incl_sum(t0.y + t1.y, lane);
+    const uint32_t is = wave_incl_sum(t0.w + t1.w, lane);
+    const int NR = __shfl((int)ir, kWave - 1, kWave), NS = __shfl((int)is, kWave - 1, kWave);
+    const int NE = NR + NS;
+    if (NE > kWE) {
+        if (lane == 0) atomicOr(&a.st->flags, kStatInternal);
+        return;
+    }
+    {
+        const uint32_t r0 = ir - t0.y - t1.y, s0 = is - t0.w - t1.w;
+        if (2 * lane < c) {
+            W.rg[2 * lane] = t0.x;
+            W.sg[2 * lane] = t0.z;
+            W.rl[2 * lane] = r0;
+            W.sl[2 * lane] = s0;
+        }
+        if (2 * lane + 1 < c) {
+            W.rg[2 * lane + 1] = t1.x;
+            W.sg[2 * lane + 1] = t1.z;
+            W.rl[2 * lane + 1] = r0 + t0.y;
+            W.sl[2 * lane + 1] = s0 + t0.w;
+        }
+        if (lane == 0) {
+            W.rl[c] = (uint32_t)NR;
+            W.sl[c] = (uint32_t)NS;
+        }
+    }
+    // 1b. local tile of every entry: head marks (R: k, S: c + k) + max-scan
+#pragma unroll
+    for (int q = 0; q < kWQ; ++q) W.tk[lane * kWQ + q] = 0;
+    wave_fence();
+    for (int k = lane; k < c; k += kWave) {
+        if (W.rl[k + 1] > W.rl[k]) W.tk[W.rl[k]] = (uint16_t)k;
+        if (W.sl[k + 1] > W.sl[k]) W.tk[NR + W.sl[k]] = (uint16_t)(c + k);
+    }
+    wave_fence();
+    {
+        uint32_t v[kWQ];
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < kWQ; ++q) {
+            const uint32_t x = W.tk[lane * kWQ + q];
+            run = x > run ? x : run;
+            v[q] = run;
+        }
+        const uint32_t inc = wave_incl_max(run, lane);
+        uint32_t ex = __shfl_up(inc, 1, kWave);
+        if (lane == 0) ex = 0;
+        wave_fence();
+#pragma unroll
+        for (int q = 0; q < kWQ; ++q) {
+            const int i = lane * kWQ + q;
+            const uint32_t t = v[q] > ex ? v[q] : ex;
+            if (i < NE) W.tk[i] = (uint16_t)(i < NR ? t : t - (uint32_t)c);
+        }
+    }
+    wave_fence();
+    // 2. load the entries (coalesced within each tile segment)
+    float4 pb[kWQ];
+    uint32_t pi[kWQ], pg[kWQ];
+#pragma unroll
+    for (int q = 0; q < kWQ; ++q) {
+        const int e = lane + q * kWave;
+        if (e < NE) {
+            const bool isR = e < NR;
+            const int k = W.tk[e];
+            const uint32_t g = isR ? W.rg[k] + (uint32_t)e - W.rl[k] : W.sg[k] + (uint32_t)(e - NR) - W.sl[k];
+            pb[q] = isR ? a.boxR[g] : a.boxS[g];
+            pi[q] = isR ? a.idfR[g] : a.idfS[g];
+            pg[q] = g;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kWQ; ++q) {
+        const int e = lane + q * kWave;
+        if (e < NE) {
+            if (MODE == kWrite) {  // the counting pass left every slab sorted
+                W.bx[e] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
+                W.id[e] = pi[q];
+            } else {
+                W.key[e] = order_key(pb[q].x);
+            }
+        }
+    }
+    wave_fence();
+    if (MODE != kWrite) {
+        // 3. rank sort inside each tile segment; sorted slab to LDS and back
+        //    to global memory
+        int pos[kWQ];
+#pragma unroll
+        for (int q = 0; q < kWQ; ++q) {
+            const int e = lane + q * kWave;
+            pos[q] = -1;
+            if (e < NE) {
+                const bool isR = e < NR;
+                const int k = W.tk[e];
+                const int lo = isR ? (int)W.rl[k] : NR + (int)W.sl[k];
+                const int hi = isR ? (int)W.rl[k + 1] : NR + (int)W.sl[k + 1];
+                pos[q] = lo + seg_rank(W.key, lo, hi, e);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kWQ; ++q) {
+            if (pos[q] >= 0) {
+                W.bx[pos[q]] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
+                W.id[pos[q]] = pi[q];
+            }
+        }
+        wave_fence();
+#pragma unroll
+        for (int q = 0; q < kWQ; ++q) {
+            const int e = lane + q * kWave;
+            if (MODE == kCount && a.writeback && e < NE) {
+                const float4 b = W.bx[e];
+                const uint32_t idv = W.id[e];
+                if (e < NR) {
+                    a.boxR[pg[q]] = b;
+                    a.idfR[pg[q]] = idv;
+                } else {
+                    a.boxS[pg[q]] = b;
+                    a.idfS[pg[q]] = idv;
+                }
+            }
+        }
+    }
+    // 4a. exact forward-scan range of every pivot (see run_lds_unit)
+    uint32_t* cnt = W.key;
+    auto X = [&](int q) { return W.bx[q].x; };
+    uint32_t v[kWQ];
+    uint32_t sum = 0;
+    uint16_t jsv[kWQ];
+#pragma unroll
+    for (int q = 0; q < kWQ; ++q) {
+        const int p = lane * kWQ + q;
+        v[q] = 0;
+        jsv[q] = 0;
+        if (p < NE) {
+            const int k = W.tk[p];
+            const float4 b = W.bx[p];
+            const bool isR = p < NR;
+            const int lo = isR ? NR + (int)W.sl[k] : (int)W.rl[k];
+            const int hi = isR ? NR + (int)W.sl[k + 1] : (int)W.rl[k + 1];
+            const int j0 = search_x(X, lo, hi, b.x, isR);
+            const int j1 = search_x(X, j0, hi, b.z, true);
+            v[q] = (uint32_t)(j1 - j0);
+            jsv[q] = (uint16_t)j0;
+        }
+        sum += v[q];
+    }
+    wave_fence();
+    // 4b. exclusive prefix of the range lengths
+    const uint32_t incs = wave_incl_sum(sum, lane);
+    const uint32_t T = __shfl(incs, kWave - 1, kWave);
+    {
+        uint32_t ex = incs - sum;
+#pragma unroll
+        for (int q = 0; q < kWQ; ++q) {
+            const int p = lane * kWQ + q;
+            if (p < NE) {
+                cnt[p] = ex;
+                W.tk[p] = jsv[q];
+            }
+            ex += v[q];
+        }
+        if (lane == 0) cnt[NE] = T;
+    }
+    wave_fence();
+    // 4c. chunks of kChunkC consecutive candidates per lane
+    sk.begin(a, u);
+    for (uint32_t it = 0; it * (uint32_t)(kWave * kChunkC) < T; ++it) {
+        const uint32_t c0 = it * (uint32_t)(kWave * kChunkC) + (uint32_t)lane * kChunkC;
+        const uint32_t cs = c0 < T ? c0 : T - 1u;
+        int lo = 0, hi = NE;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cnt[mid] <= cs) lo = mid;
+            else hi = mid;
+        }
+        int p = lo;
+        uint32_t pend = cnt[p + 1];
+        float4 pb4 = W.bx[p];
+        uint32_t pid = W.id[p];
+#pragma unroll
+        for (int i = 0; i < kChunkC; ++i) {
+            const uint32_t cc = c0 + (uint32_t)i;
+            const bool valid = cc < T;
+            if (valid && cc >= pend) {
+                do {
+                    ++p;
+                    pend = cnt[p + 1];
+                } while (cc >= pend);
+                pb4 = W.bx[p];
+                pid = W.id[p];
+            }
+            bool hit[1] = {false};
+            uint32_t er[1] = {0}, es[1] = {0};
+            if (valid) {
+                const int j = (int)W.tk[p] + (int)(cc - cnt[p]);
+                const float4 q4 = W.bx[j];
+                const uint32_t qid = W.id[j];
+                hit[0] = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
+                const bool isR = p < NR;
+                er[0] = (isR ? pid : qid) & kIdMask;
+                es[0] = (isR ? qid : pid) & kIdMask;
+            }
+            sk.template emit<1>(a, hit, er, es);
+        }
+    }
+    sk.end(a, u);
+    wave_fence();
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kWNT) void k_wave_units(Args a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    WaveLds& W = ((WaveLds*)smem)[threadIdx.x / kWave];
+    const uint32_t nu = min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
+    const uint32_t waves = gridDim.x * (kWNT / kWave);
+    const uint32_t wg = blockIdx.x * (kWNT / kWave) + threadIdx.x / kWave;
+    Sink<MODE, false> sk;
+    sk.buf = W.wbuf;
+    sk.s_acc = nullptr;
+    sk.bufcap = kWBuf;
+    sk.init(wg);
+    for (uint32_t u = wg; u < nu; u += waves) run_wave_unit<MODE>(a, W, u, sk);
+    sk.finish(a, wg);
+}
+
+// ---------------------------------------------------------------------------
+// k_classify: find the tiles with both lists non-empty and sort them into
+// three classes by entry count n = nr + ns (small / medium / dense).  One
+// block covers kClassChunk tiles; small units never cross block chunks.  A
+// tile's segment bounds are written with it, so the join kernels need no
+// dependent loads of the offset arrays.
 // ---------------------------------------------------------------------------
 constexpr int kClassNT = 256;
 constexpr int kClassPer = 8;
 constexpr int kClassChunk = kClassNT * kClassPer;
 
+__device__ __forceinline__ void append_dense(const Args& a, uint32_t t, uint32_t nr, uint32_t ns) {
+    const uint32_t d = atomicAdd(&a.ctr[kDenseCount], 1u);
+    const uint32_t base = atomicAdd(&a.ctr[kDenseEntries], nr + ns);
+    if (d < (uint32_t)a.cap_dense && (int64_t)base + nr + ns <= a.cap_dent)
+        a.dense[d] = make_uint4(t, base, nr, ns);
+    else
+        atomicOr(&a.st->flags, kStatCapacity);
+}
+
 __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
     __shared__ uint32_t s_uidx[kClassChunk];  // unit index of the k-th small tile
-    __shared__ uint32_t s_ws[3][kClassNT / kWave];
-    __shared__ uint32_t s_base[2];
+    __shared__ uint32_t s_ws[4][kClassNT / kWave];
+    __shared__ uint32_t s_base[3];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const int64_t t0 = (int64_t)blockIdx.x * kClassChunk + (int64_t)tid * kClassPer;
-    uint32_t nsmall = 0, size_small = 0;
-    uint32_t sz[kClassPer];
-    uint8_t cls[kClassPer];  // 0 none, 1 small, 2 dense
+    uint32_t nsmall = 0, size_small = 0, nmed = 0;
+    uint4 ti[kClassPer];
+    uint8_t cls[kClassPer];  // 0 none, 1 small, 2 medium, 3 dense
+    uint32_t oR[kClassPer + 1], oS[kClassPer + 1];
+#pragma unroll
+    for (int q = 0; q <= kClassPer; ++q) {
+        const int64_t t = t0 + q;
+        oR[q] = t <= a.C ? a.offR[t] : 0u;
+        oS[q] = t <= a.C ? a.offS[t] : 0u;
+    }
 #pragma unroll
     for (int q = 0; q < kClassPer; ++q) {
         const int64_t t = t0 + q;
         cls[q] = 0;
-        sz[q] = 0;
+        ti[q] = make_uint4(oR[q], 0u, oS[q], 0u);
         if (t < a.C) {
-            const uint32_t nr = a.offR[t + 1] - a.offR[t];
-            const uint32_t ns = a.offS[t + 1] - a.offS[t];
+            const uint32_t nr = oR[q + 1] - oR[q];
+            const uint32_t ns = oS[q + 1] - oS[q];
+            ti[q].y = nr;
+            ti[q].w = ns;
             if (nr && ns) {
-                sz[q] = nr + ns;
-                if (nr + ns <= (uint32_t)a.small_cap) {
+                const uint32_t n = nr + ns;
+                if (n <= (uint32_t)a.small_cap) {
                     cls[q] = 1;
                     ++nsmall;
-                    size_small += nr + ns;
-                } else {
+                    size_small += n;
+                } else if (n <= (uint32_t)a.med_cap) {
                     cls[q] = 2;
-                    uint32_t d = atomicAdd(&a.ctr[kDenseCount], 1u);
-                    uint32_t base = atomicAdd(&a.ctr[kDenseEntries], nr + ns);
-                    if (d < (uint32_t)a.cap_dense && (int64_t)base + nr + ns <= a.cap_dent)
-                        a.dense[d] = make_uint4((uint32_t)t, base, nr, ns);
-                    else
-                        atomicOr(&a.st->flags, kStatCapacity);
+                    ++nmed;
+                } else {
+                    cls[q] = 3;
+                    append_dense(a, (uint32_t)t, nr, ns);
                 }
             }
         }
     }
-    // block exclusive scans of nsmall and size_small
-    uint32_t in = nsmall, isz = size_small;
+    // block exclusive scans of nsmall, size_small and nmed
+    uint32_t in = nsmall, isz = size_small, im = nmed;
     for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t tn = __shfl_up(in, d, kWave), ts = __shfl_up(isz, d, kWave);
-        if (lane >= d) { in += tn; isz += ts; }
+        const uint32_t tn = __shfl_up(in, d, kWave), ts = __shfl_up(isz, d, kWave);
+        const uint32_t tm = __shfl_up(im, d, kWave);
+        if (lane >= d) {
+            in += tn;
+            isz += ts;
+            im += tm;
+        }
     }
-    if (lane == kWave - 1) { s_ws[0][w] = in; s_ws[1][w] = isz; }
+    if (lane == kWave - 1) {
+        s_ws[0][w] = in;
+        s_ws[1][w] = isz;
+        s_ws[2][w] = im;
+    }
     __syncthreads();
     if (tid == 0) {
-        uint32_t an = 0, as = 0;
+        uint32_t an = 0, as = 0, am = 0;
         for (int q = 0; q < kClassNT / kWave; ++q) {
-            uint32_t vn = s_ws[0][q], vs = s_ws[1][q];
-            s_ws[0][q] = an; s_ws[1][q] = as;
-            an += vn; as += vs;
+            const uint32_t vn = s_ws[0][q], vs = s_ws[1][q], vm = s_ws[2][q];
+            s_ws[0][q] = an;
+            s_ws[1][q] = as;
+            s_ws[2][q] = am;
+            an += vn;
+            as += vs;
+            am += vm;
         }
-        s_ws[2][0] = an;
+        s_ws[3][0] = an;
+        s_ws[3][1] = am;
     }
     __syncthreads();
-    const uint32_t total_small = s_ws[2][0];
+    const uint32_t total_small = s_ws[3][0], total_med = s_ws[3][1];
     uint32_t rank = s_ws[0][w] + in - nsmall;
     uint32_t spre = s_ws[1][w] + isz - size_small;
     const uint32_t B = (uint32_t)a.unit_cap;
@@ -463,33 +1127,36 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
         if (cls[q] == 1) {
             s_uidx[rank] = spre / B;
             ++rank;
-            spre += sz[q];
+            spre += ti[q].y + ti[q].w;
         }
     }
     __syncthreads();
-    if (total_small == 0) return;
-    const uint32_t nunits = s_uidx[total_small - 1] + 1;
+    const uint32_t nunits = total_small ? s_uidx[total_small - 1] + 1 : 0u;
     if (tid == 0) {
-        s_base[0] = atomicAdd(&a.ctr[kTilesWritten], total_small);
-        s_base[1] = atomicAdd(&a.ctr[kUnitsWritten], nunits);
+        s_base[0] = total_small ? atomicAdd(&a.ctr[kTilesWritten], total_small) : 0u;
+        s_base[1] = nunits ? atomicAdd(&a.ctr[kUnitsWritten], nunits) : 0u;
+        s_base[2] = total_med ? atomicAdd(&a.ctr[kMedCount], total_med) : 0u;
     }
     __syncthreads();
-    const uint32_t tb = s_base[0], ub = s_base[1];
-    if ((int64_t)tb + total_small > a.cap_tiles || (int64_t)ub + nunits > a.cap_units) {
+    const uint32_t tb = s_base[0], ub = s_base[1], mb = s_base[2];
+    if ((int64_t)tb + total_small > a.cap_tiles || (int64_t)ub + nunits > a.cap_units ||
+        (int64_t)mb + total_med > a.cap_med) {
         if (tid == 0) atomicOr(&a.st->flags, kStatCapacity);
         return;
     }
     rank = s_ws[0][w] + in - nsmall;
+    uint32_t mrank = s_ws[2][w] + im - nmed;
 #pragma unroll
     for (int q = 0; q < kClassPer; ++q) {
+        if (cls[q] == 2) a.med[mb + mrank++] = ti[q];
         if (cls[q] == 1) {
-            a.tiles[tb + rank] = (uint32_t)(t0 + q);
+            a.tinfo[tb + rank] = ti[q];
             const uint32_t u = s_uidx[rank];
             if (rank == 0 || s_uidx[rank - 1] != u) {
                 // first tile of unit u: count the tiles of the unit
                 uint32_t lo = rank, hi = total_small;
                 while (hi - lo > 1) {
-                    uint32_t mid = (lo + hi) >> 1;
+                    const uint32_t mid = (lo + hi) >> 1;
                     if (s_uidx[mid] == u) lo = mid;
                     else hi = mid;
                 }
@@ -501,63 +1168,64 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
 }
 
 // ---------------------------------------------------------------------------
-// k_lds_units (tuned): persistent workgroups over the LDS unit queue.
+// k_lds_units: one workgroup per LDS unit.  MEDIUM = false: a batch of small
+// tiles; MEDIUM = true: one medium tile.  The grid is an upper bound on the
+// unit count; surplus workgroups exit at once.
 // ---------------------------------------------------------------------------
-template <int NT, int Q>
+template <int NT, int Q, bool MEDIUM, int MODE>
 __global__ __launch_bounds__(NT) void k_lds_units(Args a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const LdsLayout L = carve(smem, NT, NT * Q);
-    Emitter em{L.wbuf + (threadIdx.x / kWave) * kWaveBuf, 0u, 0ull};
-    __shared__ uint32_t s_u;
-    const uint32_t nunits = a.ctr[kUnitsWritten];
-    while (true) {
-        if (threadIdx.x == 0) s_u = atomicAdd(&a.ctr[kUnitsTaken], 1u);
-        __syncthreads();
-        const uint32_t u = s_u;
-        __syncthreads();
-        if (u >= nunits || u >= (uint32_t)a.cap_units) break;
-        const uint2 ud = a.units[u];
-        const uint32_t* tl = a.tiles + ud.x;
-        run_lds_unit<NT, Q>(a, L, (int)ud.y, [&](int k) { return tl[k]; }, em);
+    constexpr int TC = tc_for(NT * Q, !MEDIUM);
+    const uint32_t nu = MEDIUM ? min(a.ctr[kMedCount], (uint32_t)a.cap_med)
+                               : min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
+    const LdsLayout L = carve(smem, NT, NT * Q, TC);
+    Sink<MODE, true> sk = make_sink<MODE>(L);
+    // persistent workgroups, units assigned round-robin
+    for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+        const int64_t slot = MEDIUM ? a.base_med + u : (int64_t)u;
+        sk.begin(a, slot);
+        if (MEDIUM) {
+            const uint4 ti = a.med[u];
+            run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int) { return ti; }, sk);
+        } else {
+            const uint2 ud = a.units[u];
+            const uint4* tl = a.tinfo + ud.x;
+            run_lds_unit<NT, Q, TC, MODE>(a, L, (int)ud.y, [&](int k) { return tl[k]; }, sk);
+        }
+        sk.end(a, slot);
     }
-    em.finish(a);
+    sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
 }
 
 // ---------------------------------------------------------------------------
-// k_plain_tiles (plain): one workgroup per tile.
+// k_plain_tiles (baseline): one workgroup per tile, slot = tile id.
 // ---------------------------------------------------------------------------
-template <int NT, int Q>
+template <int NT, int Q, int MODE>
 __global__ __launch_bounds__(NT) void k_plain_tiles(Args a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const LdsLayout L = carve(smem, NT, NT * Q);
-    Emitter em{L.wbuf + (threadIdx.x / kWave) * kWaveBuf, 0u, 0ull};
+    constexpr int TC = tc_for(NT * Q, false);
+    const LdsLayout L = carve(smem, NT, NT * Q, TC);
+    Sink<MODE, true> sk = make_sink<MODE>(L);
     // one workgroup per tile; a grid-stride loop only when K*K exceeds the grid
     for (int64_t t = blockIdx.x; t < a.C; t += gridDim.x) {
         const uint32_t nr = a.offR[t + 1] - a.offR[t];
         const uint32_t ns = a.offS[t + 1] - a.offS[t];
         if (nr == 0 || ns == 0) continue;
         if (nr + ns > (uint32_t)(NT * Q)) {
-            if (threadIdx.x == 0) {
-                uint32_t d = atomicAdd(&a.ctr[kDenseCount], 1u);
-                uint32_t base = atomicAdd(&a.ctr[kDenseEntries], nr + ns);
-                if (d < (uint32_t)a.cap_dense && (int64_t)base + nr + ns <= a.cap_dent)
-                    a.dense[d] = make_uint4((uint32_t)t, base, nr, ns);
-                else
-                    atomicOr(&a.st->flags, kStatCapacity);
-            }
+            if (MODE == kCount && threadIdx.x == 0) append_dense(a, (uint32_t)t, nr, ns);
             continue;
         }
-        const uint32_t tt = (uint32_t)t;
-        run_lds_unit<NT, Q>(a, L, 1, [&](int) { return tt; }, em);
+        const uint4 ti = make_uint4(a.offR[t], nr, a.offS[t], ns);
+        sk.begin(a, t);
+        run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int) { return ti; }, sk);
+        sk.end(a, t);
     }
-    em.finish(a);
+    sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
 }
 
 // ---------------------------------------------------------------------------
 // Dense tiles: sort each list into the global dense buffer ...
 // ---------------------------------------------------------------------------
-constexpr int kDenseSortNT = 1024;
-
 __device__ void bitonic_lds(unsigned long long* k, int P) {
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -565,7 +1233,7 @@ __device__ void bitonic_lds(unsigned long long* k, int P) {
                 const int lo = 2 * i - (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool up = ((lo & size) == 0);
-                unsigned long long x = k[lo], y = k[hi];
+                const unsigned long long x = k[lo], y = k[hi];
                 if ((x > y) == up) {
                     k[lo] = y;
                     k[hi] = x;
@@ -578,14 +1246,8 @@ __device__ void bitonic_lds(unsigned long long* k, int P) {
 
 __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
     __shared__ unsigned long long keys[kDenseSortMax];
-    __shared__ uint32_t s_seg;
     const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
-    while (true) {
-        if (threadIdx.x == 0) s_seg = atomicAdd(&a.ctr[kDenseSortTaken], 1u);
-        __syncthreads();
-        const uint32_t seg = s_seg;
-        __syncthreads();
-        if (seg >= 2 * nd) break;
+    for (uint32_t seg = blockIdx.x; seg < 2 * nd; seg += gridDim.x) {
         const uint4 dd = a.dense[seg >> 1];
         const bool sideS = seg & 1;
         const uint32_t src = sideS ? a.offS[dd.x] : a.offR[dd.x];
@@ -598,8 +1260,9 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             int P = 1;
             while (P < (int)L) P <<= 1;
             for (int i = threadIdx.x; i < P; i += blockDim.x)
-                keys[i] = i < (int)L ? ((unsigned long long)order_key(box[src + i].x) << 32) | (uint32_t)i
-                                     : ~0ull;
+                keys[i] = i < (int)L
+                              ? ((unsigned long long)order_key(box[src + i].x) << 32) | (uint32_t)i
+                              : ~0ull;
             __syncthreads();
             bitonic_lds(keys, P);
             fin = keys;
@@ -627,11 +1290,18 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
                     const uint32_t mid = min(lo + wdt, L), hi = min(lo + 2 * wdt, L);
                     const unsigned long long v = A[i];
                     uint32_t olo, ohi, mine;
-                    if (i < mid) { olo = mid; ohi = hi; mine = i - lo; }
-                    else { olo = lo; ohi = mid; mine = i - mid; }
+                    if (i < mid) {
+                        olo = mid;
+                        ohi = hi;
+                        mine = i - lo;
+                    } else {
+                        olo = lo;
+                        ohi = mid;
+                        mine = i - mid;
+                    }
                     uint32_t b0 = olo, b1 = ohi;
                     while (b0 < b1) {
-                        uint32_t m = (b0 + b1) >> 1;
+                        const uint32_t m = (b0 + b1) >> 1;
                         if (A[m] < v) b0 = m + 1;
                         else b1 = m;
                     }
@@ -669,7 +1339,7 @@ __global__ __launch_bounds__(1024) void k_dense_plan(Args a) {
         }
         uint32_t inc = v;
         for (int s = 1; s < kWave; s <<= 1) {
-            uint32_t t = __shfl_up(inc, s, kWave);
+            const uint32_t t = __shfl_up(inc, s, kWave);
             if (lane >= s) inc += t;
         }
         if (lane == kWave - 1) lds[w] = inc;
@@ -677,7 +1347,7 @@ __global__ __launch_bounds__(1024) void k_dense_plan(Args a) {
         if (threadIdx.x == 0) {
             uint32_t acc = 0;
             for (int q = 0; q < nw; ++q) {
-                uint32_t x = lds[q];
+                const uint32_t x = lds[q];
                 lds[q] = acc;
                 acc += x;
             }
@@ -691,57 +1361,53 @@ __global__ __launch_bounds__(1024) void k_dense_plan(Args a) {
     if (threadIdx.x == 0) {
         a.dprefix[nd] = carry;
         a.ctr[kDenseUnits] = carry;
+        if ((int64_t)carry > a.cap_dunits) atomicOr(&a.st->flags, kStatCapacity);
     }
 }
 
-// ... and sweep them, one unit = a contiguous range of pivots of one tile.
+// ... and sweep them: one unit = a contiguous range of pivots of one tile.
 struct GlobAcc {
-    const float4* box;
+    const float4* bxs;
     const uint32_t* idf;
     int base, nr, ns;  // R entries at [base, base+nr), S at [base+nr, base+nr+ns)
-    __device__ float xl(int j) const { return box[j].x; }
-    __device__ float yl(int j) const { return box[j].y; }
-    __device__ float yu(int j) const { return box[j].w; }
+    __device__ float4 box(int j) const { return bxs[j]; }
     __device__ uint32_t id(int j) const { return idf[j]; }
     __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxu, float& pyl, float& pyu,
                           uint32_t& pid) const {
         const int e = base + p;  // pivots: R entries then S entries
-        const float4 b = box[e];
+        const float4 b = bxs[e];
         pxu = b.z;
         pyl = b.y;
         pyu = b.w;
         pid = idf[e];
-        auto X = [&](int q) { return box[q].x; };
-        if (p < nr) {
-            isR = true;
-            j = search_x(X, base + nr, base + nr + ns, b.x, true);
-            jend = base + nr + ns;
-        } else {
-            isR = false;
-            j = search_x(X, base, base + nr, b.x, false);
-            jend = base + nr;
-        }
+        auto X = [&](int q) { return bxs[q].x; };
+        isR = p < nr;
+        const int lo = isR ? base + nr : base;
+        const int hi = isR ? base + nr + ns : base + nr;
+        j = search_x(X, lo, hi, b.x, isR);
+        jend = hi;
         return true;
     }
 };
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_dense_sweep(Args a) {
-    __shared__ unsigned long long wbuf[(NT / kWave) * kWaveBuf];
-    __shared__ uint32_t s_u;
-    Emitter em{wbuf + (threadIdx.x / kWave) * kWaveBuf, 0u, 0ull};
+template <int MODE>
+__global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
+    __shared__ unsigned long long wbuf[(kDenseNT / kWave) * kWaveBuf];
+    __shared__ uint32_t s_acc;
+    __shared__ uint32_t s_next;
+    const uint32_t wg = blockIdx.x * (kDenseNT / kWave) + threadIdx.x / kWave;
+    Sink<MODE, true> sk;
+    sk.buf = wbuf + (threadIdx.x / kWave) * kWaveBuf;
+    sk.s_acc = &s_acc;
+    sk.bufcap = kWaveBuf;
+    sk.init(wg);
     const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
-    const uint32_t nu = a.ctr[kDenseUnits];
-    while (true) {
-        if (threadIdx.x == 0) s_u = atomicAdd(&a.ctr[kDenseUnitsTaken], 1u);
-        __syncthreads();
-        const uint32_t u = s_u;
-        __syncthreads();
-        if (u >= nu) break;
+    const uint32_t nu = min(a.ctr[kDenseUnits], (uint32_t)a.cap_dunits);
+    for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
         // dense tile of unit u: last d with dprefix[d] <= u
         uint32_t lo = 0, hi = nd;
         while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
+            const uint32_t mid = (lo + hi) >> 1;
             if (a.dprefix[mid] <= u) lo = mid;
             else hi = mid;
         }
@@ -752,56 +1418,175 @@ __global__ __launch_bounds__(NT) void k_dense_sweep(Args a) {
             p0 = (int)(u - a.dprefix[lo]) * a.split_tau;
             p1 = min(p0 + a.split_tau, n);
         }
+        const int64_t slot = a.base_dense + u;
+        sk.begin(a, slot);
+        if (threadIdx.x == 0) s_next = 0u;
+        __syncthreads();
         GlobAcc acc{a.dbox, a.didf, (int)dd.y, (int)dd.z, (int)dd.w};
-        sweep_pivots(a, acc, p0 + (int)threadIdx.x, p1, NT, em);
+        sweep_pivots<MODE, true>(a, acc, p0, p1, &s_next, sk);
+        sk.end(a, slot);
     }
-    em.finish(a);
+    sk.finish(a, wg);
 }
 
-__global__ void k_reset(uint32_t* ctr, DevStatus* st) {
+// ---------------------------------------------------------------------------
+// Single-pass output compaction: chunk fill levels were scanned into output
+// offsets (fills[g] = first output slot of chunk g, fills[total] = pairs
+// stored); one wavefront copies one chunk.
+// ---------------------------------------------------------------------------
+constexpr int kCompactNT = 256;
+
+__global__ __launch_bounds__(kCompactNT) void k_compact(Args a) {
+    const int64_t nch = (int64_t)kRegions * a.sc_nch;
+    const int64_t g = (int64_t)blockIdx.x * (kCompactNT / kWave) + threadIdx.x / kWave;
+    if (g >= nch) return;
+    const uint32_t o0 = a.sc_fills[g], o1 = a.sc_fills[g + 1];
+    const unsigned long long* src = a.sc_buf + (size_t)g * kChunkP;
+    for (uint32_t q = lane_id(); q < o1 - o0; q += kWave) {
+        const unsigned long long idx = (unsigned long long)o0 + q;
+        if (idx < (unsigned long long)a.capacity) a.out[idx] = src[q];
+    }
+}
+
+__global__ void k_reset(uint32_t* ctr, DevStatus* st, uint32_t* sc_ctr,
+                        unsigned long long* sc_total) {
     if (threadIdx.x < kNumCtr) ctr[threadIdx.x] = 0u;
+    if (sc_ctr && threadIdx.x < kRegions) sc_ctr[threadIdx.x] = 0u;
+    if (sc_total && threadIdx.x < kTotals) sc_total[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) {
         st->n_pairs = 0ull;
+        st->m_total = 0ull;
         st->flags = 0u;
         st->n_dense = 0u;
         st->n_units = 0u;
     }
 }
 
+// Single pass: the exact pair count is the sum of the per-wave totals; with
+// no scratch overflow it must equal the pairs stored (m_total holds those).
 __global__ void k_finish(const uint32_t* ctr, DevStatus* st, const DevStatus* stR,
-                         const DevStatus* stS) {
+                         const DevStatus* stS, const unsigned long long* sc_total) {
     st->n_dense = ctr[kDenseCount];
-    st->n_units = ctr[kUnitsWritten];
+    st->n_units = ctr[kUnitsWritten] + ctr[kMedCount];
     st->flags |= stR->flags | stS->flags;
+    if (sc_total) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kTotals; ++i) t += sc_total[i];
+        st->n_pairs = t;
+        if (!(st->flags & kStatScratch) && t != st->m_total) st->flags |= kStatInternal;
+    }
 }
 
-template <int NT, int Q>
-hipError_t launch_units(const Args& a, int num_cus, bool plain, hipStream_t s) {
-    const size_t lds = lds_bytes(NT, NT * Q);
-    if (plain) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_plain_tiles<NT, Q>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <class F>
+hipError_t set_lds(F* kern, size_t lds) {
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template <int NT, int Q, int MODE>
+hipError_t launch_plain(const Args& a, hipStream_t s) {
+    const size_t lds = lds_bytes(NT, NT * Q, tc_for(NT * Q, false));
+    hipError_t e = set_lds(k_plain_tiles<NT, Q, MODE>, lds);
+    if (e != hipSuccess) return e;
+    // HIP limits a grid to fewer than 2^32 work-items
+    const int64_t max_blocks = ((int64_t)1 << 31) / NT;
+    const int64_t nb = a.C < max_blocks ? a.C : max_blocks;
+    hipLaunchKernelGGL((k_plain_tiles<NT, Q, MODE>), dim3((unsigned)nb), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int NT, int Q, bool MEDIUM, int MODE>
+hipError_t launch_units(const Args& a, int64_t bound, int num_cus, hipStream_t s) {
+    if (bound <= 0) return hipSuccess;
+    const size_t lds = lds_bytes(NT, NT * Q, tc_for(NT * Q, !MEDIUM));
+    static int per_cu = 0;  // resident workgroups per CU (computed once per instantiation)
+    if (per_cu == 0) {
+        hipError_t e = set_lds(k_lds_units<NT, Q, MEDIUM, MODE>, lds);
         if (e != hipSuccess) return e;
-        // HIP limits a grid to fewer than 2^32 work-items
-        const int64_t max_blocks = ((int64_t)1 << 31) / NT;
-        const int64_t nb = a.C < max_blocks ? a.C : max_blocks;
-        hipLaunchKernelGGL((k_plain_tiles<NT, Q>), dim3((unsigned)nb), dim3(NT), lds, s, a);
-        return hipGetLastError();
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lds_units<NT, Q, MEDIUM, MODE>,
+                                                         NT, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
     }
-    int per_cu = 0;
-    hipError_t e = hipFuncSetAttribute((const void*)k_lds_units<NT, Q>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int64_t grid = std::min<int64_t>(bound, (int64_t)num_cus * per_cu);
+    hipLaunchKernelGGL((k_lds_units<NT, Q, MEDIUM, MODE>), dim3((unsigned)grid), dim3(NT), lds, s,
+                       a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_waves(const Args& a, int64_t bound, int num_cus, hipStream_t s) {
+    if (bound <= 0) return hipSuccess;
+    const size_t lds = sizeof(WaveLds) * (kWNT / kWave);
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        hipError_t e = set_lds(k_wave_units<MODE>, lds);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_units<MODE>, kWNT, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+    }
+    const int64_t waves_per_block = kWNT / kWave;
+    const int64_t grid = std::min<int64_t>((bound + waves_per_block - 1) / waves_per_block,
+                                           (int64_t)num_cus * per_cu);
+    hipLaunchKernelGGL(k_wave_units<MODE>, dim3((unsigned)grid), dim3(kWNT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_small(const Args& a, int block, int64_t bound, int num_cus, hipStream_t s) {
+    switch (block) {
+        case 64: return launch_waves<MODE>(a, bound, num_cus, s);
+        case 128: return launch_units<128, 8, false, MODE>(a, bound, num_cus, s);
+        case 512: return launch_units<512, 4, false, MODE>(a, bound, num_cus, s);
+        default: return launch_units<256, 4, false, MODE>(a, bound, num_cus, s);
+    }
+}
+
+constexpr const char* mode_tag(int mode, const char* count, const char* write, const char* single) {
+    return mode == kCount ? count : (mode == kWrite ? write : single);
+}
+
+// one pass (count, write or single) over every unit
+template <int MODE>
+hipError_t join_pass(const Args& a, const JoinParams& p, const JoinWork& w, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (p.plain) {
+        ProfRange pr(mode_tag(MODE, "k_plain_tiles_count", "k_plain_tiles_write",
+                              "k_plain_tiles_single"), s);
+        e = launch_plain<256, 4, MODE>(a, s);
+    } else {
+        {
+            ProfRange pr(mode_tag(MODE, "k_lds_units_count", "k_lds_units_write",
+                                  "k_lds_units_single"), s);
+            e = launch_small<MODE>(a, p.block, std::min<int64_t>(p.units_bound, w.cap_units),
+                                   w.num_cus, s);
+        }
+        if (e == hipSuccess) {
+            ProfRange pr(mode_tag(MODE, "k_lds_medium_count", "k_lds_medium_write",
+                                  "k_lds_medium_single"), s);
+            e = launch_units<kMedNT, kMedE / kMedNT, true, MODE>(
+                a, std::min<int64_t>(p.med_bound, w.cap_med), w.num_cus, s);
+        }
+    }
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lds_units<NT, Q>, NT, lds);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    hipLaunchKernelGGL((k_lds_units<NT, Q>), dim3((unsigned)(num_cus * per_cu)), dim3(NT), lds, s, a);
+    ProfRange pr(mode_tag(MODE, "k_dense_sweep_count", "k_dense_sweep_write",
+                          "k_dense_sweep_single"), s);
+    hipLaunchKernelGGL(k_dense_sweep<MODE>, dim3(w.num_cus * 4), dim3(kDenseNT), 0, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int lds_unit_entries(int block) { return block == 64 ? 64 * 16 : (block == 128 ? 128 * 8 : (block == 512 ? 512 * 4 : 256 * 4)); }
+int lds_unit_entries(int block) { return block == 64 ? kWE : (block == 128 ? 1024 : block * 4); }
+int lds_medium_entries() { return kMedE; }
+int64_t classify_blocks(int64_t C) { return (C + kClassChunk - 1) / kClassChunk; }
+
+// Slots of the per-unit count array: small units, medium tiles, dense units
+// (tuned) or one per tile plus dense units (plain).
+int64_t join_slots(const JoinParams& p, const JoinWork& w) {
+    return (p.plain ? p.C : w.cap_units + w.cap_med) + w.cap_dunits;
+}
 
 hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork& w, sj_pair* out,
                     int64_t capacity, hipStream_t s) {
@@ -815,56 +1600,101 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     a.C = p.C;
     a.small_cap = p.small_cap;
     a.unit_cap = p.unit_cap;
+    a.med_cap = p.med_cap;
     a.split_tau = p.split_tau;
     a.plain = p.plain ? 1 : 0;
-    a.count_only = p.count_only ? 1 : 0;
-    a.tiles = w.tiles;
+    a.tinfo = w.tinfo;
     a.units = w.units;
+    a.med = w.med;
     a.dense = w.dense;
     a.dprefix = w.dense_unit_prefix;
     a.cap_tiles = w.cap_tiles;
     a.cap_units = w.cap_units;
+    a.cap_med = w.cap_med;
     a.cap_dense = w.cap_dense;
     a.cap_dent = w.cap_dent;
+    a.cap_dunits = w.cap_dunits;
     a.dbox = w.dbox;
     a.didf = w.didf;
     a.dtmp = w.dtmp;
+    a.ucnt = w.ucnt;
+    a.base_med = p.plain ? 0 : w.cap_units;
+    a.base_dense = p.plain ? p.C : w.cap_units + w.cap_med;
     a.ctr = w.ctr;
     a.st = w.st;
     a.stR = R.st;
     a.stS = S.st;
     a.out = (unsigned long long*)out;
     a.capacity = out ? capacity : 0;
+    const bool single = p.single && !p.plain && !p.count_only && w.sc_nch > 0;
+    a.writeback = (!single && !p.count_only) ? 1 : 0;
+    if (single) {
+        a.sc_buf = w.sc_buf;
+        a.sc_fills = w.sc_fills;
+        a.sc_ctr = w.sc_ctr;
+        a.sc_total = w.sc_total;
+        a.sc_nch = w.sc_nch;
+    }
+    const int64_t nslots = join_slots(p, w);
+    const int64_t nchunks = (int64_t)kRegions * w.sc_nch;
 
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w.ctr, w.st);
-    if (!p.plain) {
-        ProfRange pr("k_classify", s);
-        const unsigned nb = (unsigned)((p.C + kClassChunk - 1) / kClassChunk);
-        hipLaunchKernelGGL(k_classify, dim3(nb), dim3(kClassNT), 0, s, a);
-    }
-    hipError_t e;
-    {
-    ProfRange pr(p.plain ? "k_plain_tiles" : "k_lds_units", s);
-    switch (p.block) {
-        case 64: e = launch_units<64, 16>(a, w.num_cus, p.plain, s); break;
-        case 128: e = launch_units<128, 8>(a, w.num_cus, p.plain, s); break;
-        case 512: e = launch_units<512, 4>(a, w.num_cus, p.plain, s); break;
-        default: e = launch_units<256, 4>(a, w.num_cus, p.plain, s); break;
-    }
-    }
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w.ctr, w.st, single ? w.sc_ctr : nullptr,
+                       single ? w.sc_total : nullptr);
+    hipError_t e = single ? launch_fill_u32(w.sc_fills, 0u, nchunks + 1, s)
+                          : launch_fill_u32(w.ucnt, 0u, nslots + 1, s);
     if (e != hipSuccess) return e;
-    const int nsort = w.num_cus * 2;
+    if (p.plain) {
+        // the plain counting pass lists the dense tiles itself
+        ProfRange pr("k_plain_tiles_count", s);
+        e = launch_plain<256, 4, kCount>(a, s);
+        if (e != hipSuccess) return e;
+    } else {
+        ProfRange pr("k_classify", s);
+        hipLaunchKernelGGL(k_classify, dim3((unsigned)classify_blocks(p.C)), dim3(kClassNT), 0, s,
+                           a);
+    }
     {
         ProfRange pr("k_dense_sort", s);
-        hipLaunchKernelGGL(k_dense_sort, dim3(nsort), dim3(kDenseSortNT), 0, s, a);
+        hipLaunchKernelGGL(k_dense_sort, dim3(w.num_cus * 2), dim3(kDenseSortNT), 0, s, a);
     }
     hipLaunchKernelGGL(k_dense_plan, dim3(1), dim3(1024), 0, s, a);
-    {
-        ProfRange pr("k_dense_sweep", s);
-        hipLaunchKernelGGL(k_dense_sweep<256>, dim3(w.num_cus * 4), dim3(256), 0, s, a);
+    if (single) {
+        e = join_pass<kSingle>(a, p, w, s);
+        if (e != hipSuccess) return e;
+        {
+            ProfRange pr("k_scan_chunks", s);
+            e = scan_u32(w.sc_fills, nchunks, w.scan_tmp, &w.st->m_total, w.st, s);
+            if (e != hipSuccess) return e;
+        }
+        ProfRange pr("k_compact", s);
+        const int64_t per = kCompactNT / kWave;
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)((nchunks + per - 1) / per)), dim3(kCompactNT),
+                           0, s, a);
+    } else {
+        if (p.plain) {
+            ProfRange pr("k_dense_sweep_count", s);
+            hipLaunchKernelGGL(k_dense_sweep<kCount>, dim3(w.num_cus * 4), dim3(kDenseNT), 0, s, a);
+        } else {
+            e = join_pass<kCount>(a, p, w, s);
+            if (e != hipSuccess) return e;
+        }
+        {
+            ProfRange pr("k_scan_pairs", s);
+            e = scan_u32(w.ucnt, nslots, w.scan_tmp, &w.st->n_pairs, w.st, s);
+            if (e != hipSuccess) return e;
+        }
+        if (!p.count_only) {
+            e = join_pass<kWrite>(a, p, w, s);
+            if (e != hipSuccess) return e;
+        }
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, w.ctr, w.st, R.st, S.st);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, w.ctr, w.st, R.st, S.st,
+                       single ? w.sc_total : nullptr);
     return hipGetLastError();
 }
+
+int scratch_regions() { return kRegions; }
+int scratch_chunk_pairs() { return kChunkP; }
+int scratch_totals() { return kTotals; }
 
 }  // namespace sj

@@ -1,141 +1,381 @@
 // Partitioning phase of the PBSM join (Sec. 3.4 steps 1-4) on gfx950.
 //
-//   count    one thread per rectangle: validate it, compute its cell range and
-//            add 1 to the count of every tile it covers (step 2; the per-thread
-//            private counts of the paper become device-wide atomics).
-//   scan     exclusive prefix sum of the counts = per-tile segment offsets
-//            (step 3: "sum the counts, allocate one segment per tile").
-//   scatter  second read of the input: each rectangle is written into a slot
-//            of the segment of every tile it covers (step 4).  The slot is
-//            taken by an atomic decrement of the tile's count, which leaves
-//            every count at zero again for the next call.
+// The paper's parallel partitioning has m threads count the tile entries of
+// their part of the input (step 2), sums the counts into one segment per
+// tile, logically divided into one sub-segment per thread (step 3), and lets
+// every thread write its part into its own sub-segments (step 4).  Here the
+// workgroups are the threads, and the counting is done in LDS: a device-wide
+// atomic per tile entry runs at a fraction of HBM speed on this GPU, an LDS
+// histogram at near full speed.  Because an LDS histogram over all K*K tiles
+// does not fit, the counting sort runs in two levels over a blocked tile
+// order:
 //
-// All loads of the input are 16-byte float4 loads by consecutive lanes
-// (coalesced).  The scatter stores a float4 box and a 32-bit id word per
-// entry.
+//   coarse cells   the K x K grid is covered by G x G coarse cells of B x B
+//                  tiles (B = ceil(K / G), G <= 64).  Tiles are numbered
+//                  coarse-cell-major: blocked id = cell * B*B + ly * B + lx.
+//   level 1        workgroup w counts, in LDS, the coarse cells its chunk of
+//                  rectangles covers; a scan over (cell, w) gives every
+//                  workgroup a sub-segment per coarse cell; the second read
+//                  writes (box, id) into it (LDS cursors).
+//   level 2        every coarse cell is cut into chunks of at most kChunk2
+//                  level-1 entries; each chunk counts, in LDS, the tiles of
+//                  its cell its entries cover; a scan over (cell, tile, chunk)
+//                  gives each tile one contiguous segment split into per-chunk
+//                  sub-segments; the second read writes the final entries
+//                  (box, id word with the start bits of the duplicate test).
+//
+// Every kernel checks the status word first and does nothing if an earlier
+// stage reported a bad rectangle or a full buffer; the host then grows the
+// buffers (sizes are reported in the status) and runs the partition again.
 #include "sj_internal.hpp"
+#include "sj_prof.hpp"
 
 namespace sj {
 
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kL1NT = 512;  // level-1 / level-2 workgroup size
 
 __device__ __forceinline__ bool rect_ok(float4 a) {
     return isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w) && a.x <= a.z &&
            a.y <= a.w;
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
+// Block-uniform check of the status word (another workgroup may set a flag
+// while this one runs, so one thread reads it and the block shares the answer).
+__device__ __forceinline__ bool aborted(const DevStatus* st) {
+    __shared__ uint32_t s_abort;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_abort = *(volatile const uint32_t*)&st->flags & (kStatBadRect | kStatCapacity);
+    __syncthreads();
+    return s_abort != 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_count(const float4* __restrict__ rects, int64_t n,
-                                                 GridDev g, uint32_t* __restrict__ cnt,
-                                                 DevStatus* __restrict__ st) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+struct Cells {
+    int cx0, cx1, cy0, cy1;
+};
+
+__device__ __forceinline__ Cells cells_of(float4 a, const GridDev& g) {
+    Cells c;
+    c.cx0 = cell_of(a.x, g.x0, g.sx, g.K);
+    c.cx1 = cell_of(a.z, g.x0, g.sx, g.K);
+    c.cy0 = cell_of(a.y, g.y0, g.sy, g.K);
+    c.cy1 = cell_of(a.w, g.y0, g.sy, g.K);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Level 1
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ rects, int64_t n,
+                                                    GridDev g, Blocking bl, int64_t ch1,
+                                                    uint32_t* __restrict__ h1,
+                                                    DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t hist[];  // [G1]
+    const int G1 = bl.G * bl.G;
+    for (int i = threadIdx.x; i < G1; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * ch1;
+    const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        float4 a = rects[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const float4 a = rects[i];
         if (!rect_ok(a)) {
             bad = true;
             continue;
         }
-        int cx0 = cell_of(a.x, g.x0, g.sx, g.K), cx1 = cell_of(a.z, g.x0, g.sx, g.K);
-        int cy0 = cell_of(a.y, g.y0, g.sy, g.K), cy1 = cell_of(a.w, g.y0, g.sy, g.K);
-        for (int cy = cy0; cy <= cy1; ++cy) {
-            uint32_t* row = cnt + (int64_t)cy * g.K;
-            for (int cx = cx0; cx <= cx1; ++cx) atomicAdd(row + cx, 1u);
-        }
+        const Cells c = cells_of(a, g);
+        const int gx0 = c.cx0 / bl.B, gx1 = c.cx1 / bl.B;
+        const int gy0 = c.cy0 / bl.B, gy1 = c.cy1 / bl.B;
+        for (int gy = gy0; gy <= gy1; ++gy)
+            for (int gx = gx0; gx <= gx1; ++gx) atomicAdd(&hist[gy * bl.G + gx], 1u);
     }
     if (bad) atomicOr(&st->flags, kStatBadRect);
+    __syncthreads();
+    const int64_t nb = gridDim.x;
+    for (int i = threadIdx.x; i < G1; i += blockDim.x) h1[(int64_t)i * nb + blockIdx.x] = hist[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(const float4* __restrict__ rects, int64_t n,
-                                                   GridDev g, uint32_t* __restrict__ cnt,
-                                                   const uint32_t* __restrict__ off,
-                                                   float4* __restrict__ box,
-                                                   uint32_t* __restrict__ idf, int64_t cap_m,
-                                                   DevStatus* __restrict__ st) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__ rects, int64_t n,
+                                                      GridDev g, Blocking bl, int64_t ch1,
+                                                      const uint32_t* __restrict__ o1,
+                                                      float4* __restrict__ e1box,
+                                                      uint32_t* __restrict__ e1id, int64_t cap_m1,
+                                                      DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t cur[];  // [G1]
+    if (aborted(st)) return;
+    const int G1 = bl.G * bl.G;
+    const int64_t nb = gridDim.x;
+    for (int i = threadIdx.x; i < G1; i += blockDim.x) cur[i] = o1[(int64_t)i * nb + blockIdx.x];
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * ch1;
+    const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
     uint32_t err = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         float4 a = rects[i];
         if (!rect_ok(a)) continue;
         a.x += 0.0f;  // -0.0 -> +0.0
         a.y += 0.0f;
         a.z += 0.0f;
         a.w += 0.0f;
-        int cx0 = cell_of(a.x, g.x0, g.sx, g.K), cx1 = cell_of(a.z, g.x0, g.sx, g.K);
-        int cy0 = cell_of(a.y, g.y0, g.sy, g.K), cy1 = cell_of(a.w, g.y0, g.sy, g.K);
-        for (int cy = cy0; cy <= cy1; ++cy) {
-            const int64_t rowt = (int64_t)cy * g.K;
-            const uint32_t by = (cy == cy0) ? kBy : 0u;
-            for (int cx = cx0; cx <= cx1; ++cx) {
-                const int64_t t = rowt + cx;
-                uint32_t old = atomicSub(cnt + t, 1u);
-                if (old == 0u) {  // more scatters than counts: cannot happen
-                    atomicAdd(cnt + t, 1u);
-                    err |= kStatInternal;
-                    continue;
-                }
-                uint64_t pos = (uint64_t)off[t] + old - 1u;
-                if (pos >= (uint64_t)cap_m) {
+        const Cells c = cells_of(a, g);
+        const int gx0 = c.cx0 / bl.B, gx1 = c.cx1 / bl.B;
+        const int gy0 = c.cy0 / bl.B, gy1 = c.cy1 / bl.B;
+        for (int gy = gy0; gy <= gy1; ++gy)
+            for (int gx = gx0; gx <= gx1; ++gx) {
+                const uint32_t slot = atomicAdd(&cur[gy * bl.G + gx], 1u);
+                if ((int64_t)slot >= cap_m1) {
                     err |= kStatCapacity;
                     continue;
                 }
-                box[pos] = a;
-                idf[pos] = (uint32_t)i | by | ((cx == cx0) ? kBx : 0u);
+                e1box[slot] = a;
+                e1id[slot] = (uint32_t)i;
             }
-        }
     }
     if (err) atomicOr(&st->flags, err);
 }
 
-// ---- exclusive scan of per-tile counts (reduce, top-level scan, down-sweep) ----
+// ---------------------------------------------------------------------------
+// Level-2 chunk plan (one workgroup): chunks per coarse cell and their prefix.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_plan(const uint32_t* __restrict__ o1, int64_t nb1,
+                                              Blocking bl, uint32_t* __restrict__ cp,
+                                              uint32_t* __restrict__ chunk_cell,
+                                              int64_t cap_chunks, DevStatus* __restrict__ st) {
+    __shared__ uint32_t lds[1024 / kWave + 1];
+    if (aborted(st)) return;
+    const int G1 = bl.G * bl.G;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    uint32_t carry = 0;
+    for (int g0 = 0; g0 < G1; g0 += blockDim.x) {
+        const int gi = g0 + threadIdx.x;
+        uint32_t v = 0;
+        if (gi < G1) {
+            const uint32_t m = o1[(int64_t)(gi + 1) * nb1] - o1[(int64_t)gi * nb1];
+            v = m == 0u ? 1u : (m + kChunk2 - 1u) / kChunk2;
+        }
+        uint32_t inc = v;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += t;
+        }
+        if (lane == kWave - 1) lds[w] = inc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            for (int q = 0; q < nw; ++q) {
+                const uint32_t x = lds[q];
+                lds[q] = acc;
+                acc += x;
+            }
+            lds[nw] = acc;
+        }
+        __syncthreads();
+        if (gi < G1) {
+            const uint32_t start = carry + lds[w] + inc - v;
+            cp[gi] = start;
+            for (uint32_t q = 0; q < v; ++q)
+                if ((int64_t)(start + q) < cap_chunks) chunk_cell[start + q] = (uint32_t)gi;
+        }
+        carry += lds[nw];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cp[G1] = carry;
+        st->n_chunks = carry;
+        if ((int64_t)carry > cap_chunks) atomicOr(&st->flags, kStatCapacity);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level 2 (persistent over chunks)
+// ---------------------------------------------------------------------------
+struct Chunk {
+    int gx, gy;          // coarse cell
+    uint32_t e0, e1;     // level-1 entries [e0, e1)
+    uint32_t nch, c;     // chunks of the cell, index of this chunk
+    uint32_t h2base;     // B*B * cp[cell]
+};
+
+__device__ __forceinline__ Chunk chunk_info(uint32_t q, const uint32_t* cp, const uint32_t* chunk_cell,
+                                            const uint32_t* o1, int64_t nb1, const Blocking& bl) {
+    Chunk k;
+    const uint32_t cell = chunk_cell[q];
+    k.gx = (int)(cell % (uint32_t)bl.G);
+    k.gy = (int)(cell / (uint32_t)bl.G);
+    k.nch = cp[cell + 1] - cp[cell];
+    k.c = q - cp[cell];
+    const uint32_t b0 = o1[(int64_t)cell * nb1], b1 = o1[(int64_t)(cell + 1) * nb1];
+    k.e0 = b0 + k.c * kChunk2;
+    k.e1 = k.e0 + kChunk2 < b1 ? k.e0 + kChunk2 : b1;
+    k.h2base = (uint32_t)(bl.B * bl.B) * cp[cell];
+    return k;
+}
+
+// local tile range of an entry within its coarse cell
+struct Local {
+    int x0, x1, y0, y1;
+};
+
+__device__ __forceinline__ Local local_range(const Cells& c, const Chunk& k, const Blocking& bl) {
+    const int bx = k.gx * bl.B, by = k.gy * bl.B;
+    Local l;
+    l.x0 = max(c.cx0, bx) - bx;
+    l.x1 = min(c.cx1, bx + bl.B - 1) - bx;
+    l.y0 = max(c.cy0, by) - by;
+    l.y1 = min(c.cy1, by + bl.B - 1) - by;
+    return l;
+}
+
+__global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e1box,
+                                                    const uint32_t* __restrict__ o1, int64_t nb1,
+                                                    const uint32_t* __restrict__ cp,
+                                                    const uint32_t* __restrict__ chunk_cell,
+                                                    GridDev g, Blocking bl,
+                                                    uint32_t* __restrict__ h2,
+                                                    DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t hist[];  // [B*B]
+    if (aborted(st)) return;
+    const int B2 = bl.B * bl.B;
+    const uint32_t nchunks = st->n_chunks;
+    for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+        const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
+        for (int i = threadIdx.x; i < B2; i += blockDim.x) hist[i] = 0u;
+        __syncthreads();
+        for (uint32_t e = k.e0 + threadIdx.x; e < k.e1; e += blockDim.x) {
+            const Local l = local_range(cells_of(e1box[e], g), k, bl);
+            for (int y = l.y0; y <= l.y1; ++y)
+                for (int x = l.x0; x <= l.x1; ++x) atomicAdd(&hist[y * bl.B + x], 1u);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < B2; t += blockDim.x)
+            h2[k.h2base + (uint32_t)t * k.nch + k.c] = hist[t];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__ e1box,
+                                                      const uint32_t* __restrict__ e1id,
+                                                      const uint32_t* __restrict__ o1, int64_t nb1,
+                                                      const uint32_t* __restrict__ cp,
+                                                      const uint32_t* __restrict__ chunk_cell,
+                                                      GridDev g, Blocking bl,
+                                                      const uint32_t* __restrict__ o2,
+                                                      float4* __restrict__ box,
+                                                      uint32_t* __restrict__ idf, int64_t cap_m,
+                                                      DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t cur[];  // [B*B]
+    if (aborted(st)) return;
+    const int B2 = bl.B * bl.B;
+    const uint32_t nchunks = st->n_chunks;
+    uint32_t err = 0;
+    for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+        const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
+        for (int t = threadIdx.x; t < B2; t += blockDim.x)
+            cur[t] = o2[k.h2base + (uint32_t)t * k.nch + k.c];
+        __syncthreads();
+        for (uint32_t e = k.e0 + threadIdx.x; e < k.e1; e += blockDim.x) {
+            const float4 a = e1box[e];
+            const uint32_t id = e1id[e];
+            const Cells c = cells_of(a, g);
+            const Local l = local_range(c, k, bl);
+            const int bx = k.gx * bl.B, by = k.gy * bl.B;
+            for (int y = l.y0; y <= l.y1; ++y) {
+                const uint32_t fy = (by + y == c.cy0) ? kBy : 0u;
+                for (int x = l.x0; x <= l.x1; ++x) {
+                    const uint32_t slot = atomicAdd(&cur[y * bl.B + x], 1u);
+                    if ((int64_t)slot >= cap_m) {
+                        err |= kStatCapacity;
+                        continue;
+                    }
+                    box[slot] = a;
+                    idf[slot] = id | fy | ((bx + x == c.cx0) ? kBx : 0u);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (err) atomicOr(&st->flags, err);
+}
+
+// Segment start of every blocked tile: the start of its first chunk's
+// sub-segment; the last entry is the total.
+__global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t* __restrict__ cp,
+                                                        const uint32_t* __restrict__ o2,
+                                                        Blocking bl, uint32_t* __restrict__ off,
+                                                        DevStatus* __restrict__ st) {
+    if (aborted(st)) return;
+    const int64_t B2 = (int64_t)bl.B * bl.B;
+    const int64_t Cb = (int64_t)bl.G * bl.G * B2;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= Cb;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        if (t == Cb) {
+            off[Cb] = (uint32_t)st->m_total;
+            continue;
+        }
+        const int64_t cell = t / B2, lt = t - cell * B2;
+        const uint32_t nch = cp[cell + 1] - cp[cell];
+        off[t] = o2[(uint32_t)B2 * cp[cell] + (uint32_t)lt * nch];
+    }
+}
+
+// ---- exclusive scan (reduce, top-level scan, down-sweep), in place allowed ----
 constexpr int kScanItems = 16;
-constexpr int kScanChunk = kBlock * kScanItems;  // counts per block
+constexpr int kScanChunk = kBlock * kScanItems;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
     for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, kWave);
+        const uint32_t t = __shfl_up(v, d, kWave);
         if (lane >= d) v += t;
     }
     return v;
 }
 
-// Exclusive scan over the block; returns the block total in `total`.
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t& total) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int nw = blockDim.x / kWave;
-    uint32_t inc = wave_incl_scan(v, lane);
+    const uint32_t inc = wave_incl_scan(v, lane);
     if (lane == kWave - 1) lds[w] = inc;
     __syncthreads();
     if (w == 0) {
-        uint32_t x = lane < nw ? lds[lane] : 0u;
-        uint32_t xi = wave_incl_scan(x, lane);
+        const uint32_t x = lane < nw ? lds[lane] : 0u;
+        const uint32_t xi = wave_incl_scan(x, lane);
         if (lane < nw) lds[lane] = xi - x;
         if (lane == nw - 1) lds[nw] = xi;
     }
     __syncthreads();
-    uint32_t res = inc - v + lds[w];
+    const uint32_t res = inc - v + lds[w];
     total = lds[nw];
     __syncthreads();
     return res;
 }
 
+// Effective length: fixed, or (*dyn) * mult capped at cmax.
+__device__ __forceinline__ int64_t scan_len(int64_t cmax, const uint32_t* dyn, int64_t mult) {
+    if (!dyn) return cmax;
+    const int64_t c = (int64_t)(*dyn) * mult;
+    return c < cmax ? c : cmax;
+}
+
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt,
-                                                       int64_t C, uint32_t* __restrict__ bs) {
+                                                       int64_t cmax, const uint32_t* dyn,
+                                                       int64_t mult, uint32_t* __restrict__ bs,
+                                                       const DevStatus* __restrict__ st) {
     __shared__ uint32_t red[kBlock / kWave];
+    if (aborted(st)) return;
+    const int64_t C = scan_len(cmax, dyn, mult);
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     uint32_t s = 0;
+    if (base < C) {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-        if (i < C) s += cnt[i];
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+            if (i < C) s += cnt[i];
+        }
     }
-    s = wave_sum_u32(s);
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -145,42 +385,49 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
     }
 }
 
-// One block: exclusive scan of the nb block sums in place (64-bit carry to
-// detect totals beyond 2^31 - 1); writes off[C] and the entry total.
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bs, int64_t nb,
-                                                  uint32_t* __restrict__ off, int64_t C,
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bs, int64_t cmax,
+                                                  const uint32_t* dyn, int64_t mult,
+                                                  uint32_t* __restrict__ off,
+                                                  unsigned long long* total_out,
                                                   DevStatus* __restrict__ st) {
     __shared__ uint32_t lds[1024 / kWave + 1];
+    if (aborted(st)) return;
+    const int64_t C = scan_len(cmax, dyn, mult);
+    const int64_t nb = (C + kScanChunk - 1) / kScanChunk;
     unsigned long long carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += blockDim.x) {
-        int64_t i = b0 + threadIdx.x;
-        uint32_t v = i < nb ? bs[i] : 0u;
+        const int64_t i = b0 + threadIdx.x;
+        const uint32_t v = i < nb ? bs[i] : 0u;
         uint32_t tot;
-        uint32_t ex = block_excl_scan(v, lds, tot);
+        const uint32_t ex = block_excl_scan(v, lds, tot);
         if (i < nb) bs[i] = (uint32_t)(carry + ex);
         carry += tot;
     }
     if (threadIdx.x == 0) {
         if (carry >= 0x7FFFFFFFull) {
-            atomicOr(&st->flags, kStatCapacity);
+            atomicOr(&st->flags, kStatCapacity | kStatTooLarge);
             off[C] = 0x7FFFFFFFu;
         } else {
             off[C] = (uint32_t)carry;
         }
-        st->m_total = carry;
+        *total_out = carry;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* __restrict__ cnt, int64_t C,
-                                                     const uint32_t* __restrict__ bs,
-                                                     uint32_t* __restrict__ off) {
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* cnt, int64_t cmax,
+                                                     const uint32_t* dyn, int64_t mult,
+                                                     const uint32_t* __restrict__ bs, uint32_t* off,
+                                                     const DevStatus* __restrict__ st) {
     __shared__ uint32_t lds[kBlock / kWave + 1];
+    if (aborted(st)) return;
+    const int64_t C = scan_len(cmax, dyn, mult);
+    if ((int64_t)blockIdx.x * kScanChunk >= C) return;
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
+        const int64_t i = base + k;
         v[k] = i < C ? cnt[i] : 0u;
         s += v[k];
     }
@@ -188,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* __restrict
     uint32_t ex = block_excl_scan(s, lds, tot) + bs[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
+        const int64_t i = base + k;
         if (i < C) off[i] = ex;
         ex += v[k];
     }
@@ -206,40 +453,113 @@ int grid_for(int64_t n, int block, int max_blocks) {
     return (int)b;
 }
 
+// in-place capable exclusive scan of cmax (or *dyn * mult) counters
+void scan(uint32_t* data, int64_t cmax, const uint32_t* dyn, int64_t mult, uint32_t* bs,
+          unsigned long long* total, DevStatus* st, hipStream_t s) {
+    const int64_t nb = (cmax + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(kBlock), 0, s,
+                       data, cmax, dyn, mult, bs, st);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bs, cmax, dyn, mult, data, total, st);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(kBlock), 0, s,
+                       data, cmax, dyn, mult, bs, data, st);
+}
+
 }  // namespace
 
 int64_t scan_block_sums_needed(int64_t C) { return (C + kScanChunk - 1) / kScanChunk + 1; }
 
-hipError_t launch_count(const float4* rects, int64_t n, GridDev g, uint32_t* cnt, DevStatus* st,
-                        hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count, dim3(grid_for(n, kBlock, 1 << 20)), dim3(kBlock), 0, s, rects, n,
-                       g, cnt, st);
+hipError_t scan_u32(uint32_t* data, int64_t len, uint32_t* bs, unsigned long long* total,
+                    DevStatus* st, hipStream_t s) {
+    scan(data, len, nullptr, 1, bs, total, st, s);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const uint32_t* cnt, int64_t C, uint32_t* off, uint32_t* block_sums,
-                       DevStatus* st, hipStream_t s) {
-    int64_t nb = (C + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, C, block_sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, block_sums, nb, off, C, st);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, C, block_sums,
-                       off);
-    return hipGetLastError();
+Blocking blocking_for(int K) {
+    Blocking b;
+    b.G = K < kCoarsePref ? K : kCoarsePref;
+    b.B = (K + b.G - 1) / b.G;
+    if (b.B > kMaxB) b.B = (K + kCoarseMax - 1) / kCoarseMax;
+    b.G = (K + b.B - 1) / b.B;
+    return b;
 }
 
-hipError_t launch_scatter(const float4* rects, int64_t n, GridDev g, uint32_t* cnt,
-                          const uint32_t* off, float4* box, uint32_t* idf, int64_t cap_m,
-                          DevStatus* st, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kBlock, 1 << 20)), dim3(kBlock), 0, s, rects,
-                       n, g, cnt, off, box, idf, cap_m, st);
-    return hipGetLastError();
+int64_t l1_chunk(int64_t n) {
+    int64_t c = (n + kL1Blocks - 1) / kL1Blocks;
+    if (c < kL1MinChunk) c = kL1MinChunk;
+    return c;
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kBlock, 65536)), dim3(kBlock), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, hipStream_t s) {
+    static bool attrs = false;
+    if (!attrs) {  // level-2 histograms take up to 64 KB of LDS (K = 8192)
+        const int lds = kMaxB * kMaxB * 4;
+        hipError_t e = hipFuncSetAttribute((const void*)k_l2_count,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_l2_scatter,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        attrs = true;
+    }
+    const Blocking bl = P.bl;
+    const int64_t G1 = (int64_t)bl.G * bl.G, B2 = (int64_t)bl.B * bl.B;
+    const int64_t ch1 = l1_chunk(n);
+    const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
+    P.nb1 = nb1;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)P.st, 0u,
+                       (int64_t)(sizeof(DevStatus) / 4));
+    {
+        ProfRange pr("k_l1_count", s);
+        if (n > 0) {
+            hipLaunchKernelGGL(k_l1_count, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
+                               P.gd, bl, ch1, P.h1, P.st);
+        } else {
+            hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(G1, kBlock, 65536)), dim3(kBlock), 0, s,
+                               P.h1, 0u, G1);
+        }
+    }
+    {
+        ProfRange pr("k_scan_l1", s);
+        scan(P.h1, G1 * nb1, nullptr, 1, P.scan_tmp, &P.st->m1_total, P.st, s);
+    }
+    if (n > 0) {
+        ProfRange pr("k_l1_scatter", s);
+        hipLaunchKernelGGL(k_l1_scatter, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
+                           P.gd, bl, ch1, P.h1, P.e1box, P.e1id, P.cap_m1, P.st);
+    }
+    {
+        ProfRange pr("k_plan", s);
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, P.h1, nb1, bl, P.cp, P.chunk_cell,
+                           P.cap_chunks, P.st);
+    }
+    const int nb2 = num_cus * 2;
+    {
+        ProfRange pr("k_l2_count", s);
+        hipLaunchKernelGGL(k_l2_count, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1box, P.h1, nb1,
+                           P.cp, P.chunk_cell, P.gd, bl, P.h2, P.st);
+    }
+    {
+        ProfRange pr("k_scan_l2", s);
+        scan(P.h2, B2 * P.cap_chunks, &P.st->n_chunks, B2, P.scan_tmp, &P.st->m_total, P.st, s);
+    }
+    {
+        ProfRange pr("k_l2_scatter", s);
+        hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1box, P.e1id,
+                           P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.box, P.idf, P.cap_m,
+                           P.st);
+    }
+    {
+        ProfRange pr("k_tile_offsets", s);
+        const int64_t Cb = G1 * B2;
+        hipLaunchKernelGGL(k_tile_offsets, dim3(grid_for(Cb + 1, kBlock, 65536)), dim3(kBlock), 0,
+                           s, P.cp, P.h2, bl, P.off, P.st);
+    }
     return hipGetLastError();
 }
 

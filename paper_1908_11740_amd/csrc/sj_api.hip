@@ -4,10 +4,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "sj_internal.hpp"
 #include "sj_prof.hpp"
@@ -17,6 +19,8 @@ struct sj_part : public sj::Part {};
 namespace sj {
 
 int lds_unit_entries(int block);
+int lds_medium_entries();
+int64_t classify_blocks(int64_t C);
 
 namespace {
 
@@ -128,12 +132,15 @@ JoinParams join_params(const sj_grid& g, bool count_only) {
     p.C = (int64_t)g.k * g.k;
     p.plain = (g.flags & SJ_PLAIN) != 0;
     p.count_only = count_only;
-    p.block = 256;
+    p.block = 64;  // wave units for the small tiles
     const int E = lds_unit_entries(p.block);
-    p.small_cap = p.plain ? E : E / 4;
-    p.unit_cap = E - p.small_cap;
+    const int E_plain = lds_unit_entries(256);  // LDS entries of the plain per-tile kernel
+    p.small_cap = p.plain ? E_plain : E / 2;
+    p.unit_cap = p.plain ? E_plain : E - p.small_cap;
+    p.med_cap = p.plain ? E_plain : lds_medium_entries();
     p.split_tau = g.split_tau > 0 ? g.split_tau : 256;
     if (p.plain || g.split_tau == INT32_MAX) p.split_tau = INT32_MAX;
+    p.single = !p.plain && !count_only && (g.flags & SJ_TWO_PASS) == 0;
     return p;
 }
 
@@ -152,17 +159,27 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
     if (st != SJ_OK) return st;
     JoinWork& w = ds->w;
     JoinParams p = join_params(R->grid, count_only);
-    const int E = lds_unit_entries(p.block);
+    p.C = (int64_t)R->bl.G * R->bl.G * R->bl.B * R->bl.B;
     const int64_t mR = R->m, mS = S->m;
     const int64_t active = std::min<int64_t>(p.C, std::min(mR, mS)) + 1;
-    const int64_t dense_thr = p.plain ? E : p.small_cap;
-    const int64_t ndense = (mR + mS) / (dense_thr + 1) + 2;
+    p.units_bound = std::min<int64_t>(active, (mR + mS) / p.unit_cap + classify_blocks(p.C) + 1);
+    p.med_bound = std::min<int64_t>(active, (mR + mS) / (p.small_cap + 1) + 1);
+    const int64_t ndense = (mR + mS) / (p.med_cap + 1) + 2;
     hipError_t e = hipSuccess;
     if (!p.plain) {
-        if ((e = grow(w.tiles, w.cap_tiles, active)) != hipSuccess) return from_hip(e);
-        if ((e = grow(w.units, w.cap_units, active)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.tinfo, w.cap_tiles, active)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.units, w.cap_units, p.units_bound)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.med, w.cap_med, p.med_bound)) != hipSuccess) return from_hip(e);
     }
     if ((e = grow(w.dense, w.cap_dense, ndense)) != hipSuccess) return from_hip(e);
+    w.cap_dunits = p.plain ? w.cap_dense
+                           : (mR + mS) / std::max(1, p.split_tau) + w.cap_dense + 1;
+    {
+        const int64_t slots = join_slots(p, w);
+        if ((e = grow(w.ucnt, w.cap_ucnt, slots + 1)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.scan_tmp, w.cap_scan, scan_block_sums_needed(slots))) != hipSuccess)
+            return from_hip(e);
+    }
     if ((e = grow(w.dense_unit_prefix, w.cap_prefix, w.cap_dense + 1)) != hipSuccess)
         return from_hip(e);
     {
@@ -182,19 +199,53 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
             w.cap_dent = c1;
         }
     }
-    e = run_join(*R, *S, p, w, count_only ? nullptr : out, count_only ? 0 : capacity, s);
-    if (e != hipSuccess) {
-        set_err("join launch", e);
-        return from_hip(e);
+    if (p.single) {
+        // scratch of the single pass: the caller's capacity (at most 2^27
+        // pairs) spread over the regions with 25% headroom, plus one partly
+        // filled chunk per resident wavefront of the three sweep kernels
+        const int64_t regions = scratch_regions(), cp = scratch_chunk_pairs();
+        const int64_t want = std::min<int64_t>(capacity, (int64_t)1 << 27);
+        const int64_t waves = 3LL * w.num_cus * 32;
+        int64_t nch = (want + want / 4) / (regions * cp) + (waves + regions - 1) / regions + 2;
+        // test hook: a tiny scratch forces the two-pass retry
+        if (const char* dbg = std::getenv("SJ_DEBUG_SCRATCH_CHUNKS")) nch = std::max(1, std::atoi(dbg));
+        if ((e = grow(w.sc_buf, w.cap_sc_pairs, regions * nch * cp)) != hipSuccess ||
+            (e = grow(w.sc_fills, w.cap_sc_fills, regions * nch + 1)) != hipSuccess ||
+            (e = grow(w.scan_tmp, w.cap_scan, scan_block_sums_needed(regions * nch))) != hipSuccess)
+            return from_hip(e);
+        if (!w.sc_ctr) {
+            int64_t c1 = 0, c2 = 0;
+            if ((e = grow(w.sc_ctr, c1, regions)) != hipSuccess ||
+                (e = grow(w.sc_total, c2, scratch_totals())) != hipSuccess)
+                return from_hip(e);
+        }
+        w.sc_nch = nch;
     }
-    // fold the partition-time flags of both inputs into the status word
-    e = read_status(w.st, ds->host, s);
-    if (e != hipSuccess) {
-        set_err("join status readback", e);
-        return from_hip(e);
+    DevStatus hs{};
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        e = run_join(*R, *S, p, w, count_only ? nullptr : out, count_only ? 0 : capacity, s);
+        if (e != hipSuccess) {
+            set_err("join launch", e);
+            return from_hip(e);
+        }
+        // fold the partition-time flags of both inputs into the status word
+        e = read_status(w.st, ds->host, s);
+        if (e != hipSuccess) {
+            set_err("join status readback", e);
+            return from_hip(e);
+        }
+        hs = *ds->host;
+        // the scratch of the single pass ran out although the output fits:
+        // join again in two passes
+        if (p.single && (hs.flags & kStatScratch) && !(hs.flags & ~kStatScratch) &&
+            (int64_t)hs.n_pairs <= capacity) {
+            p.single = false;
+            continue;
+        }
+        break;
     }
-    const DevStatus hs = *ds->host;
     const uint32_t flags = hs.flags;
+    if (flags & kStatTooLarge) return SJ_ERR_TOO_LARGE;
     if (flags & (kStatInternal | kStatCapacity)) {
         snprintf(g_err, sizeof(g_err), "join: internal status flags 0x%x", flags);
         return SJ_ERR_DEVICE;
@@ -223,7 +274,6 @@ sj_status sj_partition(const float* rects, int64_t n, const sj_grid* g, sj_part*
     int dev = 0;
     if (current_device(&dev) != SJ_OK) return SJ_ERR_DEVICE;
     hipStream_t s = (hipStream_t)stream;
-    const int64_t C = (int64_t)grid.k * grid.k;
 
     sj_part* P = *out;
     const bool fresh = (P == nullptr);
@@ -238,78 +288,89 @@ sj_status sj_partition(const float* rects, int64_t n, const sj_grid* g, sj_part*
         if (fresh) sj_part_free(P);
         return e;
     };
-    hipError_t e;
-    if (!P->st) {
-        int64_t cap = 0;
-        if ((e = grow(P->st, cap, 1, true)) != hipSuccess) return fail(from_hip(e));
-    }
-    {
-        int64_t cc = P->cap_c;
-        if (C > cc || !P->cnt) {
-            if ((e = grow(P->cnt, P->cap_c, C, true)) != hipSuccess) return fail(from_hip(e));
-            int64_t co = 0;
-            if (P->off) (void)hipFree(P->off);
-            P->off = nullptr;
-            if ((e = grow(P->off, co, P->cap_c + 1)) != hipSuccess) return fail(from_hip(e));
-        }
-        if ((e = grow(P->scan_tmp, P->cap_scan, scan_block_sums_needed(P->cap_c))) != hipSuccess)
-            return fail(from_hip(e));
-    }
     DeviceState* ds = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         sj_status st = device_state(dev, &ds);
         if (st != SJ_OK) return fail(st);
     }
-    const float4* r4 = (const float4*)rects;
-    if ((e = launch_fill_u32((uint32_t*)P->st, 0u, sizeof(DevStatus) / 4, s)) != hipSuccess)
-        return fail(from_hip(e));
-    {
-        ProfRange pr("k_count", s);
-        if ((e = launch_count(r4, n, gd, P->cnt, P->st, s)) != hipSuccess) return fail(from_hip(e));
+    const Blocking bl = blocking_for(grid.k);
+    const int64_t G1 = (int64_t)bl.G * bl.G, B2 = (int64_t)bl.B * bl.B, Cb = G1 * B2;
+    const int64_t ch1 = l1_chunk(n);
+    const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
+    int64_t need_m1 = std::max<int64_t>(P->cap_m1, n + n / 4 + 4096);
+    int64_t need_m = std::max<int64_t>(P->cap_m, 2 * n + 4096);
+    hipError_t e;
+    if (!P->st) {
+        int64_t cap = 0;
+        if ((e = grow(P->st, cap, 1, true)) != hipSuccess) return fail(from_hip(e));
     }
-    {
-        ProfRange pr("k_scan", s);
-        if ((e = launch_scan(P->cnt, C, P->off, P->scan_tmp, P->st, s)) != hipSuccess)
+    P->bl = bl;
+    P->gd = gd;
+    P->grid = grid;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        const int64_t need_chunks = need_m1 / kChunk2 + G1 + 2;
+        if ((e = grow(P->h1, P->cap_h1, G1 * nb1 + 1)) != hipSuccess ||
+            (e = grow(P->cp, P->cap_cp, G1 + 1)) != hipSuccess ||
+            (e = grow(P->chunk_cell, P->cap_chunks, need_chunks)) != hipSuccess ||
+            (e = grow(P->h2, P->cap_h2, B2 * P->cap_chunks + 1)) != hipSuccess ||
+            (e = grow(P->off, P->cap_off, Cb + 1)) != hipSuccess ||
+            (e = grow(P->scan_tmp, P->cap_scan,
+                      scan_block_sums_needed(std::max(G1 * nb1, B2 * P->cap_chunks)))) !=
+                hipSuccess)
             return fail(from_hip(e));
-    }
-    if ((e = read_status(P->st, ds->host, s)) != hipSuccess) return fail(from_hip(e));
-    const DevStatus hs = *ds->host;
-    if (hs.flags & (kStatBadRect | kStatCapacity)) {
-        // restore the all-zero count invariant before reporting
-        (void)launch_fill_u32(P->cnt, 0u, C, s);
-        (void)launch_fill_u32((uint32_t*)P->st, 0u, sizeof(DevStatus) / 4, s);
-        (void)hipStreamSynchronize(s);
-        return fail((hs.flags & kStatBadRect) ? SJ_ERR_RECT : SJ_ERR_TOO_LARGE);
-    }
-    const int64_t M = (int64_t)hs.m_total;
-    if (M > P->cap_m || !P->box) {
-        if (P->box) (void)hipFree(P->box);
-        if (P->idf) (void)hipFree(P->idf);
-        P->box = nullptr;
-        P->idf = nullptr;
-        P->cap_m = 0;
-        int64_t c1 = 0, c2 = 0;
-        if ((e = grow(P->box, c1, std::max<int64_t>(M, 1))) != hipSuccess ||
-            (e = grow(P->idf, c2, c1)) != hipSuccess) {
-            (void)launch_fill_u32(P->cnt, 0u, C, s);
-            (void)hipStreamSynchronize(s);
+        if (need_m1 > P->cap_m1 || !P->e1box) {
+            if (P->e1box) (void)hipFree(P->e1box);
+            if (P->e1id) (void)hipFree(P->e1id);
+            P->e1box = nullptr;
+            P->e1id = nullptr;
+            P->cap_m1 = 0;
+            int64_t c1 = 0, c2 = 0;
+            if ((e = grow(P->e1box, c1, need_m1)) != hipSuccess ||
+                (e = grow(P->e1id, c2, c1)) != hipSuccess)
+                return fail(from_hip(e));
+            P->cap_m1 = c1;
+        }
+        if (need_m > P->cap_m || !P->box) {
+            if (P->box) (void)hipFree(P->box);
+            if (P->idf) (void)hipFree(P->idf);
+            P->box = nullptr;
+            P->idf = nullptr;
+            P->cap_m = 0;
+            int64_t c1 = 0, c2 = 0;
+            if ((e = grow(P->box, c1, need_m)) != hipSuccess ||
+                (e = grow(P->idf, c2, c1)) != hipSuccess)
+                return fail(from_hip(e));
+            P->cap_m = c1;
+        }
+        if ((e = run_partition(*P, (const float4*)rects, n, ds->w.num_cus, s)) != hipSuccess) {
+            set_err("partition launch", e);
             return fail(from_hip(e));
         }
-        P->cap_m = c1;
-    }
-    {
-        ProfRange pr("k_scatter", s);
-        if ((e = launch_scatter(r4, n, gd, P->cnt, P->off, P->box, P->idf, P->cap_m, P->st, s)) !=
-            hipSuccess)
+        if ((e = read_status(P->st, ds->host, s)) != hipSuccess) {
+            set_err("partition status readback", e);
             return fail(from_hip(e));
+        }
+        const DevStatus hs = *ds->host;
+        if (hs.flags & kStatBadRect) return fail(SJ_ERR_RECT);
+        if (hs.flags & kStatTooLarge) return fail(SJ_ERR_TOO_LARGE);
+        if (hs.flags & kStatInternal) {
+            snprintf(g_err, sizeof(g_err), "partition: internal status flags 0x%x", hs.flags);
+            return fail(SJ_ERR_DEVICE);
+        }
+        if (hs.flags & kStatCapacity) {
+            need_m1 = std::max<int64_t>(need_m1, (int64_t)hs.m1_total + 1);
+            if (hs.m_total) need_m = std::max<int64_t>(need_m, (int64_t)hs.m_total + 1);
+            continue;
+        }
+        P->n = n;
+        P->m = (int64_t)hs.m_total;
+        P->m1 = (int64_t)hs.m1_total;
+        *out = P;
+        return SJ_OK;
     }
-    P->grid = grid;
-    P->gd = gd;
-    P->n = n;
-    P->m = M;
-    *out = P;
-    return SJ_OK;
+    snprintf(g_err, sizeof(g_err), "partition: buffers still too small after regrowth");
+    return fail(SJ_ERR_DEVICE);
 }
 
 sj_status sj_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
@@ -333,33 +394,37 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
     if (!P) return SJ_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (hipStreamSynchronize(s) != hipSuccess) return SJ_ERR_DEVICE;
-    const int64_t C = (int64_t)P->grid.k * P->grid.k;
-    if (offsets) {
-        uint32_t* tmp = (uint32_t*)malloc((size_t)(C + 1) * 4);
-        if (!tmp) return SJ_ERR_OOM;
-        if (hipMemcpy(tmp, P->off, (size_t)(C + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess) {
-            free(tmp);
-            return SJ_ERR_DEVICE;
+    const int K = P->grid.k;
+    const int64_t B2 = (int64_t)P->bl.B * P->bl.B;
+    const int64_t Cb = (int64_t)P->bl.G * P->bl.G * B2;
+    std::vector<uint32_t> off((size_t)Cb + 1);
+    std::vector<uint32_t> raw((size_t)std::max<int64_t>(P->m, 1));
+    if (hipMemcpy(off.data(), P->off, (size_t)(Cb + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return SJ_ERR_DEVICE;
+    if (P->m > 0 &&
+        hipMemcpy(raw.data(), P->idf, (size_t)P->m * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return SJ_ERR_DEVICE;
+    // regroup from the blocked tile order into row-major tile order
+    int64_t at = 0;
+    for (int ty = 0; ty < K; ++ty)
+        for (int tx = 0; tx < K; ++tx) {
+            const int gx = tx / P->bl.B, gy = ty / P->bl.B;
+            const int64_t bt = ((int64_t)gy * P->bl.G + gx) * B2 +
+                               (int64_t)(ty - gy * P->bl.B) * P->bl.B + (tx - gx * P->bl.B);
+            if (offsets) offsets[(int64_t)ty * K + tx] = at;
+            for (uint32_t q = off[bt]; q < off[bt + 1]; ++q, ++at)
+                if (ids) ids[at] = (int32_t)(raw[q] & kIdMask);
         }
-        for (int64_t i = 0; i <= C; ++i) offsets[i] = tmp[i];
-        free(tmp);
-    }
-    if (ids && P->m > 0) {
-        if (hipMemcpy(ids, P->idf, (size_t)P->m * 4, hipMemcpyDeviceToHost) != hipSuccess)
-            return SJ_ERR_DEVICE;
-        for (int64_t i = 0; i < P->m; ++i) ids[i] = (int32_t)((uint32_t)ids[i] & kIdMask);
-    }
+    if (offsets) offsets[(int64_t)K * K] = at;
     return SJ_OK;
 }
 
 void sj_part_free(sj_part* P) {
     if (!P) return;
-    if (P->cnt) (void)hipFree(P->cnt);
-    if (P->off) (void)hipFree(P->off);
-    if (P->box) (void)hipFree(P->box);
-    if (P->idf) (void)hipFree(P->idf);
-    if (P->scan_tmp) (void)hipFree(P->scan_tmp);
-    if (P->st) (void)hipFree(P->st);
+    void* bufs[] = {P->h1, P->e1box, P->e1id, P->cp, P->chunk_cell, P->h2,
+                    P->box, P->idf, P->off, P->scan_tmp, P->st};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
     delete P;
 }
 

@@ -48,49 +48,76 @@ constexpr uint32_t kBy = 0x80000000u;
 
 // Device-side status word bits.
 constexpr uint32_t kStatBadRect = 1u;
-constexpr uint32_t kStatCapacity = 2u;  // an internal buffer was too small
-constexpr uint32_t kStatInternal = 4u;  // broken invariant (count/scatter mismatch)
+constexpr uint32_t kStatCapacity = 2u;  // an internal buffer was too small (sizes reported)
+constexpr uint32_t kStatInternal = 4u;  // broken invariant
+constexpr uint32_t kStatTooLarge = 8u;  // more than 2^31 - 1 entries
+constexpr uint32_t kStatScratch = 16u;  // single-pass pair scratch ran out (two-pass retry)
 
 // Counters written by the device and read back once per call.
 struct DevStatus {
-    unsigned long long n_pairs;  // pairs found (may exceed the output capacity)
-    unsigned long long m_total;  // entries of the partitioned side(s)
-    uint32_t flags;              // kStat* bits
-    uint32_t n_dense;            // dense tiles found by the join classification
-    uint32_t n_units;            // LDS units built by the classification
-    uint32_t pad;
+    unsigned long long n_pairs;   // pairs found (may exceed the output capacity)
+    unsigned long long m_total;   // tile entries of the partitioned input
+    unsigned long long m1_total;  // coarse-cell entries (level 1)
+    uint32_t flags;               // kStat* bits
+    uint32_t n_dense;             // dense tiles found by the join classification
+    uint32_t n_units;             // LDS units built by the classification
+    uint32_t n_chunks;            // level-2 chunks of the partition
 };
+
+// Two-level blocking of the K x K grid: G x G coarse cells of B x B tiles.
+constexpr int kCoarseMax = 64;    // G <= 64: level-1 LDS histogram <= 16 KB
+constexpr int kCoarsePref = 32;   // preferred G (longer level-1 write runs)
+constexpr int kMaxB = (SJ_K_MAX + kCoarseMax - 1) / kCoarseMax;  // B <= 128: level-2 LDS <= 64 KB
+constexpr uint32_t kChunk2 = 8192;  // level-1 entries per level-2 chunk
+constexpr int64_t kL1Blocks = 256;  // level-1 workgroups per input (upper bound)
+constexpr int64_t kL1MinChunk = 4096;
+
+struct Blocking {
+    int G;  // coarse cells per dimension
+    int B;  // tiles per coarse cell and dimension
+};
+
+Blocking blocking_for(int K);
+int64_t l1_chunk(int64_t n);
 
 // ---------------------------------------------------------------------------
 // Partitioned input (device buffers) -- the opaque sj_part.
+// Tile segments are stored in blocked tile order (see partition.hip).
 // ---------------------------------------------------------------------------
 struct Part {
     int device = 0;
     sj_grid grid{};
     GridDev gd{};
-    int64_t n = 0;         // rectangles
-    int64_t m = 0;         // entries
-    int64_t cap_c = 0;     // capacity of cnt / off (tiles)
-    int64_t cap_m = 0;     // capacity of box / idf (entries)
-    uint32_t* cnt = nullptr;   // [cap_c]    per-tile counts, all zero between calls
-    uint32_t* off = nullptr;   // [cap_c+1]  exclusive prefix of counts
-    float4* box = nullptr;     // [cap_m]    (x_l, y_l, x_u, y_u) per entry
-    uint32_t* idf = nullptr;   // [cap_m]    id word per entry
-    uint32_t* scan_tmp = nullptr;  // block sums of the scan
+    Blocking bl{1, 1};
+    int64_t n = 0;          // rectangles
+    int64_t m = 0;          // tile entries
+    int64_t m1 = 0;         // coarse-cell entries
+    int64_t nb1 = 0;        // level-1 workgroups of the last call
+    uint32_t* h1 = nullptr;   // [cap_h1]  level-1 histograms -> offsets (scanned in place)
+    int64_t cap_h1 = 0;
+    float4* e1box = nullptr;  // [cap_m1]  level-1 entries
+    uint32_t* e1id = nullptr;
+    int64_t cap_m1 = 0;
+    uint32_t* cp = nullptr;   // [G*G + 1] chunk prefix per coarse cell
+    int64_t cap_cp = 0;
+    uint32_t* chunk_cell = nullptr;  // [cap_chunks] coarse cell of each chunk
+    int64_t cap_chunks = 0;
+    uint32_t* h2 = nullptr;   // [B*B*cap_chunks + 1] level-2 histograms -> offsets
+    int64_t cap_h2 = 0;
+    float4* box = nullptr;    // [cap_m]   (x_l, y_l, x_u, y_u) per tile entry
+    uint32_t* idf = nullptr;  // [cap_m]   id word per tile entry
+    int64_t cap_m = 0;
+    uint32_t* off = nullptr;  // [G*G*B*B + 1] segment start per blocked tile
+    int64_t cap_off = 0;
+    uint32_t* scan_tmp = nullptr;
     int64_t cap_scan = 0;
-    DevStatus* st = nullptr;   // device status
+    DevStatus* st = nullptr;
 };
 
-// Launch helpers implemented in partition.hip
-hipError_t launch_count(const float4* rects, int64_t n, GridDev g, uint32_t* cnt, DevStatus* st,
-                        hipStream_t s);
-hipError_t launch_scan(const uint32_t* cnt, int64_t C, uint32_t* off, uint32_t* block_sums,
-                       DevStatus* st, hipStream_t s);
+// Implemented in partition.hip
 int64_t scan_block_sums_needed(int64_t C);
-hipError_t launch_scatter(const float4* rects, int64_t n, GridDev g, uint32_t* cnt,
-                          const uint32_t* off, float4* box, uint32_t* idf, int64_t cap_m,
-                          DevStatus* st, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Join workspace and launch helpers implemented in join.hip
@@ -100,20 +127,30 @@ struct JoinParams {
     int64_t C;
     int split_tau;   // pivots per dense unit
     int unit_cap;    // LDS unit entry budget
-    int small_cap;   // tiles with more entries than this are dense
-    int block;       // threads per workgroup for the sweep kernels
+    int small_cap;   // tiles with at most this many entries are batched
+    int med_cap;     // tiles above small_cap and up to med_cap: one per workgroup
+    int block;       // threads per workgroup for the small-unit kernel
+    int64_t units_bound;  // upper bound on small units
+    int64_t med_bound;    // upper bound on medium tiles
     bool plain;      // one workgroup per tile, no batching, no splitting
     bool count_only;
+    bool single;     // one sweep into scratch chunks + compaction (else count, scan, write)
 };
 
 struct JoinWork {
     int device = 0;
     // classification outputs
-    uint32_t* tiles = nullptr;      // [cap_tiles] tile ids of LDS units (grouped)
-    uint2* units = nullptr;         // [cap_units] (first index into tiles, count)
+    uint4* tinfo = nullptr;         // [cap_tiles] small-tile segments, grouped by unit
+    uint2* units = nullptr;         // [cap_units] (first index into tinfo, count)
+    uint4* med = nullptr;           // [cap_med] medium-tile segments
+    int64_t cap_med = 0;
     uint4* dense = nullptr;         // [cap_dense] (tile, base in dense buffer, nr, ns)
     uint32_t* dense_unit_prefix = nullptr;  // [cap_dense+1]
-    int64_t cap_tiles = 0, cap_units = 0, cap_dense = 0, cap_prefix = 0;
+    int64_t cap_tiles = 0, cap_units = 0, cap_dense = 0, cap_prefix = 0, cap_dunits = 0;
+    uint32_t* ucnt = nullptr;       // per-unit pair counts -> output offsets
+    int64_t cap_ucnt = 0;
+    uint32_t* scan_tmp = nullptr;   // block sums of the pair-count scan
+    int64_t cap_scan = 0;
     // globally sorted dense segments
     float4* dbox = nullptr;         // [cap_dent]
     uint32_t* didf = nullptr;       // [cap_dent]
@@ -121,6 +158,14 @@ struct JoinWork {
     int64_t cap_dent = 0;
     // queue counters: [0] LDS units taken, [1] dense sort taken, [2] dense units taken,
     // [3] tiles written, [4] units written, [5] dense entries allocated, [6] dense units
+    // single-pass pair scratch: scratch_regions() regions of sc_nch chunks
+    unsigned long long* sc_buf = nullptr;  // [regions * sc_nch * scratch_chunk_pairs()]
+    int64_t cap_sc_pairs = 0;
+    uint32_t* sc_fills = nullptr;   // [regions * sc_nch + 1] chunk fill levels -> offsets
+    int64_t cap_sc_fills = 0;
+    uint32_t* sc_ctr = nullptr;     // [regions] chunks reserved per region
+    unsigned long long* sc_total = nullptr;  // [scratch_totals()] pair totals
+    int64_t sc_nch = 0;
     uint32_t* ctr = nullptr;
     DevStatus* st = nullptr;
     void* host_status = nullptr;    // pinned DevStatus mirror
@@ -129,5 +174,9 @@ struct JoinWork {
 
 hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork& w,
                     sj_pair* out, int64_t capacity, hipStream_t s);
+int64_t join_slots(const JoinParams& p, const JoinWork& w);
+int scratch_regions();
+int scratch_chunk_pairs();
+int scratch_totals();
 
 }  // namespace sj

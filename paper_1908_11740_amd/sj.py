@@ -22,9 +22,10 @@ SJ_ERR_OOM = -5
 SJ_ERR_DEVICE = -6
 SJ_ERR_TOO_LARGE = -7
 
-SJ_K_MAX = 16384
+SJ_K_MAX = 8192
 SJ_PLAIN = 0x1
 SJ_RULE_ONLY = 0x2
+SJ_TWO_PASS = 0x4
 INT32_MAX = 2**31 - 1
 
 

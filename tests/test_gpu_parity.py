@@ -20,7 +20,8 @@ from paper_1908_11740_amd import sj  # noqa: E402
 from gpu_util import gpu_join, to_dev  # noqa: E402
 
 SCHEDULES = {"tuned": dict(), "plain": dict(flags=sj.SJ_PLAIN),
-             "tau1": dict(split_tau=1), "nosplit": dict(split_tau=sj.INT32_MAX)}
+             "tau1": dict(split_tau=1), "nosplit": dict(split_tau=sj.INT32_MAX),
+             "twopass": dict(flags=sj.SJ_TWO_PASS)}
 
 
 def say(*a):
@@ -43,7 +44,7 @@ def test_small_case_k64(small, sched):
 
 
 @pytest.mark.parametrize("K", [1, 2, 3, 7, 33, 200, 1000, 4096])
-@pytest.mark.parametrize("sched", ["tuned", "plain"])
+@pytest.mark.parametrize("sched", ["tuned", "plain", "twopass"])
 def test_small_case_every_grid(small, K, sched):
     R, S, _, ref = small
     say("small case K", K, sched)
@@ -140,7 +141,7 @@ def test_skewed_10m_tuned_and_plain(skewed10m):
     R, S = skewed10m
     K = 1213
     ref = oracle.pbsm(R, S, K)
-    for sched in ("tuned", "plain"):
+    for sched in ("tuned", "plain", "twopass"):
         say("skewed 10M", sched)
         got = gpu_join(R, S, K, **SCHEDULES[sched])
         assert len(got) == len(ref)
@@ -188,6 +189,22 @@ def test_capacity_reports_required_count():
     out = torch.empty((len(ref), 2), dtype=torch.int32, device="cuda")
     st, n = sj.join_into(PR, PS, out)
     assert st == sj.SJ_OK and n == len(ref)
+
+
+def test_scratch_overflow_falls_back_to_two_passes(uniform1m, monkeypatch):
+    """One scratch chunk per region cannot hold the pairs of the uniform 1M
+    join: the single pass must detect it and the call join again in two
+    passes, with the same pair set."""
+    R, S, ref = uniform1m
+    K = 1024
+    say("scratch overflow fallback, uniform 1M K", K)
+    monkeypatch.setenv("SJ_DEBUG_SCRATCH_CHUNKS", "1")
+    got = gpu_join(R, S, K)
+    assert np.array_equal(got, ref)
+    PR, PS = sj.partition(to_dev(R), K), sj.partition(to_dev(S), K)
+    out = torch.empty((10, 2), dtype=torch.int32, device="cuda")
+    st, n = sj.join_into(PR, PS, out)
+    assert st == sj.SJ_ERR_CAPACITY and n == len(ref)
 
 
 def test_handle_reuse_across_grids():
