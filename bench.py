@@ -1,15 +1,22 @@
 """Benchmark of the MBR-filter spatial join on one MI355X.
 
 A step is one pass of the whole hot path over one batch of synthetic input
-already resident in HBM: partition R, partition S (validate, count, scan,
-scatter) and join (classify tiles, per-tile sort + forward-scan sweep with
-the reference-point test, pair output).  Prints one JSON line.
+already resident in HBM: choose the grid (features + statistics rule or
+learned picker), partition R, partition S (validate, two-level count /
+scan / scatter) and join (classify tiles, per-tile sort + forward-scan sweep
+with the reference-point test, pair output and compaction).  Prints one JSON
+line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload skewed10m]
+
+The tuned run uses the learned picker when its weights are present (else the
+rule) with the batched / split schedule; --compare (default) also times the
+baseline: statistics-rule K with the plain one-workgroup-per-tile schedule.
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -31,9 +38,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="skewed10m", choices=sorted(WORKLOADS))
-    ap.add_argument("--k", type=int, default=0, help="grid size (0: statistics rule)")
-    ap.add_argument("--plain", action="store_true", help="one-workgroup-per-tile schedule")
+    ap.add_argument("--k", type=int, default=0, help="fixed grid size (0: choose every step)")
     ap.add_argument("--split-tau", type=int, default=0)
+    ap.add_argument("--picker", default="auto", choices=["auto", "rule", "learned"])
+    ap.add_argument("--plain", action="store_true", help="time only the plain rule baseline")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--two-pass", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--count", action="store_true", help="count-only join mode")
@@ -51,31 +61,28 @@ def inputs(name):
     return datagen.uniform_1m()
 
 
-def rule_k(R, S):
-    """Grid size of the statistics rule (tile extent ~ 10x the mean rectangle
-    extent), evaluated on the host for this benchmark's fixed inputs."""
-    import numpy as np
-    e = np.concatenate([(R[:, 2] - R[:, 0]).astype(np.float64) + (R[:, 3] - R[:, 1]),
-                        (S[:, 2] - S[:, 0]).astype(np.float64) + (S[:, 3] - S[:, 1])]).mean() / 2
-    return int(min(16384, max(1, round(1.0 / (10.0 * e)))))
-
-
-def kernel_bytes(name, nR, nS, mR, mS, C, P):
-    """Algorithmic HBM bytes of one launch of a kernel (per side for the
-    partition kernels: the mean over the two sides)."""
-    n = (nR + nS) / 2
-    m = (mR + mS) / 2
-    if name == "k_count":
-        return 16 * n + 4 * C
-    if name == "k_scan":
-        return 8 * C
-    if name == "k_scatter":
-        return 16 * n + 20 * m + 4 * C
-    if name in ("k_lds_units", "k_plain_tiles"):
-        return 20 * (mR + mS) + 8 * P + 8 * C
-    if name == "k_classify":
-        return 8 * C
-    return None
+def kernel_bytes(name, w):
+    """Algorithmic HBM bytes of one launch (partition kernels: mean of the two
+    sides).  Entries are 20 B (box + id word), pairs 8 B."""
+    n = (w["nR"] + w["nS"]) / 2
+    m1 = (w["m1R"] + w["m1S"]) / 2
+    m = (w["mR"] + w["mS"]) / 2
+    st = w["stats"]
+    table = {
+        "k_features": 16 * (w["nR"] + w["nS"]),
+        "k_l1_count": 16 * n,
+        "k_l1_scatter": 16 * n + 20 * m1,
+        "k_l2_count": 16 * m1,
+        "k_l2_scatter": 20 * m1 + 20 * m,
+        "k_classify": 8 * w["C"] + 16 * (st["small_tiles"] + st["medium_tiles"]),
+        "k_dense_sort": 40 * st["dense_entries"],
+        "k_compact": 16 * w["P"],
+    }
+    if st["single_pass"]:
+        table["k_lds_units_single"] = 20 * st["small_entries"] + 8 * st["pairs_small"]
+        table["k_lds_medium_single"] = 20 * st["medium_entries"] + 8 * st["pairs_medium"]
+        table["k_dense_sweep_single"] = 20 * st["dense_entries"] + 8 * st["pairs_dense"]
+    return table.get(name)
 
 
 def main():
@@ -87,82 +94,116 @@ def main():
     import numpy as np
     import torch
 
+    from paper_1908_11740_amd import picker as pk
     from paper_1908_11740_amd import sj
 
     torch.cuda.set_device(0)
     log("generating", args.workload)
     R, S = inputs(args.workload)
-    K = args.k if args.k > 0 else rule_k(R, S)
-    flags = sj.SJ_PLAIN if args.plain else 0
     Rd = torch.from_numpy(R).cuda()
     Sd = torch.from_numpy(S).cuda()
     nR, nS = len(R), len(S)
-    state = {"PR": None, "PS": None, "out": torch.empty((1 << 20, 2), dtype=torch.int32,
-                                                       device="cuda")}
+    use_learned = args.picker == "learned" or (args.picker == "auto" and pk.weights_available())
+    if use_learned:
+        pk.load()
+    state = {"PR": None, "PS": None, "pairs": 0, "K": 0, "tau": 0, "info": None,
+             "out": torch.empty((1 << 20, 2), dtype=torch.int32, device="cuda")}
 
-    def step():
-        state["PR"] = sj.partition(Rd, K, split_tau=args.split_tau, flags=flags, reuse=state["PR"])
-        state["PS"] = sj.partition(Sd, K, split_tau=args.split_tau, flags=flags, reuse=state["PS"])
+    def step(plain):
+        if args.k:
+            K, tau = args.k, args.split_tau
+        else:
+            fl = sj.SJ_RULE_ONLY if (plain or not use_learned) else 0
+            K, tau, state["info"] = sj.choose_grid(Rd, Sd, split_tau=args.split_tau, flags=fl)
+        flags = sj.SJ_PLAIN if plain else (sj.SJ_TWO_PASS if args.two_pass else 0)
+        state["PR"] = sj.partition(Rd, K, split_tau=tau, flags=flags, reuse=state["PR"])
+        state["PS"] = sj.partition(Sd, K, split_tau=tau, flags=flags, reuse=state["PS"])
+        state["K"], state["tau"] = K, tau
         if args.count:
-            return sj.join_count(state["PR"], state["PS"])
+            state["pairs"] = sj.join_count(state["PR"], state["PS"])
+            return
         st, n = sj.join_into(state["PR"], state["PS"], state["out"])
         if st == sj.SJ_ERR_CAPACITY:
             state["out"] = torch.empty((int(n * 1.1) + 1024, 2), dtype=torch.int32, device="cuda")
             st, n = sj.join_into(state["PR"], state["PS"], state["out"])
-        return n
+        state["pairs"] = n
 
-    log("warmup", args.warmup, "K", K)
-    n_pairs = 0
-    for _ in range(max(1, args.warmup)):
-        n_pairs = step()
-    torch.cuda.synchronize()
-    sj.prof_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        n_pairs = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern = sj.prof_collect()
-    sj.prof_enable(False)
-    ms = (t1 - t0) * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step, {n_pairs} pairs")
-    _, mR, _ = state["PR"].info()
-    _, mS, _ = state["PS"].info()
+    def timed(plain):
+        for _ in range(max(1, args.warmup)):
+            step(plain)
+        torch.cuda.synchronize()
+        # unprofiled: the reported time
+        times = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            step(plain)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        ms = sum(times) * 1e3 / len(times)
+        # the same steps again with per-kernel HIP events on the launch stream
+        sj.prof_enable(True)
+        for _ in range(args.steps):
+            step(plain)
+        torch.cuda.synchronize()
+        kern = sj.prof_collect()
+        sj.prof_enable(False)
+        return ms, statistics.median(times) * 1e3, kern
+
+    res = {}
+    modes = ["plain"] if args.plain else (["tuned"] + ([] if args.no_compare else ["plain"]))
+    for mode in modes:
+        log("timing", mode)
+        ms, med, kern = timed(mode == "plain")
+        _, mR, _ = state["PR"].info()
+        _, mS, _ = state["PS"].info()
+        m1R, _ = state["PR"].stats()
+        m1S, _ = state["PS"].stats()
+        res[mode] = dict(ms=ms, median=med, kern=kern, K=state["K"], tau=state["tau"],
+                         P=state["pairs"], mR=mR, mS=mS, m1R=m1R, m1S=m1S,
+                         stats=sj.last_join_stats(), info=state["info"])
+        log(f"{mode}: {ms:.3f} ms/step (median {med:.3f}), K={state['K']} tau={state['tau']}, "
+            f"{state['pairs']} pairs")
+    main_mode = modes[0]
+    r = res[main_mode]
+    K, P = r["K"], r["P"]
     C = K * K
-
+    w = dict(nR=nR, nS=nS, m1R=r["m1R"], m1S=r["m1S"], mR=r["mR"], mS=r["mS"], C=C, P=P,
+             stats=r["stats"])
     kernels = {}
-    for name, (tot, calls) in kern.items():
+    for name, (tot, calls) in r["kern"].items():
         avg = tot / max(calls, 1)
-        b = kernel_bytes(name, nR, nS, mR, mS, C, n_pairs)
+        b = kernel_bytes(name, w)
         kernels[name] = {"avg_ms": round(avg, 5), "calls": calls,
                          "alg_bytes": None if b is None else int(b),
                          "gbs": None if b is None else round(b / (avg * 1e-3) / 1e9, 1)}
+    steps = args.steps
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["calls"])
     dk = kernels[dom]
     roofline = {"kernel": dom, "bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s",
                 "frac": None if dk["gbs"] is None else round(dk["gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": None}
-    b_step = 32 * (nR + nS) + 40 * (mR + mS) + 8 * n_pairs + 32 * C
+                "traffic": None, "avg_ms": dk["avg_ms"], "alg_bytes_per_launch": dk["alg_bytes"]}
+    b_step = 32 * (nR + nS) + 40 * (r["mR"] + r["mS"]) + 8 * P + 32 * C
+    ms = r["ms"]
     verified = None
     cpu = None
     if not args.no_verify or not args.no_cpu_baseline:
         import oracle
-        log("oracle pbsm on host cores")
+        log("oracle pbsm on host cores, K", K)
         pairs, tp, tj = oracle.pbsm(R, S, K, threads=0, timings=True, sort=False)
-        verified = int(len(pairs)) == int(n_pairs)
+        verified = all(int(len(pairs)) == int(res[m]["P"]) for m in res)
         if not args.no_cpu_baseline:
             secs = tp + tj
-            cpu = {"value": round((nR + nS) / secs, 1), "unit": "input rects/s",
+            cpu = {"value": round((nR + nS) / secs, 1), "unit": "rects/s",
                    "cores": oracle.max_threads(), "kind": "oracle",
-                   "sample": f"full workload at K={K}: partition + join (Sec. 3.4), "
+                   "sample": f"the full workload at K={K}: partition + join (Sec. 3.4), "
                              f"{secs:.3f} s, {len(pairs)} pairs"}
     rec = {
         "metric": "input rects/s",
         "value": round((nR + nS) / (ms * 1e-3), 1),
         "unit": "rects/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
         "higher_is_better": True,
@@ -171,17 +212,25 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_r": nR, "n_s": nS, "grid_k": K,
-                   "schedule": "plain" if args.plain else "tuned",
-                   "mode": "count" if args.count else "pairs"},
-        "pairs_per_s": round(n_pairs / (ms * 1e-3), 1),
-        "n_pairs": int(n_pairs),
+                   "split_tau": r["tau"],
+                   "grid_choice": "fixed" if args.k else ("learned" if use_learned and main_mode == "tuned" else "rule"),
+                   "schedule": main_mode, "mode": "count" if args.count else "pairs"},
+        "pairs_per_s": round(P / (ms * 1e-3), 1),
+        "n_pairs": int(P),
         "pairs_match_oracle_count": verified,
+        "median_ms_per_step": round(r["median"], 4),
         "step_alg_bytes": int(b_step),
         "step_hbm_frac": round(b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "kernels": kernels,
+        "join_stats": r["stats"],
         "cpu_baseline": cpu,
     }
+    if "plain" in res and main_mode == "tuned":
+        b = res["plain"]
+        rec["plain_rule_baseline"] = {"ms_per_step": round(b["ms"], 4), "grid_k": b["K"],
+                                      "n_pairs": int(b["P"])}
+        rec["speedup_vs_plain_rule"] = round(b["ms"] / ms, 3)
     print(json.dumps(rec), flush=True)
 
 

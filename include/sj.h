@@ -76,7 +76,7 @@ typedef enum {
                                    never changes the result                                */
 
 /*
- * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.2.2).
+ * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.3.2).
  *   k          cells per dimension, 1..SJ_K_MAX.  0 in sj_choose_grid's input
  *              means "choose".
  *   split_tau  dense-tile split threshold: a tile whose two lists together
@@ -140,6 +140,10 @@ sj_status sj_join_count(const sj_part* R, const sj_part* S, int64_t* n_pairs, vo
 /* Entries (rectangle-tile assignments) and rectangles of a partitioned input. */
 sj_status sj_part_info(const sj_part* P, int64_t* n_rects, int64_t* n_entries, sj_grid* g);
 
+/* Two-level partition statistics: entries of the coarse (level-1) cells and
+ * level-2 chunks of the last sj_partition on P (diagnostics). */
+sj_status sj_part_stats(const sj_part* P, int64_t* level1_entries, int64_t* level2_chunks);
+
 /*
  * Copy a partitioned input back to the host (for inspection and tests):
  *   offsets   k*k + 1 int64: segment of tile t is [offsets[t], offsets[t+1]).
@@ -159,6 +163,129 @@ const char* sj_version(void);
 /* Detail of the last failure on the calling thread (HIP error text or the
  * device status word); empty if none.  The string is library-owned. */
 const char* sj_last_error(void);
+
+/*
+ * Work statistics of the last sj_join / sj_join_count on the calling thread's
+ * current device (diagnostics; synchronises the device).  Tiles with both
+ * lists non-empty are classed by entries n = |R_T| + |S_T|: small (batched
+ * into LDS units), medium (one workgroup each) and dense (sorted in global
+ * memory, swept in pivot ranges).  The plain schedule classifies no tiles
+ * (its per-tile fields are 0).  pairs_* are -1 unless single_pass.
+ */
+typedef struct {
+    int64_t n_pairs;
+    int64_t small_tiles, small_units, medium_tiles, dense_tiles, dense_units;
+    int64_t small_entries, medium_entries, dense_entries;
+    int64_t pairs_small, pairs_medium, pairs_dense;
+    int32_t single_pass;
+} sj_join_stats;
+
+sj_status sj_last_join_stats(sj_join_stats* out);
+
+/*
+ * Choosing the grid (statistics rule of Sec. 4.3.1 / 4.3.3, or the learned
+ * picker).  The chosen K and split threshold never change the join result.
+ *
+ * Features of an instance, SJ_FEAT_DIM float32 (R's block, then S's):
+ *   [0] log2(n + 1); [1], [2] log2(mean w + 1e-9), log2(mean h + 1e-9);
+ *   [3], [4] log2(std w + 1e-9), log2(std h + 1e-9)  (w, h in domain units);
+ *   [5 + 32*cy + cx] log2(1 + 1024 * share of the sampled rectangle centres
+ *   in cell (cx, cy) of a 32 x 32 grid over the domain), sampling every
+ *   100th rectangle.  Moments cover every rectangle (float64, fixed order).
+ */
+#define SJ_FEAT_SIDE 1029
+#define SJ_FEAT_DIM (2 * SJ_FEAT_SIDE)
+
+typedef struct {
+    double mean_extent;    /* e: mean over R and S of (w + h) / 2, domain units */
+    int32_t k_rule;        /* clamp(round(1 / (10 e)), 1, SJ_K_MAX)              */
+    int32_t k_learned;     /* the picker's K (0 if not used)                     */
+    int32_t tau_learned;   /* the picker's split threshold (0 if not used)       */
+    int32_t used_learned;  /* 1 if the picker chose                              */
+} sj_choice;
+
+/* The rule's K for a mean extent e (domain units): clamp(round(1/(10 e)),
+ * 1, SJ_K_MAX); e == 0 gives SJ_K_MAX.  Pure host function. */
+int32_t sj_rule_k(double mean_extent);
+
+/*
+ * Features of (R, S) (layout above) into `feat` (device, SJ_FEAT_DIM
+ * float32) and, if mean_extent != NULL, the rule's e to the host.  The
+ * domain is g's (g may be NULL: the unit square).  Synchronises the stream
+ * once.  SJ_ERR_RECT if a rectangle is invalid.
+ */
+sj_status sj_features(const float* R, int64_t nR, const float* S, int64_t nS, const sj_grid* g,
+                      float* feat, double* mean_extent, void* stream);
+
+/*
+ * Fill in g->k when it is 0 and g->split_tau when it is 0: with the loaded
+ * picker unless g->flags has SJ_RULE_ONLY, else with the rule (the split
+ * threshold then stays 0 = library default).  Non-zero fields are kept.
+ * info (host, may be NULL) receives the statistics and both choices.
+ * Computes the features on the device and synchronises the stream once.
+ */
+sj_status sj_choose_grid(const float* R, int64_t nR, const float* S, int64_t nS, sj_grid* g,
+                         sj_choice* info, void* stream);
+
+/*
+ * Learned picker for the calling thread's current device.  blob (host) =
+ * mu[SJ_FEAT_DIM] | sd[SJ_FEAT_DIM] | ystat[4] | params[sj_mlp_param_count(
+ * SJ_FEAT_DIM)]: feature standardisation, target standardisation (mean of
+ * log2 K, mean of log2 tau, their standard deviations) and the network.
+ * Copied to device memory; n must be the blob's exact length, else
+ * SJ_ERR_ARG.
+ */
+sj_status sj_picker_load(const float* blob, int64_t n);
+void sj_picker_unload(void);
+int32_t sj_picker_loaded(void);
+
+/*
+ * The picker's network: a 2 x 64 FP32 MLP, y = W3 relu(W2 relu(W1 xn + b1)
+ * + b2) + b3 with xn = (x - mu) / sd (mu, sd may be NULL: identity) and two
+ * outputs.  Parameters: one flat device array [W1 (64 x d_in, row-major),
+ * b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2)]; all buffers below
+ * are device float32, row-major per sample.  Reductions run in a fixed
+ * order, so results are deterministic.
+ */
+int64_t sj_mlp_param_count(int32_t d_in); /* -1 unless 1 <= d_in <= 4096 */
+
+/* Y[batch x 2]; act (may be NULL) receives [h1 (64), h2 (64)] per sample
+ * for sj_mlp_backward. */
+sj_status sj_mlp_forward(const float* params, int32_t d_in, const float* mu, const float* sd,
+                         const float* X, int32_t batch, float* Y, float* act, void* stream);
+
+/* Mean squared error L = 1/(2 batch) sum (Y - T)^2 into *loss (device, may
+ * be NULL) and dY = (Y - T) / batch. */
+sj_status sj_mlp_loss(const float* Y, const float* T, int32_t batch, float* dY, float* loss,
+                      void* stream);
+
+/* Gradient of the loss w.r.t. every parameter into grad (param count);
+ * dact is batch x 128 scratch. */
+sj_status sj_mlp_backward(const float* params, int32_t d_in, const float* mu, const float* sd,
+                          const float* X, int32_t batch, const float* act, const float* dY,
+                          float* dact, float* grad, void* stream);
+
+/* One Adam step (Kingma and Ba 2015, bias-corrected; step >= 1) on n
+ * parameters with moment buffers m, v. */
+sj_status sj_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t n, float lr,
+                      float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/*
+ * Synthetic instance generator on the device (the learned picker's training
+ * corpus and the many-join batch).  Counter-based Philox4x32-10 (Salmon et
+ * al., SC 2011) keyed by `seed`; `side` separates the streams of R and S.
+ * Rectangle i: with probability `background` (or when k == 0) a centre
+ * uniform in [0,1)^2, else mu_c + sigma_c * N(0, I) of a cluster c drawn by
+ * inverse CDF over cumw (redrawn while outside [0,1)^2, at most 64 times,
+ * then uniform).  Extents: ext_mode 0 = log-normal with median ext_a and
+ * log-sd ext_b; 1 = uniform in [0, ext_a].  Box = centre -/+ extent / 2.
+ *   rects       n x 4 float32, device, 16-byte aligned (output).
+ *   mu, sigma   k x 2 and k float32 cluster means / deviations, device.
+ *   cumw        k float32 cumulative weights (cumw[k-1] = 1), device.
+ */
+sj_status sj_generate(float* rects, int64_t n, const float* mu, const float* sigma,
+                      const float* cumw, int32_t k, float background, int32_t ext_mode,
+                      float ext_a, float ext_b, uint64_t seed, uint32_t side, void* stream);
 
 /*
  * Opt-in per-kernel timer (tracing).  sj_prof_enable(1) clears the totals and

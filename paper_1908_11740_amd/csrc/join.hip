@@ -50,7 +50,9 @@ enum Ctr : int {
     kDenseCount = 3,
     kDenseEntries = 4,
     kDenseUnits = 5,
-    kNumCtr = 6
+    kSmallEntries = 6,  // statistics: entries of the small and medium tiles
+    kMedEntries = 7,
+    kNumCtr = 8
 };
 
 constexpr int kWaveBuf = 256;        // staged pairs per wave (>= 64 lanes x kCand)
@@ -97,6 +99,7 @@ struct Args {
     uint32_t* sc_ctr;             // [kRegions] chunks reserved per region
     unsigned long long* sc_total; // [kTotals] hit totals
     int64_t sc_nch;               // chunks per region
+    int cls;                      // work class of the launch (pair totals per class)
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
@@ -128,6 +131,7 @@ enum Mode : int { kCount = 0, kWrite = 1, kSingle = 2 };
 constexpr int kRegions = 32;    // scratch regions / reservation counters
 constexpr int kChunkP = 512;    // pairs per scratch chunk
 constexpr int kTotals = 64;     // spread counters of the per-wave hit totals
+constexpr int kTotalsPer = 16;  // ... per work class (small, medium, dense)
 
 template <int MODE, bool BLOCK>
 struct Sink {
@@ -261,7 +265,7 @@ struct Sink {
         if (n) flush(a);
         if (lane_id() == 0) {
             if (have && ok) a.sc_fills[(size_t)region * a.sc_nch + chunk] = cfill;
-            if (total) atomicAdd(&a.sc_total[wave_gid % kTotals], total);
+            if (total) atomicAdd(&a.sc_total[a.cls * kTotalsPer + wave_gid % kTotalsPer], total);
         }
     }
 };
@@ -1047,10 +1051,11 @@ __device__ __forceinline__ void append_dense(const Args& a, uint32_t t, uint32_t
 __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
     __shared__ uint32_t s_uidx[kClassChunk];  // unit index of the k-th small tile
     __shared__ uint32_t s_ws[4][kClassNT / kWave];
+    __shared__ uint32_t s_msz[kClassNT / kWave];
     __shared__ uint32_t s_base[3];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const int64_t t0 = (int64_t)blockIdx.x * kClassChunk + (int64_t)tid * kClassPer;
-    uint32_t nsmall = 0, size_small = 0, nmed = 0;
+    uint32_t nsmall = 0, size_small = 0, nmed = 0, size_med = 0;
     uint4 ti[kClassPer];
     uint8_t cls[kClassPer];  // 0 none, 1 small, 2 medium, 3 dense
     uint32_t oR[kClassPer + 1], oS[kClassPer + 1];
@@ -1079,6 +1084,7 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
                 } else if (n <= (uint32_t)a.med_cap) {
                     cls[q] = 2;
                     ++nmed;
+                    size_med += n;
                 } else {
                     cls[q] = 3;
                     append_dense(a, (uint32_t)t, nr, ns);
@@ -1102,6 +1108,11 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
         s_ws[1][w] = isz;
         s_ws[2][w] = im;
     }
+    {
+        uint32_t ms = size_med;
+        for (int d = kWave / 2; d >= 1; d >>= 1) ms += __shfl_xor(ms, d, kWave);
+        if (lane == 0) s_msz[w] = ms;
+    }
     __syncthreads();
     if (tid == 0) {
         uint32_t an = 0, as = 0, am = 0;
@@ -1116,6 +1127,10 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
         }
         s_ws[3][0] = an;
         s_ws[3][1] = am;
+        uint32_t msum = 0;
+        for (int q = 0; q < kClassNT / kWave; ++q) msum += s_msz[q];
+        if (as) atomicAdd(&a.ctr[kSmallEntries], as);
+        if (msum) atomicAdd(&a.ctr[kMedEntries], msum);
     }
     __syncthreads();
     const uint32_t total_small = s_ws[3][0], total_med = s_ws[3][1];
@@ -1549,8 +1564,10 @@ constexpr const char* mode_tag(int mode, const char* count, const char* write, c
 
 // one pass (count, write or single) over every unit
 template <int MODE>
-hipError_t join_pass(const Args& a, const JoinParams& p, const JoinWork& w, hipStream_t s) {
+hipError_t join_pass(const Args& a0, const JoinParams& p, const JoinWork& w, hipStream_t s) {
     hipError_t e = hipSuccess;
+    Args a = a0;
+    a.cls = 0;
     if (p.plain) {
         ProfRange pr(mode_tag(MODE, "k_plain_tiles_count", "k_plain_tiles_write",
                               "k_plain_tiles_single"), s);
@@ -1563,6 +1580,7 @@ hipError_t join_pass(const Args& a, const JoinParams& p, const JoinWork& w, hipS
                                    w.num_cus, s);
         }
         if (e == hipSuccess) {
+            a.cls = 1;
             ProfRange pr(mode_tag(MODE, "k_lds_medium_count", "k_lds_medium_write",
                                   "k_lds_medium_single"), s);
             e = launch_units<kMedNT, kMedE / kMedNT, true, MODE>(
@@ -1570,6 +1588,7 @@ hipError_t join_pass(const Args& a, const JoinParams& p, const JoinWork& w, hipS
         }
     }
     if (e != hipSuccess) return e;
+    a.cls = 2;
     ProfRange pr(mode_tag(MODE, "k_dense_sweep_count", "k_dense_sweep_write",
                           "k_dense_sweep_single"), s);
     hipLaunchKernelGGL(k_dense_sweep<MODE>, dim3(w.num_cus * 4), dim3(kDenseNT), 0, s, a);
@@ -1691,6 +1710,35 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, w.ctr, w.st, R.st, S.st,
                        single ? w.sc_total : nullptr);
     return hipGetLastError();
+}
+
+hipError_t join_stats(const JoinWork& w, bool single, sj_join_stats* o) {
+    uint32_t c[kNumCtr];
+    unsigned long long t[kTotals];
+    hipError_t e = hipMemcpy(c, w.ctr, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    if (single && w.sc_total) {
+        e = hipMemcpy(t, w.sc_total, sizeof(t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+    }
+    o->small_tiles = c[kTilesWritten];
+    o->small_units = c[kUnitsWritten];
+    o->medium_tiles = c[kMedCount];
+    o->dense_tiles = c[kDenseCount];
+    o->dense_units = c[kDenseUnits];
+    o->small_entries = c[kSmallEntries];
+    o->medium_entries = c[kMedEntries];
+    o->dense_entries = c[kDenseEntries];
+    int64_t pc[3] = {-1, -1, -1};
+    if (single && w.sc_total)
+        for (int k = 0; k < 3; ++k) {
+            pc[k] = 0;
+            for (int i = 0; i < kTotalsPer; ++i) pc[k] += (int64_t)t[k * kTotalsPer + i];
+        }
+    o->pairs_small = pc[0];
+    o->pairs_medium = pc[1];
+    o->pairs_dense = pc[2];
+    return hipSuccess;
 }
 
 int scratch_regions() { return kRegions; }

@@ -235,6 +235,7 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
             return from_hip(e);
         }
         hs = *ds->host;
+        w.last_single = p.single;
         // the scratch of the single pass ran out although the output fits:
         // join again in two passes
         if (p.single && (hs.flags & kStatScratch) && !(hs.flags & ~kStatScratch) &&
@@ -390,6 +391,18 @@ sj_status sj_part_info(const sj_part* P, int64_t* n_rects, int64_t* n_entries, s
     return SJ_OK;
 }
 
+sj_status sj_part_stats(const sj_part* P, int64_t* level1_entries, int64_t* level2_chunks) {
+    if (!P) return SJ_ERR_ARG;
+    if (level1_entries) *level1_entries = P->m1;
+    if (level2_chunks) {
+        uint32_t nc = 0;
+        if (P->st && hipMemcpy(&nc, &P->st->n_chunks, 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return SJ_ERR_DEVICE;
+        *level2_chunks = nc;
+    }
+    return SJ_OK;
+}
+
 sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, void* stream) {
     if (!P) return SJ_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
@@ -445,5 +458,21 @@ const char* sj_status_string(sj_status s) {
 const char* sj_version(void) { return "sj 0.1 (gfx950)"; }
 
 const char* sj_last_error(void) { return g_err; }
+
+sj_status sj_last_join_stats(sj_join_stats* out) {
+    if (!out) return SJ_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SJ_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end() || !it->second.init) return SJ_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    const JoinWork& w = it->second.w;
+    if (hipDeviceSynchronize() != hipSuccess) return SJ_ERR_DEVICE;
+    if (join_stats(w, w.last_single, out) != hipSuccess) return SJ_ERR_DEVICE;
+    out->n_pairs = (int64_t)it->second.host->n_pairs;
+    out->single_pass = w.last_single ? 1 : 0;
+    return SJ_OK;
+}
 
 }  // extern "C"

@@ -166,6 +166,7 @@ struct JoinWork {
     uint32_t* sc_ctr = nullptr;     // [regions] chunks reserved per region
     unsigned long long* sc_total = nullptr;  // [scratch_totals()] pair totals
     int64_t sc_nch = 0;
+    bool last_single = false;       // the last join ran in one pass
     uint32_t* ctr = nullptr;
     DevStatus* st = nullptr;
     void* host_status = nullptr;    // pinned DevStatus mirror
@@ -175,6 +176,7 @@ struct JoinWork {
 hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork& w,
                     sj_pair* out, int64_t capacity, hipStream_t s);
 int64_t join_slots(const JoinParams& p, const JoinWork& w);
+hipError_t join_stats(const JoinWork& w, bool single, sj_join_stats* out);
 int scratch_regions();
 int scratch_chunk_pairs();
 int scratch_totals();

@@ -41,6 +41,22 @@ class Grid(ctypes.Structure):
                 ("domain", ctypes.c_float * 4), ("flags", ctypes.c_uint32)]
 
 
+class Choice(ctypes.Structure):
+    _fields_ = [("mean_extent", ctypes.c_double), ("k_rule", ctypes.c_int32),
+                ("k_learned", ctypes.c_int32), ("tau_learned", ctypes.c_int32),
+                ("used_learned", ctypes.c_int32)]
+
+
+class JoinStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in (
+        "n_pairs", "small_tiles", "small_units", "medium_tiles", "dense_tiles", "dense_units",
+        "small_entries", "medium_entries", "dense_entries", "pairs_small", "pairs_medium",
+        "pairs_dense")] + [("single_pass", ctypes.c_int32)]
+
+
+FEAT_SIDE = 1029
+FEAT_DIM = 2 * FEAT_SIDE
+
 _lib = None
 
 
@@ -71,7 +87,34 @@ def lib():
         L.sj_prof_total_ms.restype = ctypes.c_double
         L.sj_prof_calls.argtypes = [ctypes.c_int]
         L.sj_prof_calls.restype = ctypes.c_int64
-        for f in ("sj_partition", "sj_join", "sj_join_count", "sj_part_info", "sj_part_download"):
+        f32 = ctypes.c_float
+        L.sj_part_stats.argtypes = [vp, i64p, i64p]
+        L.sj_part_stats.restype = ctypes.c_int
+        L.sj_last_join_stats.argtypes = [ctypes.POINTER(JoinStats)]
+        L.sj_last_join_stats.restype = ctypes.c_int
+        L.sj_generate.argtypes = [vp, i64, vp, vp, vp, ctypes.c_int32, f32, ctypes.c_int32, f32,
+                                  f32, ctypes.c_uint64, ctypes.c_uint32, vp]
+        L.sj_generate.restype = ctypes.c_int
+        L.sj_rule_k.argtypes = [ctypes.c_double]
+        L.sj_rule_k.restype = ctypes.c_int32
+        L.sj_features.argtypes = [vp, i64, vp, i64, ctypes.POINTER(Grid), vp,
+                                  ctypes.POINTER(ctypes.c_double), vp]
+        L.sj_choose_grid.argtypes = [vp, i64, vp, i64, ctypes.POINTER(Grid),
+                                     ctypes.POINTER(Choice), vp]
+        L.sj_picker_load.argtypes = [vp, i64]
+        L.sj_picker_unload.argtypes = []
+        L.sj_picker_unload.restype = None
+        L.sj_picker_loaded.restype = ctypes.c_int32
+        L.sj_mlp_param_count.argtypes = [ctypes.c_int32]
+        L.sj_mlp_param_count.restype = i64
+        L.sj_mlp_forward.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.sj_mlp_loss.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.sj_mlp_backward.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, vp,
+                                      vp, vp]
+        L.sj_mlp_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, ctypes.c_int32, vp]
+        for f in ("sj_partition", "sj_join", "sj_join_count", "sj_part_info", "sj_part_download",
+                  "sj_features", "sj_choose_grid", "sj_picker_load", "sj_mlp_forward",
+                  "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -126,6 +169,12 @@ class Part:
         _check(lib().sj_part_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(g)),
                "sj_part_info")
         return n.value, m.value, g
+
+    def stats(self):
+        """(level-1 entries, level-2 chunks) of the last partition."""
+        m1, nc = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sj_part_stats(self._h, ctypes.byref(m1), ctypes.byref(nc)), "sj_part_stats")
+        return m1.value, nc.value
 
     def download(self, stream=None):
         n, m, g = self.info()
@@ -192,6 +241,120 @@ def join(R, S, capacity=None, stream=None):
         s, n = join_into(R, S, out, stream)
         _check(s, "sj_join")
     return out[:n]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
+
+
+def last_join_stats():
+    """Work statistics of the last join on the current device (dict)."""
+    st = JoinStats()
+    _check(lib().sj_last_join_stats(ctypes.byref(st)), "sj_last_join_stats")
+    return {f: getattr(st, f) for f, _ in JoinStats._fields_}
+
+
+def generate(n, mu=None, sigma=None, weights=None, background=1.0, extent="lognormal",
+             ext_a=5e-5, ext_b=1.0, seed=0, side=0, stream=None):
+    """(n, 4) float32 device tensor of synthetic rectangles (sj_generate).
+    mu (k, 2), sigma (k,), weights (k,): the cluster mixture (host arrays)."""
+    import numpy as np
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((int(n), 4), dtype=torch.float32, device=dev)
+    k = 0 if mu is None else len(mu)
+    if k:
+        cw = np.cumsum(np.asarray(weights, np.float64))
+        cw = (cw / cw[-1]).astype(np.float32)
+        cw[-1] = 1.0
+        mu_d = torch.from_numpy(np.ascontiguousarray(mu, np.float32)).to(dev)
+        sg_d = torch.from_numpy(np.ascontiguousarray(sigma, np.float32)).to(dev)
+        cw_d = torch.from_numpy(cw).to(dev)
+    else:
+        mu_d = sg_d = cw_d = None
+    mode = 0 if extent == "lognormal" else 1
+    _check(lib().sj_generate(_ptr(out), int(n), _ptr(mu_d), _ptr(sg_d), _ptr(cw_d), k,
+                             float(background), mode, float(ext_a), float(ext_b),
+                             int(seed) & (2**64 - 1), int(side), _stream(stream)), "sj_generate")
+    return out
+
+
+def rule_k(mean_extent):
+    return int(lib().sj_rule_k(float(mean_extent)))
+
+
+def features(R, S, domain=None, stream=None):
+    """(SJ_FEAT_DIM,) float32 device tensor of instance features and the rule's
+    mean extent e."""
+    R, S = _rects(R), _rects(S)
+    out = torch.empty(FEAT_DIM, dtype=torch.float32, device=R.device)
+    e = ctypes.c_double()
+    g = make_grid(1, 0, domain)
+    _check(lib().sj_features(_ptr(R), R.shape[0], _ptr(S), S.shape[0], ctypes.byref(g),
+                             _ptr(out), ctypes.byref(e), _stream(stream)), "sj_features")
+    return out, e.value
+
+
+def choose_grid(R, S, k=0, split_tau=0, domain=None, flags=0, stream=None):
+    """sj_choose_grid: returns (k, split_tau, info dict)."""
+    R, S = _rects(R), _rects(S)
+    g = make_grid(k, split_tau, domain, flags)
+    c = Choice()
+    _check(lib().sj_choose_grid(_ptr(R), R.shape[0], _ptr(S), S.shape[0], ctypes.byref(g),
+                                ctypes.byref(c), _stream(stream)), "sj_choose_grid")
+    info = {f: getattr(c, f) for f, _ in Choice._fields_}
+    return g.k, g.split_tau, info
+
+
+def picker_load(blob):
+    """Load a picker blob (host float32 array: mu | sd | ystat | params)."""
+    import numpy as np
+    b = np.ascontiguousarray(blob, dtype=np.float32)
+    _check(lib().sj_picker_load(b.ctypes.data_as(ctypes.c_void_p), b.size), "sj_picker_load")
+
+
+def picker_unload():
+    lib().sj_picker_unload()
+
+
+def picker_loaded():
+    return bool(lib().sj_picker_loaded())
+
+
+def mlp_param_count(d_in):
+    return int(lib().sj_mlp_param_count(int(d_in)))
+
+
+def mlp_forward(params, X, mu=None, sd=None, act=None, stream=None):
+    B, d = X.shape
+    Y = torch.empty((B, 2), dtype=torch.float32, device=X.device)
+    _check(lib().sj_mlp_forward(_ptr(params), d, _ptr(mu), _ptr(sd), _ptr(X), B, _ptr(Y),
+                                _ptr(act), _stream(stream)), "sj_mlp_forward")
+    return Y
+
+
+def mlp_loss(Y, T, stream=None):
+    dY = torch.empty_like(Y)
+    loss = torch.empty(1, dtype=torch.float32, device=Y.device)
+    _check(lib().sj_mlp_loss(_ptr(Y), _ptr(T), Y.shape[0], _ptr(dY), _ptr(loss), _stream(stream)),
+           "sj_mlp_loss")
+    return loss, dY
+
+
+def mlp_backward(params, X, act, dY, mu=None, sd=None, grad=None, dact=None, stream=None):
+    B, d = X.shape
+    if grad is None:
+        grad = torch.empty_like(params)
+    if dact is None:
+        dact = torch.empty((B, 128), dtype=torch.float32, device=X.device)
+    _check(lib().sj_mlp_backward(_ptr(params), d, _ptr(mu), _ptr(sd), _ptr(X), B, _ptr(act),
+                                 _ptr(dY), _ptr(dact), _ptr(grad), _stream(stream)),
+           "sj_mlp_backward")
+    return grad
+
+
+def mlp_adam(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().sj_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), lr,
+                             beta1, beta2, eps, int(step), _stream(stream)), "sj_mlp_adam")
 
 
 def version():
