@@ -165,6 +165,71 @@ const char* sj_version(void);
 const char* sj_last_error(void);
 
 /*
+ * Autotuner.  sj_tune times the join of (R, S) -- into `out` (capacity
+ * pairs), or count-only if out is NULL -- `reps` times for every candidate
+ * schedule: workgroup size of the small-tile kernel (64 = one wavefront per
+ * LDS unit, 128, 256, 512), the entry cap of a small tile (E/4 or E/2 of
+ * the unit's LDS slab E), the entry cap of a medium tile (1024, 2048) and,
+ * unless the grid fixes it, the split threshold (128, 256, 1024).  The
+ * fastest is cached for (device, K, log2 |entries| of R and S, mode) and
+ * used by every later sj_join / sj_join_count that matches; best (host, may
+ * be NULL) receives it.  The schedule never changes the result.
+ * Synchronises the stream.  sj_tune_clear empties the cache.
+ */
+typedef struct {
+    int32_t block;      /* 64, 128, 256 or 512                  */
+    int32_t small_cap;  /* tiles with <= small_cap entries are batched */
+    int32_t med_cap;    /* tiles with <= med_cap entries: one workgroup each */
+    int32_t split_tau;  /* 0 = the grid's                        */
+    double ms;          /* mean time of the winning candidate    */
+} sj_tuning;
+
+sj_status sj_tune(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
+                  int32_t reps, sj_tuning* best, void* stream);
+void sj_tune_clear(void);
+/* Put a schedule into the cache for the class of (R, S) (as sj_tune would):
+ * block in {64, 128, 256, 512}, caps >= 2; clamped to the kernel's LDS slab. */
+sj_status sj_tune_set(const sj_part* R, const sj_part* S, int32_t count_only,
+                      const sj_tuning* t);
+
+/*
+ * Many independent joins in one replayable launch.  Joins, like tiles, are
+ * independent tasks (Sec. 3.4): a batch plans every join once (grid from
+ * grids[j], or where its k or split_tau is 0 the picker / rule of
+ * sj_choose_grid), sizes its buffers, assigns the joins longest-first to a
+ * few concurrent streams and records all partition and join kernels into
+ * one hipGraph.  sj_batch_run replays it: one graph launch and one status
+ * readback for the whole batch.
+ *   R[j], S[j]   device rectangle arrays (as sj_partition) of nR[j], nS[j]
+ *                rectangles; borrowed for the batch's lifetime (replays
+ *                read them again, so their contents may change between runs).
+ *   grids        n_joins grids, or NULL (all chosen).
+ *   out          device pair buffer, or NULL for count-only joins; join j
+ *                writes [out_offsets[j], out_offsets[j+1]) (host array of
+ *                n_joins + 1).  Borrowed like the inputs.
+ *   n_pairs      host, n_joins: |J_j| of every join.
+ * Creation runs every join once (capacities are checked on the device and
+ * grown as needed) before recording.  A run returns SJ_ERR_CAPACITY if some
+ * join's pairs exceed its slice (its n_pairs is still exact).  A join that
+ * outgrows its buffers on a later run (new data) is re-run alone with grown
+ * buffers and the graph is recorded again.  Synchronises `stream` once.
+ */
+typedef struct sj_batch sj_batch;
+
+sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t* nR,
+                          const float* const* S, const int64_t* nS, const sj_grid* grids,
+                          sj_pair* out, const int64_t* out_offsets, sj_batch** batch,
+                          void* stream);
+sj_status sj_batch_run(sj_batch* batch, int64_t* n_pairs, void* stream);
+/* The grid of every join (k and split_tau; 0 = library default). */
+sj_status sj_batch_info(const sj_batch* batch, int32_t* k, int32_t* split_tau);
+void sj_batch_free(sj_batch* batch);
+/* One-shot: create (which runs every join), report, free. */
+sj_status sj_batch_join(int32_t n_joins, const float* const* R, const int64_t* nR,
+                        const float* const* S, const int64_t* nS, const sj_grid* grids,
+                        sj_pair* out, const int64_t* out_offsets, int64_t* n_pairs, void* stream);
+
+/*
  * Work statistics of the last sj_join / sj_join_count on the calling thread's
  * current device (diagnostics; synchronises the device).  Tiles with both
  * lists non-empty are classed by entries n = |R_T| + |S_T|: small (batched

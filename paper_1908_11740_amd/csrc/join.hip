@@ -609,19 +609,71 @@ __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const Til
     }
     __syncthreads();
     if (MODE != kWrite) {
-        // 3. rank sort within each tile segment, write the sorted payload to
-        //    LDS and back to the slab in global memory
+        // 3. sort within each tile segment, write the sorted payload to LDS
+        //    and back to the slab in global memory.  Batched small tiles:
+        //    rank sort (each entry counts the smaller keys of its segment).
+        //    One large tile (TC == 2): a rank sort is quadratic, so both lists
+        //    are bitonic-sorted as (key, position) words in the box area,
+        //    and the sorted positions are inverted into ranks.
         int pos[Q];
+        if (TC == 2 && (NR > 64 || NS > 64)) {
+            unsigned long long* kw = (unsigned long long*)L.bx;  // 2E words fit E boxes
+            int PR = 1, PS = 1;
+            while (PR < NR) PR <<= 1;
+            while (PS < NS) PS <<= 1;
+            for (int i = tid; i < PR + PS; i += NT) {
+                const bool r = i < PR;
+                const int j = r ? i : i - PR;
+                const int n = r ? NR : NS;
+                kw[i] = j < n ? ((unsigned long long)L.key[r ? j : NR + j] << 32) | (uint32_t)j
+                              : ~0ull;
+            }
+            __syncthreads();
+            // both networks at once: pair index i < PR/2 belongs to R's
+            for (int size = 2; size <= (PR > PS ? PR : PS); size <<= 1) {
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int i = tid; i < (PR + PS) / 2; i += NT) {
+                        const bool r = i < PR / 2;
+                        const int P = r ? PR : PS;
+                        if (size > P) continue;
+                        const int ii = r ? i : i - PR / 2;
+                        const int lo = 2 * ii - (ii & (stride - 1));
+                        const int hi = lo + stride;
+                        const bool up = (lo & size) == 0;
+                        unsigned long long* w = r ? kw : kw + PR;
+                        const unsigned long long x = w[lo], y = w[hi];
+                        if ((x > y) == up) {
+                            w[lo] = y;
+                            w[hi] = x;
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int i = tid; i < NE; i += NT) {  // rank of each entry (keys are no longer needed)
+                const bool r = i < NR;
+                const uint32_t src = (uint32_t)kw[r ? i : PR + (i - NR)];
+                L.key[r ? src : NR + src] = (uint32_t)i;
+            }
+            __syncthreads();
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int e = tid + q * NT;
-            pos[q] = -1;
-            if (e < NE) {
-                const bool isR = e < NR;
-                const int k = L.tk[e];
-                const int lo = isR ? (int)L.rl[k] : NR + (int)L.sl[k];
-                const int hi = isR ? (int)L.rl[k + 1] : NR + (int)L.sl[k + 1];
-                pos[q] = lo + seg_rank(L.key, lo, hi, e);
+            for (int q = 0; q < Q; ++q) {
+                const int e = tid + q * NT;
+                pos[q] = e < NE ? (int)L.key[e] : -1;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int e = tid + q * NT;
+                pos[q] = -1;
+                if (e < NE) {
+                    const bool isR = e < NR;
+                    const int k = L.tk[e];
+                    const int lo = isR ? (int)L.rl[k] : NR + (int)L.sl[k];
+                    const int hi = isR ? (int)L.rl[k + 1] : NR + (int)L.sl[k + 1];
+                    pos[q] = lo + seg_rank(L.key, lo, hi, e);
+                }
             }
         }
 #pragma unroll

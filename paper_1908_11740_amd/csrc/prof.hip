@@ -25,6 +25,7 @@ struct Tot {
 
 std::mutex mu;
 bool enabled = false;
+bool paused = false;
 std::vector<hipEvent_t> pool;
 std::vector<Rec> pending;
 std::vector<std::pair<std::string, Tot>> totals;
@@ -49,9 +50,16 @@ Tot& slot(const std::string& n) {
 
 }  // namespace
 
+bool prof_pause(bool p) {
+    std::lock_guard<std::mutex> lk(mu);
+    const bool old = paused;
+    paused = p;
+    return old;
+}
+
 ProfRange::ProfRange(const char* name, hipStream_t s) : name_(name), s_(s), a_(nullptr) {
     std::lock_guard<std::mutex> lk(mu);
-    if (!enabled) return;
+    if (!enabled || paused) return;
     a_ = take();
     if (a_ && hipEventRecord((hipEvent_t)a_, s) != hipSuccess) a_ = nullptr;
 }

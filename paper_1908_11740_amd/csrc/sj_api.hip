@@ -2,6 +2,7 @@
 // workspace management, kernel sequencing and the one status readback per
 // call.  No exception crosses the ABI.
 #include <algorithm>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -125,6 +126,26 @@ hipError_t read_status(const DevStatus* dst, DevStatus* host, hipStream_t s) {
     return hipStreamSynchronize(s);
 }
 
+// Autotuner cache: launch shape of the small-tile kernel, LDS slab caps and
+// split threshold per (device, K, log2 entries of R and S, mode).
+struct TuneKey {
+    int dev, k, lr, ls, count_only;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(dev, k, lr, ls, count_only) < std::tie(o.dev, o.k, o.lr, o.ls, o.count_only);
+    }
+};
+std::map<TuneKey, sj_tuning> g_tune;
+
+int log2_bucket(int64_t m) {
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < m) ++b;
+    return b;
+}
+
+TuneKey tune_key(int dev, const sj_grid& g, int64_t mR, int64_t mS, bool count_only) {
+    return TuneKey{dev, g.k, log2_bucket(mR), log2_bucket(mS), count_only ? 1 : 0};
+}
+
 // Schedule parameters of a join.
 JoinParams join_params(const sj_grid& g, bool count_only) {
     JoinParams p{};
@@ -144,23 +165,29 @@ JoinParams join_params(const sj_grid& g, bool count_only) {
     return p;
 }
 
-sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
-                  int64_t* n_pairs, bool count_only, hipStream_t s) {
-    if (!R || !S || !n_pairs || capacity < 0) return SJ_ERR_ARG;
-    if (!count_only && capacity > 0 && !out) return SJ_ERR_ARG;
-    if (!same_grid(R->grid, S->grid)) return SJ_ERR_GRID_MISMATCH;
-    if (R->device != S->device) return SJ_ERR_ARG;
-    std::lock_guard<std::mutex> lk(g_mu);
-    int cur = 0;
-    if (hipGetDevice(&cur) != hipSuccess) return SJ_ERR_DEVICE;
-    if (cur != R->device && hipSetDevice(R->device) != hipSuccess) return SJ_ERR_DEVICE;
-    DeviceState* ds = nullptr;
-    sj_status st = device_state(R->device, &ds);
-    if (st != SJ_OK) return st;
-    JoinWork& w = ds->w;
-    JoinParams p = join_params(R->grid, count_only);
-    p.C = (int64_t)R->bl.G * R->bl.G * R->bl.B * R->bl.B;
-    const int64_t mR = R->m, mS = S->m;
+// Apply a tuning (block shape, caps; split threshold unless the grid fixes one).
+void apply_tuning(JoinParams& p, const sj_grid& g, const sj_tuning& t) {
+    if (p.plain) return;
+    p.block = t.block;
+    const int E = lds_unit_entries(p.block);
+    p.small_cap = std::min(t.small_cap, E / 2 + E / 4);
+    p.unit_cap = E - p.small_cap;
+    p.med_cap = std::max(p.small_cap, std::min(t.med_cap, lds_medium_entries()));
+    if (g.split_tau == 0 && t.split_tau > 0) p.split_tau = t.split_tau;
+}
+
+JoinParams tuned_params(int dev, const sj_grid& g, int64_t mR, int64_t mS, bool count_only) {
+    JoinParams p = join_params(g, count_only);
+    auto it = g_tune.find(tune_key(dev, g, mR, mS, count_only));
+    if (it != g_tune.end()) apply_tuning(p, g, it->second);
+    return p;
+}
+
+// Bounds of a join's work lists and growth of the workspace to hold them
+// (tile entries mR, mS: exact after a partition, or capacity bounds).
+sj_status join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_t mS,
+                       int64_t capacity) {
+    p.C = C;
     const int64_t active = std::min<int64_t>(p.C, std::min(mR, mS)) + 1;
     p.units_bound = std::min<int64_t>(active, (mR + mS) / p.unit_cap + classify_blocks(p.C) + 1);
     p.med_bound = std::min<int64_t>(active, (mR + mS) / (p.small_cap + 1) + 1);
@@ -172,8 +199,8 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
         if ((e = grow(w.med, w.cap_med, p.med_bound)) != hipSuccess) return from_hip(e);
     }
     if ((e = grow(w.dense, w.cap_dense, ndense)) != hipSuccess) return from_hip(e);
-    w.cap_dunits = p.plain ? w.cap_dense
-                           : (mR + mS) / std::max(1, p.split_tau) + w.cap_dense + 1;
+    w.cap_dunits = std::max<int64_t>(
+        w.cap_dunits, p.plain ? w.cap_dense : (mR + mS) / std::max(1, p.split_tau) + w.cap_dense + 1);
     {
         const int64_t slots = join_slots(p, w);
         if ((e = grow(w.ucnt, w.cap_ucnt, slots + 1)) != hipSuccess) return from_hip(e);
@@ -208,7 +235,8 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
         const int64_t waves = 3LL * w.num_cus * 32;
         int64_t nch = (want + want / 4) / (regions * cp) + (waves + regions - 1) / regions + 2;
         // test hook: a tiny scratch forces the two-pass retry
-        if (const char* dbg = std::getenv("SJ_DEBUG_SCRATCH_CHUNKS")) nch = std::max(1, std::atoi(dbg));
+        const char* dbg = std::getenv("SJ_DEBUG_SCRATCH_CHUNKS");
+        if (dbg) nch = std::max(1, std::atoi(dbg));
         if ((e = grow(w.sc_buf, w.cap_sc_pairs, regions * nch * cp)) != hipSuccess ||
             (e = grow(w.sc_fills, w.cap_sc_fills, regions * nch + 1)) != hipSuccess ||
             (e = grow(w.scan_tmp, w.cap_scan, scan_block_sums_needed(regions * nch))) != hipSuccess)
@@ -219,8 +247,75 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
                 (e = grow(w.sc_total, c2, scratch_totals())) != hipSuccess)
                 return from_hip(e);
         }
-        w.sc_nch = nch;
+        w.sc_nch = dbg ? nch : std::max<int64_t>(w.sc_nch, nch);
     }
+    return SJ_OK;
+}
+
+// Grow the buffers of a partitioned input for n rectangles with level-1 and
+// tile-entry capacities of at least need_m1 and need_m (P.bl set).
+hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
+    Part* P = &Pr;
+    hipError_t e = hipSuccess;
+    const Blocking bl = P->bl;
+    const int64_t G1 = (int64_t)bl.G * bl.G, B2 = (int64_t)bl.B * bl.B, Cb = G1 * B2;
+    const int64_t ch1 = l1_chunk(n);
+    const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
+    const int64_t need_chunks = need_m1 / kChunk2 + G1 + 2;
+    if ((e = grow(P->h1, P->cap_h1, G1 * nb1 + 1)) != hipSuccess ||
+        (e = grow(P->cp, P->cap_cp, G1 + 1)) != hipSuccess ||
+        (e = grow(P->chunk_cell, P->cap_chunks, need_chunks)) != hipSuccess ||
+        (e = grow(P->h2, P->cap_h2, B2 * P->cap_chunks + 1)) != hipSuccess ||
+        (e = grow(P->off, P->cap_off, Cb + 1)) != hipSuccess ||
+        (e = grow(P->scan_tmp, P->cap_scan,
+                  scan_block_sums_needed(std::max(G1 * nb1, B2 * P->cap_chunks)))) !=
+            hipSuccess)
+        return e;
+    if (need_m1 > P->cap_m1 || !P->e1box) {
+        if (P->e1box) (void)hipFree(P->e1box);
+        if (P->e1id) (void)hipFree(P->e1id);
+        P->e1box = nullptr;
+        P->e1id = nullptr;
+        P->cap_m1 = 0;
+        int64_t c1 = 0, c2 = 0;
+        if ((e = grow(P->e1box, c1, need_m1)) != hipSuccess ||
+            (e = grow(P->e1id, c2, c1)) != hipSuccess)
+            return e;
+        P->cap_m1 = c1;
+    }
+    if (need_m > P->cap_m || !P->box) {
+        if (P->box) (void)hipFree(P->box);
+        if (P->idf) (void)hipFree(P->idf);
+        P->box = nullptr;
+        P->idf = nullptr;
+        P->cap_m = 0;
+        int64_t c1 = 0, c2 = 0;
+        if ((e = grow(P->box, c1, need_m)) != hipSuccess ||
+            (e = grow(P->idf, c2, c1)) != hipSuccess)
+            return e;
+        P->cap_m = c1;
+    }
+    return hipSuccess;
+}
+
+sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
+                  int64_t* n_pairs, bool count_only, hipStream_t s) {
+    if (!R || !S || !n_pairs || capacity < 0) return SJ_ERR_ARG;
+    if (!count_only && capacity > 0 && !out) return SJ_ERR_ARG;
+    if (!same_grid(R->grid, S->grid)) return SJ_ERR_GRID_MISMATCH;
+    if (R->device != S->device) return SJ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return SJ_ERR_DEVICE;
+    if (cur != R->device && hipSetDevice(R->device) != hipSuccess) return SJ_ERR_DEVICE;
+    DeviceState* ds = nullptr;
+    sj_status st = device_state(R->device, &ds);
+    if (st != SJ_OK) return st;
+    JoinWork& w = ds->w;
+    JoinParams p = tuned_params(R->device, R->grid, R->m, S->m, count_only);
+    st = join_prepare(w, p, (int64_t)R->bl.G * R->bl.G * R->bl.B * R->bl.B, R->m, S->m, capacity);
+    if (st != SJ_OK) return st;
+    hipError_t e = hipSuccess;
     DevStatus hs{};
     for (int attempt = 0; attempt < 2; ++attempt) {
         e = run_join(*R, *S, p, w, count_only ? nullptr : out, count_only ? 0 : capacity, s);
@@ -257,6 +352,30 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
 }
 
 }  // namespace
+
+// Entry points for the batch driver (batch.hip).
+std::mutex& api_mutex() { return g_mu; }
+void api_set_error(const char* msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
+sj_status api_workspace(int dev, JoinWork** w, int* num_cus) {
+    DeviceState* ds = nullptr;
+    sj_status st = device_state(dev, &ds);
+    if (st != SJ_OK) return st;
+    *w = &ds->w;
+    *num_cus = ds->w.num_cus;
+    return SJ_OK;
+}
+sj_status api_resolve_grid(const sj_grid* g, sj_grid& out, GridDev& gd) {
+    return resolve_grid(g, out, gd);
+}
+JoinParams api_join_params(const sj_grid& g, bool count_only) { return join_params(g, count_only); }
+sj_status api_join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_t mS,
+                           int64_t capacity) {
+    return join_prepare(w, p, C, mR, mS, capacity);
+}
+hipError_t api_part_prepare(Part& P, int64_t n, int64_t need_m1, int64_t need_m) {
+    return part_prepare(P, n, need_m1, need_m);
+}
+
 }  // namespace sj
 
 using namespace sj;
@@ -310,40 +429,7 @@ sj_status sj_partition(const float* rects, int64_t n, const sj_grid* g, sj_part*
     P->gd = gd;
     P->grid = grid;
     for (int attempt = 0; attempt < 4; ++attempt) {
-        const int64_t need_chunks = need_m1 / kChunk2 + G1 + 2;
-        if ((e = grow(P->h1, P->cap_h1, G1 * nb1 + 1)) != hipSuccess ||
-            (e = grow(P->cp, P->cap_cp, G1 + 1)) != hipSuccess ||
-            (e = grow(P->chunk_cell, P->cap_chunks, need_chunks)) != hipSuccess ||
-            (e = grow(P->h2, P->cap_h2, B2 * P->cap_chunks + 1)) != hipSuccess ||
-            (e = grow(P->off, P->cap_off, Cb + 1)) != hipSuccess ||
-            (e = grow(P->scan_tmp, P->cap_scan,
-                      scan_block_sums_needed(std::max(G1 * nb1, B2 * P->cap_chunks)))) !=
-                hipSuccess)
-            return fail(from_hip(e));
-        if (need_m1 > P->cap_m1 || !P->e1box) {
-            if (P->e1box) (void)hipFree(P->e1box);
-            if (P->e1id) (void)hipFree(P->e1id);
-            P->e1box = nullptr;
-            P->e1id = nullptr;
-            P->cap_m1 = 0;
-            int64_t c1 = 0, c2 = 0;
-            if ((e = grow(P->e1box, c1, need_m1)) != hipSuccess ||
-                (e = grow(P->e1id, c2, c1)) != hipSuccess)
-                return fail(from_hip(e));
-            P->cap_m1 = c1;
-        }
-        if (need_m > P->cap_m || !P->box) {
-            if (P->box) (void)hipFree(P->box);
-            if (P->idf) (void)hipFree(P->idf);
-            P->box = nullptr;
-            P->idf = nullptr;
-            P->cap_m = 0;
-            int64_t c1 = 0, c2 = 0;
-            if ((e = grow(P->box, c1, need_m)) != hipSuccess ||
-                (e = grow(P->idf, c2, c1)) != hipSuccess)
-                return fail(from_hip(e));
-            P->cap_m = c1;
-        }
+        if ((e = part_prepare(*P, n, need_m1, need_m)) != hipSuccess) return fail(from_hip(e));
         if ((e = run_partition(*P, (const float4*)rects, n, ds->w.num_cus, s)) != hipSuccess) {
             set_err("partition launch", e);
             return fail(from_hip(e));
@@ -377,6 +463,88 @@ sj_status sj_partition(const float* rects, int64_t n, const sj_grid* g, sj_part*
 sj_status sj_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
                   int64_t* n_pairs, void* stream) {
     return do_join(R, S, out, capacity, n_pairs, false, (hipStream_t)stream);
+}
+
+sj_status sj_tune(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
+                  int32_t reps, sj_tuning* best, void* stream) {
+    if (!R || !S || capacity < 0 || reps < 1 || (capacity > 0 && !out)) return SJ_ERR_ARG;
+    if (!same_grid(R->grid, S->grid)) return SJ_ERR_GRID_MISMATCH;
+    if (R->grid.flags & SJ_PLAIN) return SJ_ERR_ARG;
+    const bool count_only = (out == nullptr);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SJ_ERR_DEVICE;
+    const int blocks[] = {64, 128, 256, 512};
+    const int taus[] = {128, 256, 1024};
+    sj_tuning win{};
+    win.ms = -1.0;
+    sj_status rs = SJ_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tune.erase(tune_key(R->device, R->grid, R->m, S->m, count_only));
+    }
+    for (int blk : blocks) {
+        const int E = lds_unit_entries(blk);
+        for (int sc : {E / 4, E / 2}) {
+            for (int mc : {1024, 2048}) {
+                for (int tau : taus) {
+                    if (R->grid.split_tau != 0 && tau != taus[0]) continue;  // fixed by the grid
+                    sj_tuning t{blk, sc, mc, R->grid.split_tau != 0 ? 0 : tau, 0.0};
+                    {
+                        std::lock_guard<std::mutex> lk(g_mu);
+                        g_tune[tune_key(R->device, R->grid, R->m, S->m, count_only)] = t;
+                    }
+                    int64_t np = 0;
+                    float ms = 0.f, tot = 0.f;
+                    sj_status st = do_join(R, S, out, capacity, &np, count_only, s);  // warm-up
+                    for (int r = 0; r < reps && (st == SJ_OK || st == SJ_ERR_CAPACITY); ++r) {
+                        if (hipEventRecord(e0, s) != hipSuccess) st = SJ_ERR_DEVICE;
+                        if (st != SJ_ERR_DEVICE)
+                            st = do_join(R, S, out, capacity, &np, count_only, s);
+                        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                            st = SJ_ERR_DEVICE;
+                        tot += ms;
+                    }
+                    if (st != SJ_OK && st != SJ_ERR_CAPACITY) {
+                        rs = st;
+                        break;
+                    }
+                    t.ms = tot / reps;
+                    if (win.ms < 0 || t.ms < win.ms) win = t;
+                }
+                if (rs != SJ_OK) break;
+            }
+            if (rs != SJ_OK) break;
+        }
+        if (rs != SJ_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_mu);
+    const TuneKey key = tune_key(R->device, R->grid, R->m, S->m, count_only);
+    if (rs != SJ_OK) {
+        g_tune.erase(key);
+        return rs;
+    }
+    g_tune[key] = win;
+    if (best) *best = win;
+    return SJ_OK;
+}
+
+sj_status sj_tune_set(const sj_part* R, const sj_part* S, int32_t count_only,
+                      const sj_tuning* t) {
+    if (!R || !S || !t) return SJ_ERR_ARG;
+    if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512) return SJ_ERR_ARG;
+    if (t->small_cap < 2 || t->med_cap < 2 || t->split_tau < 0) return SJ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune[tune_key(R->device, R->grid, R->m, S->m, count_only != 0)] = *t;
+    return SJ_OK;
+}
+
+void sj_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune.clear();
 }
 
 sj_status sj_join_count(const sj_part* R, const sj_part* S, int64_t* n_pairs, void* stream) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/sj.h"
 
 namespace sj {
@@ -180,5 +182,16 @@ hipError_t join_stats(const JoinWork& w, bool single, sj_join_stats* out);
 int scratch_regions();
 int scratch_chunk_pairs();
 int scratch_totals();
+
+// Helpers of the API layer (sj_api.hip) used by the batch driver.
+std::mutex& api_mutex();
+void api_set_error(const char* msg);
+sj_status api_workspace(int dev, JoinWork** w, int* num_cus);
+sj_status api_resolve_grid(const sj_grid* g, sj_grid& out, GridDev& gd);
+JoinParams api_join_params(const sj_grid& g, bool count_only);
+sj_status api_join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_t mS,
+                           int64_t capacity);
+hipError_t api_part_prepare(Part& P, int64_t n, int64_t need_m1, int64_t need_m);
+bool prof_pause(bool pause);  // prof.hip: suspend event brackets (graph capture)
 
 }  // namespace sj

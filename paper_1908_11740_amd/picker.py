@@ -73,17 +73,23 @@ def sized_instance(i, scale=1.0, kind="picker"):
     pu = sp.n_r * sp.n_s * scale * scale * (2 * me) ** 2
     if pu > P_UNIFORM_CAP:
         scale *= np.sqrt(P_UNIFORM_CAP / pu)
-    R, S, sp = instance(i, scale, kind)
-    _, e = sj.features(R, S)
-    k = sj.rule_k(e)
-    PR, PS = sj.partition(R, k), sj.partition(S, k)
-    p = sj.join_count(PR, PS)
-    PR.free()
-    PS.free()
-    if p > P_CAP:
+    for it in range(6):
+        R, S, sp = instance(i, scale, kind)
+        _, e = sj.features(R, S)
+        k = sj.rule_k(e)
+        PR, PS = sj.partition(R, k), sj.partition(S, k)
+        try:
+            p = sj.join_count(PR, PS)
+        except sj.SjError as err:  # beyond 2^31 pairs
+            if err.status != sj.SJ_ERR_TOO_LARGE:
+                raise
+            p = 2.0 ** 33
+        PR.free()
+        PS.free()
+        if p <= P_CAP or it == 5:
+            break
         del R, S
         scale *= np.sqrt(P_CAP / p)
-        R, S, sp = instance(i, scale, kind)
     return R, S, sp, scale
 
 

@@ -47,6 +47,12 @@ class Choice(ctypes.Structure):
                 ("used_learned", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("small_cap", ctypes.c_int32),
+                ("med_cap", ctypes.c_int32), ("split_tau", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
 class JoinStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in (
         "n_pairs", "small_tiles", "small_units", "medium_tiles", "dense_tiles", "dense_units",
@@ -92,6 +98,21 @@ def lib():
         L.sj_part_stats.restype = ctypes.c_int
         L.sj_last_join_stats.argtypes = [ctypes.POINTER(JoinStats)]
         L.sj_last_join_stats.restype = ctypes.c_int
+        L.sj_tune.argtypes = [vp, vp, vp, i64, ctypes.c_int32, ctypes.POINTER(Tuning), vp]
+        L.sj_tune.restype = ctypes.c_int
+        L.sj_tune_set.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(Tuning)]
+        L.sj_tune_set.restype = ctypes.c_int
+        L.sj_tune_clear.argtypes = []
+        L.sj_tune_clear.restype = None
+        L.sj_batch_create.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                      ctypes.POINTER(vp), vp]
+        L.sj_batch_run.argtypes = [vp, vp, vp]
+        L.sj_batch_info.argtypes = [vp, vp, vp]
+        L.sj_batch_free.argtypes = [vp]
+        L.sj_batch_free.restype = None
+        L.sj_batch_join.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        for f in ("sj_batch_create", "sj_batch_run", "sj_batch_info", "sj_batch_join"):
+            getattr(L, f).restype = ctypes.c_int
         L.sj_generate.argtypes = [vp, i64, vp, vp, vp, ctypes.c_int32, f32, ctypes.c_int32, f32,
                                   f32, ctypes.c_uint64, ctypes.c_uint32, vp]
         L.sj_generate.restype = ctypes.c_int
@@ -247,6 +268,26 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else None)
 
 
+def tune(R, S, out=None, reps=2, stream=None):
+    """sj_tune: time every candidate schedule for (R, S), cache and return the
+    fastest as a dict.  out: (cap, 2) int32 device tensor, or None (count-only)."""
+    t = Tuning()
+    cap = 0 if out is None else out.shape[0]
+    _check(lib().sj_tune(R.handle, S.handle, _ptr(out), cap, int(reps), ctypes.byref(t),
+                         _stream(stream)), "sj_tune")
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+
+def tune_set(R, S, block, small_cap, med_cap, split_tau=0, count_only=False):
+    t = Tuning(block, small_cap, med_cap, split_tau, 0.0)
+    _check(lib().sj_tune_set(R.handle, S.handle, 1 if count_only else 0, ctypes.byref(t)),
+           "sj_tune_set")
+
+
+def tune_clear():
+    lib().sj_tune_clear()
+
+
 def last_join_stats():
     """Work statistics of the last join on the current device (dict)."""
     st = JoinStats()
@@ -276,6 +317,78 @@ def generate(n, mu=None, sigma=None, weights=None, background=1.0, extent="logno
                              float(background), mode, float(ext_a), float(ext_b),
                              int(seed) & (2**64 - 1), int(side), _stream(stream)), "sj_generate")
     return out
+
+
+class Batch:
+    """Many joins recorded into one hipGraph (sj_batch_create / sj_batch_run).
+
+    pairs: list of (R, S) device tensors.  grids: optional list of (k, split_tau)
+    (0 entries are chosen).  capacities: per-join output slices (None:
+    count-only batch)."""
+
+    def __init__(self, pairs, grids=None, capacities=None, stream=None):
+        import numpy as np
+        n = len(pairs)
+        self.n = n
+        self._keep = [(_rects(r), _rects(s)) for r, s in pairs]
+        P = ctypes.c_void_p * max(n, 1)
+        self._R = P(*[r.data_ptr() if r.numel() else None for r, _ in self._keep])
+        self._S = P(*[s.data_ptr() if s.numel() else None for _, s in self._keep])
+        self._nR = np.array([r.shape[0] for r, _ in self._keep] or [0], np.int64)
+        self._nS = np.array([s.shape[0] for _, s in self._keep] or [0], np.int64)
+        g = (Grid * max(n, 1))()
+        for j in range(n):
+            k, tau = grids[j] if grids is not None else (0, 0)
+            g[j] = make_grid(k, tau)
+        self._g = g
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if capacities is None:
+            self.out = None
+            self.offsets = None
+            out_p, off_p = None, None
+        else:
+            self.offsets = np.concatenate([[0], np.cumsum(capacities)]).astype(np.int64)
+            self.out = torch.empty((int(self.offsets[-1]) + 1, 2), dtype=torch.int32, device=dev)
+            out_p = ctypes.c_void_p(self.out.data_ptr())
+            off_p = self.offsets.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(lib().sj_batch_create(n, self._R, self._nR.ctypes.data_as(ctypes.c_void_p),
+                                     self._S, self._nS.ctypes.data_as(ctypes.c_void_p), g,
+                                     out_p, off_p, ctypes.byref(h), _stream(stream)),
+               "sj_batch_create")
+        self._h = h.value
+
+    def run(self, stream=None):
+        """Replay; returns (status, n_pairs array)."""
+        import numpy as np
+        n = np.zeros(max(self.n, 1), np.int64)
+        s = lib().sj_batch_run(self._h, n.ctypes.data_as(ctypes.c_void_p), _stream(stream))
+        if s not in (SJ_OK, SJ_ERR_CAPACITY):
+            raise SjError(s, "sj_batch_run")
+        return s, n[:self.n]
+
+    def grids(self):
+        import numpy as np
+        k = np.zeros(max(self.n, 1), np.int32)
+        t = np.zeros(max(self.n, 1), np.int32)
+        _check(lib().sj_batch_info(self._h, k.ctypes.data_as(ctypes.c_void_p),
+                                   t.ctypes.data_as(ctypes.c_void_p)), "sj_batch_info")
+        return k[:self.n], t[:self.n]
+
+    def pairs(self, j, n):
+        o = int(self.offsets[j])
+        return self.out[o:o + int(n)]
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().sj_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def rule_k(mean_extent):

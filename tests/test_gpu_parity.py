@@ -51,6 +51,14 @@ def test_small_case_every_grid(small, K, sched):
     assert np.array_equal(gpu_join(R, S, K, **SCHEDULES[sched]), ref)
 
 
+@pytest.mark.parametrize("sched", sorted(SCHEDULES))
+def test_golden_two_by_two(sched):
+    from golden.load import load
+    R, S, pairs, _ = load("two_by_two.txt")
+    for K in (1, 2, 3, 64):
+        assert np.array_equal(gpu_join(R, S, K, **SCHEDULES[sched]), pairs), K
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_adversarial(seed):
     from test_oracle import adversarial

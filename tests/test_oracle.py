@@ -284,3 +284,22 @@ def test_partition_membership_exact(K):
             want = sorted(i for i in range(len(A))
                           if covers(A[i, 0], A[i, 2], tx) and covers(A[i, 1], A[i, 3], ty))
             assert sorted(ids[off[T]:off[T + 1]].tolist()) == want
+
+
+# ----------------------------------------------------------------------------
+# Hand-derived golden fixture (tests/golden/two_by_two.txt)
+# ----------------------------------------------------------------------------
+def test_golden_two_by_two():
+    from golden.load import load
+    R, S, pairs, tiles = load("two_by_two.txt")
+    assert np.array_equal(oracle.bruteforce(R, S), pairs)
+    assert np.array_equal(oracle.sweep(R, S), pairs)
+    for K in (1, 2, 3, 4, 7, 64):
+        assert np.array_equal(oracle.pbsm(R, S, K), pairs), K
+    # at K = 2 each pair is reported by exactly the tile listed in the fixture:
+    # joining R with only the rectangles of one tile's membership reproduces it
+    offR, idR = oracle.partition_ids(R, 2)
+    offS, idS = oracle.partition_ids(S, 2)
+    for (r, s), (tx, ty) in zip(pairs, tiles):
+        t = ty * 2 + tx
+        assert r in idR[offR[t]:offR[t + 1]] and s in idS[offS[t]:offS[t + 1]]
