@@ -810,15 +810,21 @@ constexpr int kWNT = 256;               // threads per workgroup (4 independent 
 constexpr int kWQ = 4;                  // entries per lane
 constexpr int kWE = kWave * kWQ;        // entries per wave unit
 constexpr int kWTC = kWE / 2 + 1;       // tiles per wave unit (each has >= 2 entries)
-constexpr int kWBuf = 128;              // staged pairs per wave
+constexpr int kWBuf = 96;               // staged pairs per wave (>= 64 + one flush margin)
 
+struct WaveTable {                      // one unit's local tile table and entry -> tile map
+    uint16_t rl[kWTC + 1], sl[kWTC + 1];  // local start (prefix) of each tile's R / S segment
+    uint16_t tk[kWE];                     // local tile of each entry, then scan starts
+};
+
+// 10,048 bytes: four waves of a workgroup and four workgroups fit one CU
 struct WaveLds {
     float4 bx[kWE];                     // sorted boxes (R part, then S part)
     uint32_t id[kWE];                   // sorted id words
     uint32_t key[kWE + 8];              // sort keys, then candidate-range prefix
-    uint32_t rg[kWTC + 1], rl[kWTC + 1], sg[kWTC + 1], sl[kWTC + 1];
-    unsigned long long wbuf[kWBuf];     // pair staging (writing pass)
-    uint16_t tk[kWE];                   // local tile of each entry, then scan starts
+    uint32_t rg[kWTC + 1], sg[kWTC + 1];  // global segment starts (staging only)
+    WaveTable tab[2];                   // the unit being swept and the next one
+    unsigned long long wbuf[kWBuf];     // pair staging
 };
 
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
@@ -839,53 +845,84 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t v, int lane) {
     return v;
 }
 
-template <int MODE>
-__device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, false>& sk) {
+// A unit staged for the sweep: its table in LDS (WaveLds::tab[buffer]) and
+// its entries in flight into registers.  The kernel stages unit u + 1 (and
+// loads the table of u + 2) before it sweeps unit u, so both dependent
+// global round trips of a unit overlap the previous unit's work.
+static_assert(sizeof(WaveLds) * 4 <= 40960, "four wave-unit workgroups per CU");
+
+struct WaveStage {
+    int c, NR, NS;
+    float4 pb[kWQ];
+    uint32_t pi[kWQ], pg[kWQ];
+};
+
+// table registers: lane l holds tiles 2l and 2l+1 of the unit
+struct WaveTabRegs {
+    uint4 t0, t1;
+    int c;
+};
+
+__device__ __forceinline__ WaveTabRegs load_wave_table(const Args& a, uint2 ud) {
     const int lane = lane_id();
-    const uint2 ud = a.units[u];
-    const int c = (int)ud.y;
+    WaveTabRegs r;
+    r.c = (int)ud.y;
+    r.t0 = make_uint4(0, 0, 0, 0);
+    r.t1 = make_uint4(0, 0, 0, 0);
+    if (2 * lane < r.c) r.t0 = a.tinfo[ud.x + 2 * lane];
+    if (2 * lane + 1 < r.c) r.t1 = a.tinfo[ud.x + 2 * lane + 1];
+    return r;
+}
+
+// Write the table of a unit to LDS, map entries to tiles and issue the
+// gather of the unit's entries.  Returns false (status flagged) if the unit
+// breaks the classification's invariants.
+__device__ bool stage_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const WaveTabRegs& tr,
+                                WaveStage& st) {
+    const int lane = lane_id();
+    const int c = tr.c;
+    st.c = c;
+    st.NR = st.NS = 0;
     if (c > kWTC) {  // cannot happen for units built by k_classify
         if (lane == 0) atomicOr(&a.st->flags, kStatInternal);
-        return;
+        return false;
     }
-    // 1. tile table: lane l holds tiles 2l and 2l+1
-    uint4 t0 = make_uint4(0, 0, 0, 0), t1 = make_uint4(0, 0, 0, 0);
-    if (2 * lane < c) t0 = a.tinfo[ud.x + 2 * lane];
-    if (2 * lane + 1 < c) t1 = a.tinfo[ud.x + 2 * lane + 1];
-    const uint32_t ir = wave_incl_sum(t0.y + t1.y, lane);
-    const uint32_t is = wave_incl_sum(t0.w + t1.w, lane);
+    const uint32_t ir = wave_incl_sum(tr.t0.y + tr.t1.y, lane);
+    const uint32_t is = wave_incl_sum(tr.t0.w + tr.t1.w, lane);
     const int NR = __shfl((int)ir, kWave - 1, kWave), NS = __shfl((int)is, kWave - 1, kWave);
     const int NE = NR + NS;
     if (NE > kWE) {
         if (lane == 0) atomicOr(&a.st->flags, kStatInternal);
-        return;
+        return false;
     }
+    st.NR = NR;
+    st.NS = NS;
     {
-        const uint32_t r0 = ir - t0.y - t1.y, s0 = is - t0.w - t1.w;
+        const uint32_t r0 = ir - tr.t0.y - tr.t1.y, s0 = is - tr.t0.w - tr.t1.w;
         if (2 * lane < c) {
-            W.rg[2 * lane] = t0.x;
-            W.sg[2 * lane] = t0.z;
-            W.rl[2 * lane] = r0;
-            W.sl[2 * lane] = s0;
+            W.rg[2 * lane] = tr.t0.x;
+            W.sg[2 * lane] = tr.t0.z;
+            T.rl[2 * lane] = (uint16_t)r0;
+            T.sl[2 * lane] = (uint16_t)s0;
         }
         if (2 * lane + 1 < c) {
-            W.rg[2 * lane + 1] = t1.x;
-            W.sg[2 * lane + 1] = t1.z;
-            W.rl[2 * lane + 1] = r0 + t0.y;
-            W.sl[2 * lane + 1] = s0 + t0.w;
+            W.rg[2 * lane + 1] = tr.t1.x;
+            W.sg[2 * lane + 1] = tr.t1.z;
+            T.rl[2 * lane + 1] = (uint16_t)(r0 + tr.t0.y);
+            T.sl[2 * lane + 1] = (uint16_t)(s0 + tr.t0.w);
         }
         if (lane == 0) {
-            W.rl[c] = (uint32_t)NR;
-            W.sl[c] = (uint32_t)NS;
+            T.rl[c] = (uint16_t)NR;
+            T.sl[c] = (uint16_t)NS;
         }
     }
-    // 1b. local tile of every entry: head marks (R: k, S: c + k) + max-scan
+    // local tile of every entry: head marks (R: k, S: c + k) + max-scan
 #pragma unroll
-    for (int q = 0; q < kWQ; ++q) W.tk[lane * kWQ + q] = 0;
+    for (int q = 0; q < kWQ; ++q) T.tk[lane * kWQ + q] = 0;
     wave_fence();
     for (int k = lane; k < c; k += kWave) {
-        if (W.rl[k + 1] > W.rl[k]) W.tk[W.rl[k]] = (uint16_t)k;
-        if (W.sl[k + 1] > W.sl[k]) W.tk[NR + W.sl[k]] = (uint16_t)(c + k);
+        if (T.rl[k + 1] > T.rl[k]) T.tk[T.rl[k]] = (uint16_t)k;
+        if (T.sl[k + 1] > T.sl[k]) T.tk[NR + T.sl[k]] = (uint16_t)(c + k);
     }
     wave_fence();
     {
@@ -893,7 +930,7 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
         uint32_t run = 0;
 #pragma unroll
         for (int q = 0; q < kWQ; ++q) {
-            const uint32_t x = W.tk[lane * kWQ + q];
+            const uint32_t x = T.tk[lane * kWQ + q];
             run = x > run ? x : run;
             v[q] = run;
         }
@@ -905,41 +942,51 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
         for (int q = 0; q < kWQ; ++q) {
             const int i = lane * kWQ + q;
             const uint32_t t = v[q] > ex ? v[q] : ex;
-            if (i < NE) W.tk[i] = (uint16_t)(i < NR ? t : t - (uint32_t)c);
+            if (i < NE) T.tk[i] = (uint16_t)(i < NR ? t : t - (uint32_t)c);
         }
     }
     wave_fence();
-    // 2. load the entries (coalesced within each tile segment)
-    float4 pb[kWQ];
-    uint32_t pi[kWQ], pg[kWQ];
+    // issue the gather (coalesced within each tile segment)
 #pragma unroll
     for (int q = 0; q < kWQ; ++q) {
         const int e = lane + q * kWave;
+        st.pg[q] = 0;
         if (e < NE) {
             const bool isR = e < NR;
-            const int k = W.tk[e];
-            const uint32_t g = isR ? W.rg[k] + (uint32_t)e - W.rl[k] : W.sg[k] + (uint32_t)(e - NR) - W.sl[k];
-            pb[q] = isR ? a.boxR[g] : a.boxS[g];
-            pi[q] = isR ? a.idfR[g] : a.idfS[g];
-            pg[q] = g;
+            const int k = T.tk[e];
+            const uint32_t g = isR ? W.rg[k] + (uint32_t)e - T.rl[k] : W.sg[k] + (uint32_t)(e - NR) - T.sl[k];
+            st.pb[q] = isR ? a.boxR[g] : a.boxS[g];
+            st.pi[q] = isR ? a.idfR[g] : a.idfS[g];
+            st.pg[q] = g;
         }
     }
+    return true;
+}
+
+// Sort the staged unit's tile segments by x_l (counting pass: written back
+// sorted) and sweep them: the load-balanced candidate ranges of run_lds_unit
+// with one wavefront and wave-level fences only.
+template <int MODE>
+__device__ void sweep_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const WaveStage& st,
+                                uint32_t u, Sink<MODE, false>& sk) {
+    const int lane = lane_id();
+    const int NR = st.NR, NE = st.NR + st.NS;
 #pragma unroll
     for (int q = 0; q < kWQ; ++q) {
         const int e = lane + q * kWave;
         if (e < NE) {
             if (MODE == kWrite) {  // the counting pass left every slab sorted
-                W.bx[e] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
-                W.id[e] = pi[q];
+                W.bx[e] = make_float4(st.pb[q].x, st.pb[q].y, st.pb[q].z, st.pb[q].w);
+                W.id[e] = st.pi[q];
             } else {
-                W.key[e] = order_key(pb[q].x);
+                W.key[e] = order_key(st.pb[q].x);
             }
         }
     }
     wave_fence();
     if (MODE != kWrite) {
-        // 3. rank sort inside each tile segment; sorted slab to LDS and back
-        //    to global memory
+        // rank sort inside each tile segment; sorted slab to LDS (and back to
+        // global memory when a writing pass follows)
         int pos[kWQ];
 #pragma unroll
         for (int q = 0; q < kWQ; ++q) {
@@ -947,32 +994,34 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
             pos[q] = -1;
             if (e < NE) {
                 const bool isR = e < NR;
-                const int k = W.tk[e];
-                const int lo = isR ? (int)W.rl[k] : NR + (int)W.sl[k];
-                const int hi = isR ? (int)W.rl[k + 1] : NR + (int)W.sl[k + 1];
+                const int k = T.tk[e];
+                const int lo = isR ? (int)T.rl[k] : NR + (int)T.sl[k];
+                const int hi = isR ? (int)T.rl[k + 1] : NR + (int)T.sl[k + 1];
                 pos[q] = lo + seg_rank(W.key, lo, hi, e);
             }
         }
 #pragma unroll
         for (int q = 0; q < kWQ; ++q) {
             if (pos[q] >= 0) {
-                W.bx[pos[q]] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
-                W.id[pos[q]] = pi[q];
+                W.bx[pos[q]] = make_float4(st.pb[q].x, st.pb[q].y, st.pb[q].z, st.pb[q].w);
+                W.id[pos[q]] = st.pi[q];
             }
         }
         wave_fence();
+        if (MODE == kCount && a.writeback) {
 #pragma unroll
-        for (int q = 0; q < kWQ; ++q) {
-            const int e = lane + q * kWave;
-            if (MODE == kCount && a.writeback && e < NE) {
-                const float4 b = W.bx[e];
-                const uint32_t idv = W.id[e];
-                if (e < NR) {
-                    a.boxR[pg[q]] = b;
-                    a.idfR[pg[q]] = idv;
-                } else {
-                    a.boxS[pg[q]] = b;
-                    a.idfS[pg[q]] = idv;
+            for (int q = 0; q < kWQ; ++q) {
+                const int e = lane + q * kWave;
+                if (e < NE) {
+                    const float4 b = W.bx[e];
+                    const uint32_t idv = W.id[e];
+                    if (e < NR) {
+                        a.boxR[st.pg[q]] = b;
+                        a.idfR[st.pg[q]] = idv;
+                    } else {
+                        a.boxS[st.pg[q]] = b;
+                        a.idfS[st.pg[q]] = idv;
+                    }
                 }
             }
         }
@@ -989,11 +1038,11 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
         v[q] = 0;
         jsv[q] = 0;
         if (p < NE) {
-            const int k = W.tk[p];
+            const int k = T.tk[p];
             const float4 b = W.bx[p];
             const bool isR = p < NR;
-            const int lo = isR ? NR + (int)W.sl[k] : (int)W.rl[k];
-            const int hi = isR ? NR + (int)W.sl[k + 1] : (int)W.rl[k + 1];
+            const int lo = isR ? NR + (int)T.sl[k] : (int)T.rl[k];
+            const int hi = isR ? NR + (int)T.sl[k + 1] : (int)T.rl[k + 1];
             const int j0 = search_x(X, lo, hi, b.x, isR);
             const int j1 = search_x(X, j0, hi, b.z, true);
             v[q] = (uint32_t)(j1 - j0);
@@ -1004,7 +1053,7 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
     wave_fence();
     // 4b. exclusive prefix of the range lengths
     const uint32_t incs = wave_incl_sum(sum, lane);
-    const uint32_t T = __shfl(incs, kWave - 1, kWave);
+    const uint32_t Tc = __shfl(incs, kWave - 1, kWave);
     {
         uint32_t ex = incs - sum;
 #pragma unroll
@@ -1012,18 +1061,18 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
             const int p = lane * kWQ + q;
             if (p < NE) {
                 cnt[p] = ex;
-                W.tk[p] = jsv[q];
+                T.tk[p] = jsv[q];
             }
             ex += v[q];
         }
-        if (lane == 0) cnt[NE] = T;
+        if (lane == 0) cnt[NE] = Tc;
     }
     wave_fence();
     // 4c. chunks of kChunkC consecutive candidates per lane
     sk.begin(a, u);
-    for (uint32_t it = 0; it * (uint32_t)(kWave * kChunkC) < T; ++it) {
+    for (uint32_t it = 0; it * (uint32_t)(kWave * kChunkC) < Tc; ++it) {
         const uint32_t c0 = it * (uint32_t)(kWave * kChunkC) + (uint32_t)lane * kChunkC;
-        const uint32_t cs = c0 < T ? c0 : T - 1u;
+        const uint32_t cs = c0 < Tc ? c0 : Tc - 1u;
         int lo = 0, hi = NE;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -1037,7 +1086,7 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
 #pragma unroll
         for (int i = 0; i < kChunkC; ++i) {
             const uint32_t cc = c0 + (uint32_t)i;
-            const bool valid = cc < T;
+            const bool valid = cc < Tc;
             if (valid && cc >= pend) {
                 do {
                     ++p;
@@ -1049,7 +1098,7 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
             bool hit[1] = {false};
             uint32_t er[1] = {0}, es[1] = {0};
             if (valid) {
-                const int j = (int)W.tk[p] + (int)(cc - cnt[p]);
+                const int j = (int)T.tk[p] + (int)(cc - cnt[p]);
                 const float4 q4 = W.bx[j];
                 const uint32_t qid = W.id[j];
                 hit[0] = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
@@ -1065,7 +1114,7 @@ __device__ void run_wave_unit(const Args& a, WaveLds& W, uint32_t u, Sink<MODE, 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kWNT) void k_wave_units(Args a) {
+__global__ __launch_bounds__(kWNT, 4) void k_wave_units(Args a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     WaveLds& W = ((WaveLds*)smem)[threadIdx.x / kWave];
     const uint32_t nu = min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
@@ -1076,7 +1125,31 @@ __global__ __launch_bounds__(kWNT) void k_wave_units(Args a) {
     sk.s_acc = nullptr;
     sk.bufcap = kWBuf;
     sk.init(wg);
-    for (uint32_t u = wg; u < nu; u += waves) run_wave_unit<MODE>(a, W, u, sk);
+    // three-stage pipeline: table of u + 2w in registers, unit u + w staged
+    // (table in LDS, entries in flight), unit u swept
+    WaveStage cur, nxt;
+    WaveTabRegs tr{};
+    int buf = 0;
+    bool ok = true;
+    if (wg < nu) {
+        const WaveTabRegs t0 = load_wave_table(a, a.units[wg]);
+        ok = stage_wave_unit(a, W, W.tab[0], t0, cur);
+        if (wg + waves < nu) tr = load_wave_table(a, a.units[wg + waves]);
+    }
+    for (uint32_t u = wg; ok && u < nu; u += waves) {
+        const uint32_t un = u + waves;
+        bool have_next = false;
+        if (un < nu) {
+            ok = stage_wave_unit(a, W, W.tab[buf ^ 1], tr, nxt);
+            have_next = true;
+            if (un + waves < nu) tr = load_wave_table(a, a.units[un + waves]);
+        }
+        sweep_wave_unit<MODE>(a, W, W.tab[buf], cur, u, sk);
+        if (have_next) {
+            cur = nxt;
+            buf ^= 1;
+        }
+    }
     sk.finish(a, wg);
 }
 
@@ -1635,8 +1708,11 @@ hipError_t join_pass(const Args& a0, const JoinParams& p, const JoinWork& w, hip
             a.cls = 1;
             ProfRange pr(mode_tag(MODE, "k_lds_medium_count", "k_lds_medium_write",
                                   "k_lds_medium_single"), s);
-            e = launch_units<kMedNT, kMedE / kMedNT, true, MODE>(
-                a, std::min<int64_t>(p.med_bound, w.cap_med), w.num_cus, s);
+            // medium tiles up to 1024 entries: a half-size slab, twice the
+            // workgroups per CU
+            const int64_t mb = std::min<int64_t>(p.med_bound, w.cap_med);
+            e = p.med_cap <= 1024 ? launch_units<256, 4, true, MODE>(a, mb, w.num_cus, s)
+                                  : launch_units<kMedNT, kMedE / kMedNT, true, MODE>(a, mb, w.num_cus, s);
         }
     }
     if (e != hipSuccess) return e;
