@@ -89,6 +89,35 @@ def kernel_bytes(name, w):
     return table.get(name)
 
 
+def source_digest():
+    """Hash of the HIP sources (the kernels a stored traffic figure belongs to)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1908_11740_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    none for this workload or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    data = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if data.get("source_digest") != source_digest():
+        return None
+    k = data["kernels"].get(kernel)
+    return None if k is None else int(k["fetch_bytes"] + k["write_bytes"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -206,7 +235,8 @@ def main():
     roofline = {"kernel": dom, "bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s",
                 "frac": None if dk["gbs"] is None else round(dk["gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_ms": dk["avg_ms"], "alg_bytes_per_launch": dk["alg_bytes"]}
+                "traffic": measured_traffic(args.workload, dom) if main_mode == "tuned" else None,
+                "avg_ms": dk["avg_ms"], "alg_bytes_per_launch": dk["alg_bytes"]}
     b_step = 32 * (nR + nS) + 40 * (r["mR"] + r["mS"]) + 8 * P + 32 * C
     ms = r["ms"]
     verified = None

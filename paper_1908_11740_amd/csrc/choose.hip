@@ -29,7 +29,7 @@ namespace sj {
 
 int64_t mlp_params(int D);
 hipError_t mlp_forward(const float* P, int D, const float* X, const float* mu, const float* sd,
-                       int B, float* Y, float* act, hipStream_t s);
+                       int B, float* Y, float* act, hipStream_t s, float* h1_scratch);
 
 namespace {
 
@@ -210,6 +210,7 @@ struct ChooseState {
     ChooseOut* out = nullptr;
     ChooseOut* host = nullptr;   // pinned
     float* y = nullptr;          // [2]
+    float* h1 = nullptr;         // [64] hidden layer of the picker
     float* picker = nullptr;     // mu | sd | ystat | params
     int64_t picker_n = 0;
     bool loaded = false;
@@ -223,7 +224,7 @@ sj_status state_for(int dev, ChooseState** out) {
     if (!c.host) {
         if (alloc(c.feat, kFeatDim) != hipSuccess || alloc(c.part, 2 * kFeatBlocks * 4) != hipSuccess ||
             alloc(c.hist, 2 * kHist * kHist + 1) != hipSuccess || alloc(c.out, 1) != hipSuccess ||
-            alloc(c.y, 2) != hipSuccess)
+            alloc(c.y, 2) != hipSuccess || alloc(c.h1, 64) != hipSuccess)
             return SJ_ERR_OOM;
         if (hipHostMalloc((void**)&c.host, sizeof(ChooseOut), hipHostMallocDefault) != hipSuccess) {
             c.host = nullptr;
@@ -369,7 +370,7 @@ sj_status sj_choose_grid(const float* R, int64_t nR, const float* S, int64_t nS,
         const float* sd = mu + kFeatDim;
         const float* ystat = sd + kFeatDim;
         const float* P = ystat + 4;
-        if (mlp_forward(P, kFeatDim, c->feat, mu, sd, 1, c->y, nullptr, s) != hipSuccess)
+        if (mlp_forward(P, kFeatDim, c->feat, mu, sd, 1, c->y, nullptr, s, c->h1) != hipSuccess)
             return SJ_ERR_DEVICE;
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(1), 0, s, c->y, ystat, c->out);
     }

@@ -65,10 +65,8 @@ constexpr int kDenseNT = 256;
 struct Args {
     const uint32_t* offR;
     const uint32_t* offS;
-    float4* boxR;     // tile slabs; the counting pass writes each slab back sorted
-    uint32_t* idfR;
-    float4* boxS;
-    uint32_t* idfS;
+    Entry* entR;      // tile slabs; the counting pass writes each slab back sorted
+    Entry* entS;
     int64_t C;        // blocked tiles
     int small_cap;    // small tiles: nr + ns <= small_cap
     int unit_cap;     // entries per small unit (target)
@@ -596,8 +594,9 @@ __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const Til
             const int k = L.tk[e];
             const uint32_t g = isR ? L.rg[k] + (uint32_t)e - L.rl[k]
                                    : L.sg[k] + (uint32_t)(e - NR) - L.sl[k];
-            pb[q] = isR ? a.boxR[g] : a.boxS[g];
-            pi[q] = isR ? a.idfR[g] : a.idfS[g];
+            const Entry* en = isR ? a.entR + g : a.entS + g;
+            pb[q] = en->b;
+            pi[q] = en->m.x;
             pg[q] = g;
             if (MODE == kWrite) {  // the counting pass left every slab sorted
                 L.bx[e] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
@@ -690,11 +689,11 @@ __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const Til
             if (MODE == kCount && a.writeback && e < NE) {
                 const float4 b = L.bx[e];
                 if (e < NR) {
-                    a.boxR[pg[q]] = b;
-                    a.idfR[pg[q]] = L.id[e];
+                    a.entR[pg[q]].b = b;
+                    a.entR[pg[q]].m = make_uint4(L.id[e], 0u, 0u, 0u);
                 } else {
-                    a.boxS[pg[q]] = b;
-                    a.idfS[pg[q]] = L.id[e];
+                    a.entS[pg[q]].b = b;
+                    a.entS[pg[q]].m = make_uint4(L.id[e], 0u, 0u, 0u);
                 }
             }
         }
@@ -955,8 +954,9 @@ __device__ bool stage_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const W
             const bool isR = e < NR;
             const int k = T.tk[e];
             const uint32_t g = isR ? W.rg[k] + (uint32_t)e - T.rl[k] : W.sg[k] + (uint32_t)(e - NR) - T.sl[k];
-            st.pb[q] = isR ? a.boxR[g] : a.boxS[g];
-            st.pi[q] = isR ? a.idfR[g] : a.idfS[g];
+            const Entry* en = isR ? a.entR + g : a.entS + g;
+            st.pb[q] = en->b;
+            st.pi[q] = en->m.x;
             st.pg[q] = g;
         }
     }
@@ -1016,11 +1016,11 @@ __device__ void sweep_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const W
                     const float4 b = W.bx[e];
                     const uint32_t idv = W.id[e];
                     if (e < NR) {
-                        a.boxR[st.pg[q]] = b;
-                        a.idfR[st.pg[q]] = idv;
+                        a.entR[st.pg[q]].b = b;
+                        a.entR[st.pg[q]].m = make_uint4(idv, 0u, 0u, 0u);
                     } else {
-                        a.boxS[st.pg[q]] = b;
-                        a.idfS[st.pg[q]] = idv;
+                        a.entS[st.pg[q]].b = b;
+                        a.entS[st.pg[q]].m = make_uint4(idv, 0u, 0u, 0u);
                     }
                 }
             }
@@ -1393,15 +1393,14 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
         const uint32_t src = sideS ? a.offS[dd.x] : a.offR[dd.x];
         const uint32_t L = sideS ? dd.w : dd.z;
         const uint32_t dst = dd.y + (sideS ? dd.z : 0u);
-        const float4* box = sideS ? a.boxS : a.boxR;
-        const uint32_t* idf = sideS ? a.idfS : a.idfR;
+        const Entry* ent = sideS ? a.entS : a.entR;
         const unsigned long long* fin;  // final sorted keys (low 32 bits = position)
         if (L <= (uint32_t)kDenseSortMax) {
             int P = 1;
             while (P < (int)L) P <<= 1;
             for (int i = threadIdx.x; i < P; i += blockDim.x)
                 keys[i] = i < (int)L
-                              ? ((unsigned long long)order_key(box[src + i].x) << 32) | (uint32_t)i
+                              ? ((unsigned long long)order_key(ent[src + i].b.x) << 32) | (uint32_t)i
                               : ~0ull;
             __syncthreads();
             bitonic_lds(keys, P);
@@ -1415,7 +1414,7 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             for (uint32_t c0 = 0; c0 < L; c0 += kDenseSortMax) {
                 const int n = (int)min((uint32_t)kDenseSortMax, L - c0);
                 for (int i = threadIdx.x; i < kDenseSortMax; i += blockDim.x)
-                    keys[i] = i < n ? ((unsigned long long)order_key(box[src + c0 + i].x) << 32) |
+                    keys[i] = i < n ? ((unsigned long long)order_key(ent[src + c0 + i].b.x) << 32) |
                                           (c0 + (uint32_t)i)
                                     : ~0ull;
                 __syncthreads();
@@ -1456,8 +1455,8 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
         }
         for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
             const uint32_t q = (uint32_t)fin[i];
-            a.dbox[dst + i] = box[src + q];
-            a.didf[dst + i] = idf[src + q];
+            a.dbox[dst + i] = ent[src + q].b;
+            a.didf[dst + i] = ent[src + q].m.x;
         }
         __syncthreads();
     }
@@ -1740,10 +1739,8 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     Args a{};
     a.offR = R.off;
     a.offS = S.off;
-    a.boxR = R.box;
-    a.idfR = R.idf;
-    a.boxS = S.box;
-    a.idfS = S.idf;
+    a.entR = R.ent;
+    a.entS = S.ent;
     a.C = p.C;
     a.small_cap = p.small_cap;
     a.unit_cap = p.unit_cap;

@@ -17,6 +17,7 @@ namespace {
 constexpr int kH = 64;   // hidden width
 constexpr int kOut = 2;  // (log2 K, log2 tau), standardised
 constexpr int kMaxD = 4096;
+constexpr int kSmallBatch = 16;  // up to this batch, the spread layer-1 kernel
 
 struct Layout {
     int64_t w1, b1, w2, b2, w3, b3, total;
@@ -83,6 +84,57 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ P, in
     if (act && threadIdx.x < kH) {
         act[(int64_t)b * 2 * kH + threadIdx.x] = h1[threadIdx.x];
         act[(int64_t)b * 2 * kH + kH + threadIdx.x] = h2[threadIdx.x];
+    }
+}
+
+// Small batches (inference): layer 1 spread over one workgroup per
+// (hidden unit, sample), so the 64 x D weight matrix streams through many
+// CUs at once, then layers 2 and 3 per sample.  Each dot product is reduced
+// in a fixed order within its workgroup (deterministic; its rounding may
+// differ from the per-sample kernel's in the last bits).
+__global__ __launch_bounds__(256) void k_mlp_fwd_l1(const float* __restrict__ P, int D,
+                                                    const float* __restrict__ X,
+                                                    const float* __restrict__ mu,
+                                                    const float* __restrict__ sd,
+                                                    float* __restrict__ H1) {
+    __shared__ float red[256 / 64];
+    const int o = blockIdx.x, b = blockIdx.y;
+    const Layout L = layout(D);
+    const float* row = P + L.w1 + (int64_t)o * D;
+    const float* x = X + (int64_t)b * D;
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < D; i += blockDim.x) acc = fmaf(row[i], norm_in(x, mu, sd, i), acc);
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int w = 0; w < 4; ++w) t += red[w];
+        H1[(int64_t)b * kH + o] = fmaxf(t + P[L.b1 + o], 0.f);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_mlp_fwd_l23(const float* __restrict__ P, int D,
+                                                    const float* __restrict__ H1, int B,
+                                                    float* __restrict__ Y, float* __restrict__ act) {
+    __shared__ float h1[kH], h2[kH];
+    const int b = blockIdx.x, o = threadIdx.x;
+    if (b >= B) return;
+    const Layout L = layout(D);
+    h1[o] = H1[(int64_t)b * kH + o];
+    __syncthreads();
+    float acc = P[L.b2 + o];
+    for (int j = 0; j < kH; ++j) acc = fmaf(P[L.w2 + o * kH + j], h1[j], acc);
+    h2[o] = fmaxf(acc, 0.f);
+    __syncthreads();
+    if (o < kOut) {
+        float y = P[L.b3 + o];
+        for (int j = 0; j < kH; ++j) y = fmaf(P[L.w3 + o * kH + j], h2[j], y);
+        Y[(int64_t)b * kOut + o] = y;
+    }
+    if (act) {
+        act[(int64_t)b * 2 * kH + o] = h1[o];
+        act[(int64_t)b * 2 * kH + kH + o] = h2[o];
     }
 }
 
@@ -188,9 +240,16 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, float* __re
 int64_t mlp_params(int D) { return layout(D).total; }
 
 hipError_t mlp_forward(const float* P, int D, const float* X, const float* mu, const float* sd,
-                       int B, float* Y, float* act, hipStream_t s) {
+                       int B, float* Y, float* act, hipStream_t s, float* h1_scratch) {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)B), dim3(256), 0, s, P, D, X, mu, sd, B, Y, act);
+    if (h1_scratch && B <= kSmallBatch) {
+        hipLaunchKernelGGL(k_mlp_fwd_l1, dim3(kH, (unsigned)B), dim3(256), 0, s, P, D, X, mu, sd,
+                           h1_scratch);
+        hipLaunchKernelGGL(k_mlp_fwd_l23, dim3((unsigned)B), dim3(kH), 0, s, P, D, h1_scratch, B, Y,
+                           act);
+    } else {
+        hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)B), dim3(256), 0, s, P, D, X, mu, sd, B, Y, act);
+    }
     return hipGetLastError();
 }
 
@@ -209,7 +268,8 @@ sj_status sj_mlp_forward(const float* params, int32_t d_in, const float* mu, con
                          const float* X, int32_t batch, float* Y, float* act, void* stream) {
     if (d_in < 1 || d_in > kMaxD || batch < 0 || (batch > 0 && (!params || !X || !Y)))
         return SJ_ERR_ARG;
-    return mlp_forward(params, d_in, X, mu, sd, batch, Y, act, (hipStream_t)stream) == hipSuccess
+    return mlp_forward(params, d_in, X, mu, sd, batch, Y, act, (hipStream_t)stream, nullptr) ==
+                   hipSuccess
                ? SJ_OK
                : SJ_ERR_DEVICE;
 }

@@ -101,8 +101,7 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
 __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__ rects, int64_t n,
                                                       GridDev g, Blocking bl, int64_t ch1,
                                                       const uint32_t* __restrict__ o1,
-                                                      float4* __restrict__ e1box,
-                                                      uint32_t* __restrict__ e1id, int64_t cap_m1,
+                                                      Entry* __restrict__ e1, int64_t cap_m1,
                                                       DevStatus* __restrict__ st) {
     extern __shared__ uint32_t cur[];  // [G1]
     if (aborted(st)) return;
@@ -130,8 +129,8 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
                     err |= kStatCapacity;
                     continue;
                 }
-                e1box[slot] = a;
-                e1id[slot] = (uint32_t)i;
+                e1[slot].b = a;
+                e1[slot].m = make_uint4((uint32_t)i, 0u, 0u, 0u);
             }
     }
     if (err) atomicOr(&st->flags, err);
@@ -229,7 +228,7 @@ __device__ __forceinline__ Local local_range(const Cells& c, const Chunk& k, con
     return l;
 }
 
-__global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e1box,
+__global__ __launch_bounds__(kL1NT) void k_l2_count(const Entry* __restrict__ e1,
                                                     const uint32_t* __restrict__ o1, int64_t nb1,
                                                     const uint32_t* __restrict__ cp,
                                                     const uint32_t* __restrict__ chunk_cell,
@@ -245,7 +244,7 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e
         for (int i = threadIdx.x; i < B2; i += blockDim.x) hist[i] = 0u;
         __syncthreads();
         for (uint32_t e = k.e0 + threadIdx.x; e < k.e1; e += blockDim.x) {
-            const Local l = local_range(cells_of(e1box[e], g), k, bl);
+            const Local l = local_range(cells_of(e1[e].b, g), k, bl);
             for (int y = l.y0; y <= l.y1; ++y)
                 for (int x = l.x0; x <= l.x1; ++x) atomicAdd(&hist[y * bl.B + x], 1u);
         }
@@ -256,15 +255,13 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e
     }
 }
 
-__global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__ e1box,
-                                                      const uint32_t* __restrict__ e1id,
+__global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ e1,
                                                       const uint32_t* __restrict__ o1, int64_t nb1,
                                                       const uint32_t* __restrict__ cp,
                                                       const uint32_t* __restrict__ chunk_cell,
                                                       GridDev g, Blocking bl,
                                                       const uint32_t* __restrict__ o2,
-                                                      float4* __restrict__ box,
-                                                      uint32_t* __restrict__ idf, int64_t cap_m,
+                                                      Entry* __restrict__ ent, int64_t cap_m,
                                                       DevStatus* __restrict__ st) {
     extern __shared__ uint32_t cur[];  // [B*B]
     if (aborted(st)) return;
@@ -277,8 +274,8 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__
             cur[t] = o2[k.h2base + (uint32_t)t * k.nch + k.c];
         __syncthreads();
         for (uint32_t e = k.e0 + threadIdx.x; e < k.e1; e += blockDim.x) {
-            const float4 a = e1box[e];
-            const uint32_t id = e1id[e];
+            const float4 a = e1[e].b;
+            const uint32_t id = e1[e].m.x;
             const Cells c = cells_of(a, g);
             const Local l = local_range(c, k, bl);
             const int bx = k.gx * bl.B, by = k.gy * bl.B;
@@ -290,8 +287,8 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__
                         err |= kStatCapacity;
                         continue;
                     }
-                    box[slot] = a;
-                    idf[slot] = id | fy | ((bx + x == c.cx0) ? kBx : 0u);
+                    ent[slot].b = a;
+                    ent[slot].m = make_uint4(id | fy | ((bx + x == c.cx0) ? kBx : 0u), 0u, 0u, 0u);
                 }
             }
         }
@@ -531,17 +528,17 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     if (n > 0) {
         ProfRange pr("k_l1_scatter", s);
         hipLaunchKernelGGL(k_l1_scatter, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
-                           P.gd, bl, ch1, P.h1, P.e1box, P.e1id, P.cap_m1, P.st);
+                           P.gd, bl, ch1, P.h1, P.e1, P.cap_m1, P.st);
     }
     {
         ProfRange pr("k_plan", s);
         hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, P.h1, nb1, bl, P.cp, P.chunk_cell,
                            P.cap_chunks, P.st);
     }
-    const int nb2 = num_cus * 2;
+    const int nb2 = num_cus * 4;  // 32 waves per CU: the scatter is latency-bound
     {
         ProfRange pr("k_l2_count", s);
-        hipLaunchKernelGGL(k_l2_count, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1box, P.h1, nb1,
+        hipLaunchKernelGGL(k_l2_count, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1, P.h1, nb1,
                            P.cp, P.chunk_cell, P.gd, bl, P.h2, P.st);
     }
     {
@@ -550,8 +547,8 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     }
     {
         ProfRange pr("k_l2_scatter", s);
-        hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1box, P.e1id,
-                           P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.box, P.idf, P.cap_m,
+        hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1,
+                           P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m,
                            P.st);
     }
     {

@@ -271,30 +271,8 @@ hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
                   scan_block_sums_needed(std::max(G1 * nb1, B2 * P->cap_chunks)))) !=
             hipSuccess)
         return e;
-    if (need_m1 > P->cap_m1 || !P->e1box) {
-        if (P->e1box) (void)hipFree(P->e1box);
-        if (P->e1id) (void)hipFree(P->e1id);
-        P->e1box = nullptr;
-        P->e1id = nullptr;
-        P->cap_m1 = 0;
-        int64_t c1 = 0, c2 = 0;
-        if ((e = grow(P->e1box, c1, need_m1)) != hipSuccess ||
-            (e = grow(P->e1id, c2, c1)) != hipSuccess)
-            return e;
-        P->cap_m1 = c1;
-    }
-    if (need_m > P->cap_m || !P->box) {
-        if (P->box) (void)hipFree(P->box);
-        if (P->idf) (void)hipFree(P->idf);
-        P->box = nullptr;
-        P->idf = nullptr;
-        P->cap_m = 0;
-        int64_t c1 = 0, c2 = 0;
-        if ((e = grow(P->box, c1, need_m)) != hipSuccess ||
-            (e = grow(P->idf, c2, c1)) != hipSuccess)
-            return e;
-        P->cap_m = c1;
-    }
+    if ((e = grow(P->e1, P->cap_m1, need_m1)) != hipSuccess) return e;
+    if ((e = grow(P->ent, P->cap_m, need_m)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -579,11 +557,11 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
     const int64_t B2 = (int64_t)P->bl.B * P->bl.B;
     const int64_t Cb = (int64_t)P->bl.G * P->bl.G * B2;
     std::vector<uint32_t> off((size_t)Cb + 1);
-    std::vector<uint32_t> raw((size_t)std::max<int64_t>(P->m, 1));
+    std::vector<Entry> raw((size_t)std::max<int64_t>(P->m, 1));
     if (hipMemcpy(off.data(), P->off, (size_t)(Cb + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
         return SJ_ERR_DEVICE;
     if (P->m > 0 &&
-        hipMemcpy(raw.data(), P->idf, (size_t)P->m * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(raw.data(), P->ent, (size_t)P->m * sizeof(Entry), hipMemcpyDeviceToHost) != hipSuccess)
         return SJ_ERR_DEVICE;
     // regroup from the blocked tile order into row-major tile order
     int64_t at = 0;
@@ -594,7 +572,7 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
                                (int64_t)(ty - gy * P->bl.B) * P->bl.B + (tx - gx * P->bl.B);
             if (offsets) offsets[(int64_t)ty * K + tx] = at;
             for (uint32_t q = off[bt]; q < off[bt + 1]; ++q, ++at)
-                if (ids) ids[at] = (int32_t)(raw[q] & kIdMask);
+                if (ids) ids[at] = (int32_t)(raw[q].m.x & kIdMask);
         }
     if (offsets) offsets[(int64_t)K * K] = at;
     return SJ_OK;
@@ -602,8 +580,7 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
 
 void sj_part_free(sj_part* P) {
     if (!P) return;
-    void* bufs[] = {P->h1, P->e1box, P->e1id, P->cp, P->chunk_cell, P->h2,
-                    P->box, P->idf, P->off, P->scan_tmp, P->st};
+    void* bufs[] = {P->h1, P->e1, P->cp, P->chunk_cell, P->h2, P->ent, P->off, P->scan_tmp, P->st};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete P;

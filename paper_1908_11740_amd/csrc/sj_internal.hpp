@@ -48,6 +48,15 @@ constexpr uint32_t kIdMask = 0x3FFFFFFFu;
 constexpr uint32_t kBx = 0x40000000u;
 constexpr uint32_t kBy = 0x80000000u;
 
+// A partition entry: the rectangle (x_l, y_l, x_u, y_u) and its id word,
+// padded to one 32-byte sector so that a scattered entry write is a single
+// full-sector HBM write (a 16-byte and a separate 4-byte store would each
+// cost a 32-byte request).  m.y..m.w are zero.
+struct __attribute__((aligned(32))) Entry {
+    float4 b;
+    uint4 m;
+};
+
 // Device-side status word bits.
 constexpr uint32_t kStatBadRect = 1u;
 constexpr uint32_t kStatCapacity = 2u;  // an internal buffer was too small (sizes reported)
@@ -71,8 +80,8 @@ constexpr int kCoarseMax = 64;    // G <= 64: level-1 LDS histogram <= 16 KB
 constexpr int kCoarsePref = 32;   // preferred G (longer level-1 write runs)
 constexpr int kMaxB = (SJ_K_MAX + kCoarseMax - 1) / kCoarseMax;  // B <= 128: level-2 LDS <= 64 KB
 constexpr uint32_t kChunk2 = 8192;  // level-1 entries per level-2 chunk
-constexpr int64_t kL1Blocks = 256;  // level-1 workgroups per input (upper bound)
-constexpr int64_t kL1MinChunk = 4096;
+constexpr int64_t kL1Blocks = 1024;  // level-1 workgroups per input (upper bound: 4 per CU)
+constexpr int64_t kL1MinChunk = 2048;
 
 struct Blocking {
     int G;  // coarse cells per dimension
@@ -97,8 +106,7 @@ struct Part {
     int64_t nb1 = 0;        // level-1 workgroups of the last call
     uint32_t* h1 = nullptr;   // [cap_h1]  level-1 histograms -> offsets (scanned in place)
     int64_t cap_h1 = 0;
-    float4* e1box = nullptr;  // [cap_m1]  level-1 entries
-    uint32_t* e1id = nullptr;
+    Entry* e1 = nullptr;      // [cap_m1]  level-1 entries
     int64_t cap_m1 = 0;
     uint32_t* cp = nullptr;   // [G*G + 1] chunk prefix per coarse cell
     int64_t cap_cp = 0;
@@ -106,8 +114,7 @@ struct Part {
     int64_t cap_chunks = 0;
     uint32_t* h2 = nullptr;   // [B*B*cap_chunks + 1] level-2 histograms -> offsets
     int64_t cap_h2 = 0;
-    float4* box = nullptr;    // [cap_m]   (x_l, y_l, x_u, y_u) per tile entry
-    uint32_t* idf = nullptr;  // [cap_m]   id word per tile entry
+    Entry* ent = nullptr;     // [cap_m]   tile entries (id word: position | start bits)
     int64_t cap_m = 0;
     uint32_t* off = nullptr;  // [G*G*B*B + 1] segment start per blocked tile
     int64_t cap_off = 0;
