@@ -29,6 +29,8 @@ WORKLOADS = {
     "skewed10m": "skewed 10M x 10M: 200-Gaussian mixture + 20% background, log-normal extents "
                  "(median 5e-5, sigma 1.0), float32",
     "uniform1m": "uniform 1M x 1M, extents U[0,2e-4], float32",
+    "batch256": "256 independent joins, n/side log-uniform [1e3, 2e6], per-join mixture "
+                "(clusters log-uniform [1,500], background U[0,0.5]), extents U[0,2e-4], float32",
 }
 
 
@@ -118,6 +120,90 @@ def measured_traffic(workload, kernel):
     return None if k is None else int(k["fetch_bytes"] + k["write_bytes"])
 
 
+def bench_batch(args, pk, sj, torch):
+    """Many joins in one recorded graph: a step is one replay of the whole
+    batch (partition + join of every join, grids chosen once by the picker
+    or the rule when the batch is planned)."""
+    import numpy as np
+    from paper_1908_11740_amd import datagen
+    n = 256
+    log("generating", n, "joins")
+    host = [datagen.batch_instance(j)[:2] for j in range(n)]
+    dev = [(torch.from_numpy(R).cuda(), torch.from_numpy(S).cuda()) for R, S in host]
+    use_learned = args.picker == "learned" or (args.picker == "auto" and pk.weights_available())
+    if use_learned:
+        pk.load()
+    else:
+        sj.picker_unload()
+    counting = sj.Batch(dev)
+    _, counts = counting.run()
+    counting.free()
+    b = sj.Batch(dev, capacities=[int(c) for c in counts])
+    for _ in range(max(1, args.warmup)):
+        st, npairs = b.run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        st, npairs = b.run()
+        times.append(time.perf_counter() - t0)
+    ms = sum(times) * 1e3 / len(times)
+    ks, taus = b.grids()
+    nrects = int(sum(R.shape[0] + S.shape[0] for R, S in host))
+    # the same joins one by one through the single-join entry points (same
+    # grids): what the recorded graph saves
+    outs = [torch.empty((int(c) + 1, 2), dtype=torch.int32, device="cuda") for c in counts]
+    parts = [[None, None] for _ in range(n)]
+
+    def sequential():
+        for j, (Rd, Sd) in enumerate(dev):
+            parts[j][0] = sj.partition(Rd, int(ks[j]), split_tau=int(taus[j]), reuse=parts[j][0])
+            parts[j][1] = sj.partition(Sd, int(ks[j]), split_tau=int(taus[j]), reuse=parts[j][1])
+            sj.join_into(parts[j][0], parts[j][1], outs[j])
+
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        sequential()
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3 / max(1, args.steps // 2)
+    for pr in parts:
+        pr[0].free()
+        pr[1].free()
+    P = int(npairs.sum())
+    verified = None
+    cpu = None
+    if not args.no_verify or not args.no_cpu_baseline:
+        import oracle
+        log("oracle pbsm per join on host cores")
+        t_cpu, ok = 0.0, True
+        for j, (R, S) in enumerate(host):
+            pairs, tp, tj = oracle.pbsm(R, S, int(ks[j]), threads=0, timings=True, sort=False)
+            ok = ok and len(pairs) == int(npairs[j])
+            t_cpu += tp + tj
+        verified = ok
+        if not args.no_cpu_baseline:
+            cpu = {"value": round(nrects / t_cpu, 1), "unit": "rects/s", "cores": oracle.max_threads(),
+                   "kind": "oracle", "sample": f"all {n} joins at the batch's grids, {t_cpu:.3f} s"}
+    rec = {
+        "metric": "input rects/s", "value": round(nrects / (ms * 1e-3), 1), "unit": "rects/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch256"], "joins": n, "rects": nrects,
+                   "grid_choice": "learned" if use_learned else "rule",
+                   "grid_k_min": int(ks.min()), "grid_k_max": int(ks.max()),
+                   "schedule": "one recorded graph, 4 concurrent branches", "mode": "pairs"},
+        "pairs_per_s": round(P / (ms * 1e-3), 1), "n_pairs": P,
+        "pairs_match_oracle_count": verified, "median_ms_per_step": round(statistics.median(times) * 1e3, 4),
+        "sequential_ms_per_step": round(ms_seq, 4), "speedup_vs_sequential": round(ms_seq / ms, 3),
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    b.free()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -142,6 +228,8 @@ def main():
     from paper_1908_11740_amd import sj
 
     torch.cuda.set_device(0)
+    if args.workload == "batch256":
+        return bench_batch(args, pk, sj, torch)
     log("generating", args.workload)
     R, S = inputs(args.workload)
     Rd = torch.from_numpy(R).cuda()

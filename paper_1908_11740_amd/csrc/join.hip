@@ -56,6 +56,7 @@ enum Ctr : int {
 };
 
 constexpr int kWaveBuf = 256;        // staged pairs per wave (>= 64 lanes x kCand)
+constexpr int kUnitWaveBuf = 128;    // LDS units emit one candidate per lane and call
 constexpr int kMedNT = 512;          // workgroup of the medium-tile kernel
 constexpr int kMedE = 2048;          // LDS entries of a medium tile
 constexpr int kDenseSortMax = 8192;  // entries sorted in LDS by the dense sort
@@ -368,7 +369,7 @@ __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_e
 // LDS unit: a batch of tiles staged, sorted and swept in LDS.
 // ---------------------------------------------------------------------------
 struct LdsLayout {
-    unsigned long long* wbuf;  // [nwaves * kWaveBuf]
+    unsigned long long* wbuf;  // [nwaves * kUnitWaveBuf]
     uint32_t* acc;             // [0] sink accumulator, [1] next pivot to claim
     uint32_t* rg;  // [tc+1] global start of each tile's R segment
     uint32_t* rl;  // [tc+1] local start (prefix) of each tile's R segment
@@ -382,7 +383,7 @@ struct LdsLayout {
 
 __host__ __device__ inline size_t lds_bytes(int nt, int E, int tc) {
     size_t b = 0;
-    b += (size_t)(nt / kWave) * kWaveBuf * 8;
+    b += (size_t)(nt / kWave) * kUnitWaveBuf * 8;
     b += 16;
     b += (size_t)4 * (tc + 1) * 4;
     b = (b + 15) / 16 * 16;
@@ -396,14 +397,14 @@ __host__ __device__ inline size_t lds_bytes(int nt, int E, int tc) {
 __device__ inline LdsLayout carve(unsigned char* p, int nt, int E, int tc) {
     LdsLayout L;
     L.wbuf = (unsigned long long*)p;
-    p += (size_t)(nt / kWave) * kWaveBuf * 8;
+    p += (size_t)(nt / kWave) * kUnitWaveBuf * 8;
     L.acc = (uint32_t*)p; p += 16;
     L.rg = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
     L.rl = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
     L.sg = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
     L.sl = (uint32_t*)p; p += (size_t)(tc + 1) * 4;
     {
-        const size_t used = (size_t)((nt / kWave) * kWaveBuf * 8 + 16 + 4 * (tc + 1) * 4);
+        const size_t used = (size_t)((nt / kWave) * kUnitWaveBuf * 8 + 16 + 4 * (tc + 1) * 4);
         p += ((used + 15) / 16 * 16) - used;  // 16-byte alignment of the boxes
     }
     L.bx = (float4*)p; p += (size_t)E * 16;
@@ -419,54 +420,37 @@ __host__ __device__ constexpr int tc_for(int E, bool batched) { return batched ?
 template <int MODE>
 __device__ inline Sink<MODE, true> make_sink(const LdsLayout& L) {
     Sink<MODE, true> sk;
-    sk.buf = L.wbuf + (threadIdx.x / kWave) * kWaveBuf;
+    sk.buf = L.wbuf + (threadIdx.x / kWave) * kUnitWaveBuf;
     sk.s_acc = L.acc;
-    sk.bufcap = kWaveBuf;
+    sk.bufcap = kUnitWaveBuf;
     sk.init(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
     return sk;
 }
 
-struct LdsAcc {
-    const LdsLayout* L;
-    int NR;  // R entries of the unit; S entries start at NR
-    __device__ float4 box(int j) const { return L->bx[j]; }
-    __device__ uint32_t id(int j) const { return L->id[j]; }
-    __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxu, float& pyl, float& pyu,
-                          uint32_t& pid) const {
-        const int k = L->tk[p];
-        const float4 b = L->bx[p];
-        pxu = b.z;
-        pyl = b.y;
-        pyu = b.w;
-        pid = L->id[p];
-        auto X = [&](int q) { return L->bx[q].x; };
-        // R pivot: scan S from the first s with s.x_l > r.x_l;
-        // S pivot: scan R from the first r with r.x_l >= s.x_l
-        isR = p < NR;
-        const int lo = isR ? NR + (int)L->sl[k] : (int)L->rl[k];
-        const int hi = isR ? NR + (int)L->sl[k + 1] : (int)L->rl[k + 1];
-        j = search_x(X, lo, hi, b.x, isR);
-        jend = hi;
-        return true;
-    }
-};
-
 // Rank of (key[e], e) among the entries [lo, hi): the sorted position of e
 // within its segment (ties broken by position).  Eight keys per two 128-bit
 // LDS loads; key[] is 16-byte aligned and readable 8 entries past the end.
+// A position j counts if key[j] < key[e], or key[j] == key[e] and j < e,
+// i.e. if key[j] < key[e] + (j < e) (finite order keys stay below 2^32 - 1).
+// Only the first and last groups of eight need the segment bounds.
 __device__ __forceinline__ int seg_rank(const uint32_t* key, int lo, int hi, int e) {
     const uint32_t my = key[e];
     const uint4* k4 = (const uint4*)key;
     int rank = 0;
-    for (int jb = lo & ~3; jb < hi; jb += 8) {
-        const uint4 A = k4[jb >> 2], B = k4[(jb >> 2) + 1];
+    int jb = lo & ~3;
+    auto group = [&](int j0, bool bounded) {
+        const uint4 A = k4[j0 >> 2], B = k4[(j0 >> 2) + 1];
         const uint32_t kk[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
+        const int d = e - j0;  // positions u < d precede e
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int jj = jb + u;
-            rank += (jj >= lo && jj < hi) && (kk[u] < my || (kk[u] == my && jj < e));
+            const bool c = kk[u] < my + (u < d ? 1u : 0u);
+            rank += (bounded ? (c && j0 + u >= lo && j0 + u < hi) : c) ? 1 : 0;
         }
-    }
+    };
+    group(jb, true);  // head: may start before lo and end after hi
+    for (jb += 8; jb + 8 <= hi; jb += 8) group(jb, false);
+    if (jb < hi) group(jb, true);
     return rank;
 }
 

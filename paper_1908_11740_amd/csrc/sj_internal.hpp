@@ -79,7 +79,7 @@ struct DevStatus {
 constexpr int kCoarseMax = 64;    // G <= 64: level-1 LDS histogram <= 16 KB
 constexpr int kCoarsePref = 32;   // preferred G (longer level-1 write runs)
 constexpr int kMaxB = (SJ_K_MAX + kCoarseMax - 1) / kCoarseMax;  // B <= 128: level-2 LDS <= 64 KB
-constexpr uint32_t kChunk2 = 8192;  // level-1 entries per level-2 chunk
+constexpr uint32_t kChunk2 = 4096;  // level-1 entries per level-2 chunk
 constexpr int64_t kL1Blocks = 1024;  // level-1 workgroups per input (upper bound: 4 per CU)
 constexpr int64_t kL1MinChunk = 2048;
 
