@@ -36,7 +36,7 @@
  *              that stream once to read it.
  * Ownership    Input pointers are borrowed for the duration of the call (the
  *              caller may free them once the stream has synchronised).
- *              Output buffers are caller-owned.  sj_part and sj_ctx handles
+ *              Output buffers are caller-owned.  sj_part and sj_batch handles
  *              are library-owned and released with their _free function.
  * Errors       No exception or abort crosses the ABI; every failure is a
  *              negative sj_status.  Handles are not thread-safe: calls that

@@ -14,23 +14,29 @@
 //
 // Work units
 //   small:   tiles with both lists non-empty and at most `small_cap` entries
-//            are batched into LDS units of about `unit_cap` entries; one
-//            workgroup stages the unit's tile slabs in LDS, sorts every tile
-//            segment in LDS and sweeps from LDS.
+//            are batched into LDS units of about `unit_cap` entries; a unit
+//            is staged, sorted per tile segment and swept in LDS, either by
+//            one wavefront (64-thread schedule: wave-level fences only, the
+//            next unit staged while the current one is swept) or by one
+//            workgroup of 128 / 256 / 512 threads.
 //   medium:  tiles up to `med_cap` entries, one per workgroup, same code with
-//            a larger LDS slab.
+//            a larger LDS slab (large lists bitonic-sorted in LDS).
 //   dense:   larger tiles are sorted into a global buffer and swept by units
 //            of at most `split_tau` pivots, so one tile is shared by many CUs.
 //   plain:   (baseline) one workgroup per tile for every tile, LDS up to
 //            1024 entries, larger tiles dense without splitting.
 //
-// Output without a shared counter: a device-wide atomic on one address
-// serialises at roughly 80 M/s on this GPU, so the join runs in two passes.
-// The counting pass writes each unit's pair count to its own slot; an
-// exclusive scan of the slots gives every unit an exclusive output region;
-// the writing pass stages pairs per wave in LDS (ballot + masked popcount
-// for the slots) and flushes them into the unit's region, reserving space
-// with an LDS atomic.  Count-only joins stop after the scan.
+// Output without a shared counter (a device-wide atomic on one address
+// serialises at roughly 80 M/s on this GPU).  Every wave stages its pairs in
+// LDS (ballot + masked popcount give the slots) and flushes them:
+//   single pass (default): into 512-pair chunks of a scratch buffer that the
+//            wave reserves from one of 32 spread counters; chunk fill levels
+//            are scanned and the chunks compacted into the caller's buffer.
+//            Exact totals are kept even if the scratch runs out, and the call
+//            then joins again in two passes.
+//   two passes: a counting pass writes each unit's pair count to its own
+//            slot, an exclusive scan gives every unit its output region and
+//            the writing pass fills it.  Count-only joins stop after the scan.
 #include <algorithm>
 
 #include "sj_internal.hpp"
@@ -454,11 +460,14 @@ __device__ __forceinline__ int seg_rank(const uint32_t* key, int lo, int hi, int
     return rank;
 }
 
-// Stage tiles [0, c) -- segment bounds from tile_of(k) -- in LDS, sort every
+// Stage tiles [0, c) -- segment bounds from tile_of(k, k / NT) -- in LDS, sort every
 // tile segment by x_l and sweep.  Every thread of the workgroup calls it.
-template <int NT, int Q, int TC, int MODE, class TileOf>
-__device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const TileOf& tile_of,
-                             Sink<MODE, true>& sk) {
+// prefetch() runs once the unit's entries have arrived: the caller issues
+// the loads of its next unit there, so they overlap this unit's sort and
+// sweep.
+template <int NT, int Q, int TC, int MODE, class TileOf, class Prefetch>
+__device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const TileOf& tile_of,
+                             const Prefetch& prefetch, Sink<MODE, true>& sk) {
     constexpr int E = NT * Q;
     const int tid = threadIdx.x;
     if (c > TC) {  // more tiles than the LDS tile table holds: cannot happen
@@ -467,13 +476,17 @@ __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const Til
     }
     __shared__ uint32_t s_tot[2];
     __shared__ uint32_t s_wsum[2][NT / kWave + 1];
-    // 1. tile table with local prefixes (chunks of NT tiles)
+    // 1. tile table with local prefixes (chunks of NT tiles; unrolled, so
+    //    the chunk index is a constant for tile_of)
     uint32_t carry_r = 0, carry_s = 0;
-    for (int k0 = 0; k0 < c; k0 += NT) {
+#pragma unroll
+    for (int jc = 0; jc < (TC + NT - 1) / NT; ++jc) {
+        const int k0 = jc * NT;
+        if (k0 >= c) break;
         const int k = k0 + tid;
         uint32_t nr = 0, ns = 0, r0 = 0, s0 = 0;
         if (k < c) {
-            const uint4 ti = tile_of(k);  // (R start, nr, S start, ns)
+            const uint4 ti = tile_of(k, jc);  // (R start, nr, S start, ns)
             r0 = ti.x;
             nr = ti.y;
             s0 = ti.z;
@@ -590,6 +603,7 @@ __device__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const Til
             }
         }
     }
+    prefetch();
     __syncthreads();
     if (MODE != kWrite) {
         // 3. sort within each tile segment, write the sorted payload to LDS
@@ -1304,19 +1318,58 @@ __global__ __launch_bounds__(NT) void k_lds_units(Args a) {
                                : min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
     const LdsLayout L = carve(smem, NT, NT * Q, TC);
     Sink<MODE, true> sk = make_sink<MODE>(L);
-    // persistent workgroups, units assigned round-robin
-    for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
-        const int64_t slot = MEDIUM ? a.base_med + u : (int64_t)u;
-        sk.begin(a, slot);
+    // persistent workgroups, units assigned round-robin; the tile table of
+    // the next unit (and the unit record of the one after) is loaded while
+    // the current unit is sorted and swept
+    // table entries prefetched per thread (the rest are read when needed)
+    constexpr int kPf = TC > 2 ? ((TC + NT - 1) / NT < 3 ? (TC + NT - 1) / NT : 3) : 1;
+    const int tid = threadIdx.x;
+    const uint32_t G = gridDim.x;
+    uint4 pf0 = make_uint4(0, 0, 0, 0), pf1 = pf0, pf2 = pf0;
+    uint2 ud = make_uint2(0, 0), ud_next = make_uint2(0, 0);
+    if (blockIdx.x < nu) {
         if (MEDIUM) {
-            const uint4 ti = a.med[u];
-            run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int) { return ti; }, sk);
+            pf0 = a.med[blockIdx.x];
         } else {
-            const uint2 ud = a.units[u];
-            const uint4* tl = a.tinfo + ud.x;
-            run_lds_unit<NT, Q, TC, MODE>(a, L, (int)ud.y, [&](int k) { return tl[k]; }, sk);
+            ud = a.units[blockIdx.x];
+            if (tid < (int)ud.y) pf0 = a.tinfo[ud.x + tid];
+            if (kPf > 1 && tid + NT < (int)ud.y) pf1 = a.tinfo[ud.x + tid + NT];
+            if (kPf > 2 && tid + 2 * NT < (int)ud.y) pf2 = a.tinfo[ud.x + tid + 2 * NT];
+            if (blockIdx.x + G < nu) ud_next = a.units[blockIdx.x + G];
         }
+    }
+    for (uint32_t u = blockIdx.x; u < nu; u += G) {
+        const int64_t slot = MEDIUM ? a.base_med + u : (int64_t)u;
+        const uint4 c0 = pf0, c1 = pf1, c2 = pf2;
+        const int c = MEDIUM ? 1 : (int)ud.y;
+        const uint4* tl = a.tinfo + ud.x;
+        // chunk j of the table: thread tid asks for its own tile k = tid + j * NT
+        auto tile_of = [&](int k, int j) -> uint4 {
+            if (MEDIUM) return c0;
+            return j == 0 ? c0 : (j == 1 && kPf > 1 ? c1 : (j == 2 && kPf > 2 ? c2 : tl[k]));
+        };
+        const uint32_t un = u + G;
+        auto prefetch = [&]() {
+            if (un < nu) {
+                if (MEDIUM) {
+                    pf0 = a.med[un];
+                } else {
+                    const uint2 d = ud_next;
+                    if (tid < (int)d.y) pf0 = a.tinfo[d.x + tid];
+                    if (kPf > 1 && tid + NT < (int)d.y) pf1 = a.tinfo[d.x + tid + NT];
+                    if (kPf > 2 && tid + 2 * NT < (int)d.y) pf2 = a.tinfo[d.x + tid + 2 * NT];
+                    if (un + G < nu) ud = a.units[un + G];  // becomes ud_next below
+                }
+            }
+        };
+        sk.begin(a, slot);
+        run_lds_unit<NT, Q, TC, MODE>(a, L, c, tile_of, prefetch, sk);
         sk.end(a, slot);
+        if (!MEDIUM) {
+            const uint2 t = ud_next;
+            ud_next = ud;
+            ud = t;
+        }
     }
     sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
 }
@@ -1341,7 +1394,7 @@ __global__ __launch_bounds__(NT) void k_plain_tiles(Args a) {
         }
         const uint4 ti = make_uint4(a.offR[t], nr, a.offS[t], ns);
         sk.begin(a, t);
-        run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int) { return ti; }, sk);
+        run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int, int) { return ti; }, [] {}, sk);
         sk.end(a, t);
     }
     sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
