@@ -65,9 +65,12 @@ __global__ __launch_bounds__(kFeatNT) void k_feat_partial(const float4* __restri
     __syncthreads();
     double sw = 0, sh = 0, sww = 0, shh = 0;
     uint32_t bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float4 r = rects[i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float4 nxt = i < n ? rects[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (; i < n; i += stride) {
+        const float4 r = nxt;  // the next rectangle is loaded while this one is summed
+        if (i + stride < n) nxt = rects[i + stride];
         if (!rect_valid(r)) {
             ++bad;
             continue;

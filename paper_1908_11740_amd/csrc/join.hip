@@ -579,7 +579,10 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
         }
     }
     __syncthreads();
-    // 2. load entries (coalesced within each tile segment)
+    // 2. load entries (coalesced within each tile segment).  All loads are
+    //    issued before the first LDS store that uses one, so the Q gathers
+    //    are in flight together (an LDS store between them would order the
+    //    next address computation after the previous load's return).
     float4 pb[Q];
     uint32_t pi[Q], pg[Q];
 #pragma unroll
@@ -595,6 +598,12 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
             pb[q] = en->b;
             pi[q] = en->m.x;
             pg[q] = g;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int e = tid + q * NT;
+        if (e < NE) {
             if (MODE == kWrite) {  // the counting pass left every slab sorted
                 L.bx[e] = make_float4(pb[q].x, pb[q].y, pb[q].z, pb[q].w);
                 L.id[e] = pi[q];

@@ -80,8 +80,12 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
     const int64_t lo = (int64_t)blockIdx.x * ch1;
     const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
     bool bad = false;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const float4 a = rects[i];
+    // the next rectangle is loaded while this one is counted
+    int64_t i = lo + threadIdx.x;
+    float4 nxt = i < hi ? rects[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (; i < hi; i += blockDim.x) {
+        const float4 a = nxt;
+        if (i + blockDim.x < hi) nxt = rects[i + blockDim.x];
         if (!rect_ok(a)) {
             bad = true;
             continue;
@@ -112,8 +116,11 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
     const int64_t lo = (int64_t)blockIdx.x * ch1;
     const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
     uint32_t err = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        float4 a = rects[i];
+    int64_t i = lo + threadIdx.x;
+    float4 nxt = i < hi ? rects[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (; i < hi; i += blockDim.x) {
+        float4 a = nxt;
+        if (i + blockDim.x < hi) nxt = rects[i + blockDim.x];
         if (!rect_ok(a)) continue;
         a.x += 0.0f;  // -0.0 -> +0.0
         a.y += 0.0f;
@@ -243,8 +250,12 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const Entry* __restrict__ e1
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
         for (int i = threadIdx.x; i < B2; i += blockDim.x) hist[i] = 0u;
         __syncthreads();
-        for (uint32_t e = k.e0 + threadIdx.x; e < k.e1; e += blockDim.x) {
-            const Local l = local_range(cells_of(e1[e].b, g), k, bl);
+        uint32_t e = k.e0 + threadIdx.x;
+        float4 nxt = e < k.e1 ? e1[e].b : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (; e < k.e1; e += blockDim.x) {
+            const float4 cur = nxt;
+            if (e + blockDim.x < k.e1) nxt = e1[e + blockDim.x].b;
+            const Local l = local_range(cells_of(cur, g), k, bl);
             for (int y = l.y0; y <= l.y1; ++y)
                 for (int x = l.x0; x <= l.x1; ++x) atomicAdd(&hist[y * bl.B + x], 1u);
         }
@@ -273,9 +284,20 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ 
         for (int t = threadIdx.x; t < B2; t += blockDim.x)
             cur[t] = o2[k.h2base + (uint32_t)t * k.nch + k.c];
         __syncthreads();
-        for (uint32_t e = k.e0 + threadIdx.x; e < k.e1; e += blockDim.x) {
-            const float4 a = e1[e].b;
-            const uint32_t id = e1[e].m.x;
+        uint32_t e = k.e0 + threadIdx.x;
+        float4 nb = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint32_t nid = 0;
+        if (e < k.e1) {
+            nb = e1[e].b;
+            nid = e1[e].m.x;
+        }
+        for (; e < k.e1; e += blockDim.x) {
+            const float4 a = nb;
+            const uint32_t id = nid;
+            if (e + blockDim.x < k.e1) {  // the next entry is loaded while this one is placed
+                nb = e1[e + blockDim.x].b;
+                nid = e1[e + blockDim.x].m.x;
+            }
             const Cells c = cells_of(a, g);
             const Local l = local_range(c, k, bl);
             const int bx = k.gx * bl.B, by = k.gy * bl.B;
