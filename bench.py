@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--two-pass", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--stripes", action="store_true",
+                    help="one-dimensional partitioning: K vertical stripes swept along y")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--count", action="store_true", help="count-only join mode")
@@ -242,12 +244,14 @@ def main():
              "out": torch.empty((1 << 20, 2), dtype=torch.int32, device="cuda")}
 
     def step(plain):
+        stripes = sj.SJ_STRIPES if args.stripes else 0
         if args.k:
             K, tau = args.k, args.split_tau
         else:
             fl = sj.SJ_RULE_ONLY if (plain or not use_learned) else 0
-            K, tau, state["info"] = sj.choose_grid(Rd, Sd, split_tau=args.split_tau, flags=fl)
-        flags = sj.SJ_PLAIN if plain else (sj.SJ_TWO_PASS if args.two_pass else 0)
+            K, tau, state["info"] = sj.choose_grid(Rd, Sd, split_tau=args.split_tau,
+                                                   flags=fl | stripes)
+        flags = stripes | (sj.SJ_PLAIN if plain else (sj.SJ_TWO_PASS if args.two_pass else 0))
         state["PR"] = sj.partition(Rd, K, split_tau=tau, flags=flags, reuse=state["PR"])
         state["PS"] = sj.partition(Sd, K, split_tau=tau, flags=flags, reuse=state["PS"])
         state["K"], state["tau"] = K, tau
@@ -355,7 +359,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_r": nR, "n_s": nS, "grid_k": K,
                    "split_tau": r["tau"],
-                   "grid_choice": "fixed" if args.k else ("learned" if use_learned and main_mode == "tuned" else "rule"),
+                   "grid_choice": "fixed" if args.k else ("learned" if use_learned and main_mode == "tuned"
+                                                          and not args.stripes else "rule"),
+                   "partitioning": "1-D stripes" if args.stripes else "2-D grid",
                    "schedule": main_mode, "mode": "count" if args.count else "pairs",
                    "autotuned": r["tuning"]},
         "pairs_per_s": round(P / (ms * 1e-3), 1),

@@ -74,6 +74,11 @@ typedef enum {
 #define SJ_TWO_PASS 0x4u        /* sj_join: count, scan, then write the pairs in a second
                                    sweep instead of one sweep into scratch + compaction;
                                    never changes the result                                */
+#define SJ_STRIPES 0x8u         /* one-dimensional partitioning (Sec. 3.1): k vertical stripes
+                                   of the domain, each joined by a plane sweep along y; the
+                                   duplicate test of Eq. (1) reduces to the reference point's
+                                   x (Sec. 3.2).  sj_choose_grid's rule then uses the mean
+                                   x-extent (Sec. 4.3.1)                                   */
 
 /*
  * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.3.2).
@@ -87,10 +92,12 @@ typedef enum {
  *   domain     x0, y0, x1, y1 of the gridded region; all zero = the unit
  *              square [0,1)^2 (the paper normalises data to [0,1], Sec. 4.1).
  *              Rectangles outside it are clamped into the border tiles.
- *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS.
+ *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS, SJ_STRIPES.
  * Tile (tx, ty) holds the rectangles whose cell ranges
  * [cell(x_l), cell(x_u)] x [cell(y_l), cell(y_u)] contain it, with
  * cell(v) = clamp(floor((v - x0) * K / (x1 - x0)), 0, K - 1) in float32.
+ * With SJ_STRIPES, stripe t holds the rectangles whose x cell range
+ * [cell(x_l), cell(x_u)] contains t.
  */
 typedef struct {
     int32_t k;
@@ -146,7 +153,8 @@ sj_status sj_part_stats(const sj_part* P, int64_t* level1_entries, int64_t* leve
 
 /*
  * Copy a partitioned input back to the host (for inspection and tests):
- *   offsets   k*k + 1 int64: segment of tile t is [offsets[t], offsets[t+1]).
+ *   offsets   k*k + 1 int64 (k + 1 with SJ_STRIPES): segment of tile t = ty*k + tx
+ *             (stripe t) is [offsets[t], offsets[t+1]).
  *   ids       n_entries int32 rectangle positions, grouped by tile (order
  *             within a tile unspecified).
  * Either pointer may be NULL.  Synchronises the stream.
@@ -267,6 +275,7 @@ typedef struct {
     int32_t k_learned;     /* the picker's K (0 if not used)                     */
     int32_t tau_learned;   /* the picker's split threshold (0 if not used)       */
     int32_t used_learned;  /* 1 if the picker chose                              */
+    double mean_x_extent;  /* mean over R and S of w (the 1-D rule's statistic)  */
 } sj_choice;
 
 /* The rule's K for a mean extent e (domain units): clamp(round(1/(10 e)),
@@ -286,6 +295,8 @@ sj_status sj_features(const float* R, int64_t nR, const float* S, int64_t nS, co
  * Fill in g->k when it is 0 and g->split_tau when it is 0: with the loaded
  * picker unless g->flags has SJ_RULE_ONLY, else with the rule (the split
  * threshold then stays 0 = library default).  Non-zero fields are kept.
+ * With SJ_STRIPES the rule is the 1-D one, k = clamp(round(1 / (10 e_x)),
+ * 1, SJ_K_MAX) from the mean x-extent e_x, and the picker is not used.
  * info (host, may be NULL) receives the statistics and both choices.
  * Computes the features on the device and synchronises the stream once.
  */

@@ -57,6 +57,18 @@ def mean_extent(R, S, domain=None):
     return tot / (2.0 * n) if n else 0.0
 
 
+def mean_x_extent(R, S, domain=None):
+    """Mean over R and S of w in domain units: the statistic of the 1-D rule
+    (stripes about ten times the mean x-extent, Sec. 4.3.1)."""
+    x0, _, x1, _ = _domain(domain)
+    tot, n = 0.0, 0
+    for A in (R, S):
+        A = np.asarray(A, dtype=np.float64).reshape(-1, 4)
+        tot += ((A[:, 2] - A[:, 0]) / (x1 - x0)).sum()
+        n += len(A)
+    return tot / n if n else 0.0
+
+
 def side_features(A, domain=None):
     x0, y0, x1, y1 = _domain(domain)
     A32 = np.asarray(A, dtype=np.float32).reshape(-1, 4)

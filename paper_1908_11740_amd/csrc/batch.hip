@@ -99,7 +99,7 @@ sj_status prepare_join(sj_batch* b, int j) {
         (e = api_part_prepare(S, b->ns[j], b->need_m1S[j], b->need_mS[j])) != hipSuccess)
         return from_hip_err(e);
     JoinParams p = api_join_params(b->grid[j], b->count_only);
-    const int64_t C = (int64_t)R.bl.G * R.bl.G * R.bl.B * R.bl.B;
+    const int64_t C = (int64_t)R.bl.cells() * R.bl.tiles_per_cell();
     sj_status st = api_join_prepare(b->work[b->lane[j]], p, C, R.cap_m, S.cap_m, cap_of(b, j));
     if (st != SJ_OK) return st;
     b->jp[j] = p;
@@ -331,7 +331,7 @@ sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t*
             P->device = b->device;
             P->grid = rg;
             P->gd = gd;
-            P->bl = blocking_for(rg.k);
+            P->bl = blocking_for(gd.kx, gd.ky);
         }
         b->R[j].n = nR[j];
         b->S[j].n = nS[j];

@@ -42,8 +42,8 @@ constexpr int kFeatBlocks = 2048;
 static_assert(kSide == 5 + kHist * kHist, "feature layout");
 
 struct ChooseOut {
-    double ebar;
-    int32_t k_rule, k_pick, tau_pick, invalid;
+    double ebar, ebar_x;
+    int32_t k_rule, k_pick, tau_pick, invalid, k_rule_x, pad;
     float y[2];
 };
 
@@ -168,6 +168,15 @@ __global__ __launch_bounds__(1024) void k_feat_final(const double* __restrict__ 
         }
         out->ebar = e;
         out->k_rule = k;
+        // 1-D partitioning (Sec. 4.3.1): stripes ten times the mean x-extent
+        const double ex = n > 0 ? (s[0][0] + s[1][0]) / (double)n : 0.0;
+        int kx1 = 1;
+        if (n > 0) {
+            const double kk = ex > 0 ? floor(1.0 / (10.0 * ex) + 0.5) : (double)SJ_K_MAX;
+            kx1 = (int)fmin(fmax(kk, 1.0), (double)SJ_K_MAX);
+        }
+        out->ebar_x = ex;
+        out->k_rule_x = kx1;
         out->k_pick = 0;
         out->tau_pick = 0;
         out->invalid = (int32_t)*invalid;
@@ -366,7 +375,8 @@ sj_status sj_choose_grid(const float* R, int64_t nR, const float* S, int64_t nS,
     if (st != SJ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if (launch_features(*c, R, nR, S, nS, d, s) != hipSuccess) return SJ_ERR_DEVICE;
-    const bool learned = c->loaded && !(g->flags & SJ_RULE_ONLY);
+    const bool stripes = (g->flags & SJ_STRIPES) != 0;
+    const bool learned = c->loaded && !(g->flags & SJ_RULE_ONLY) && !stripes;
     if (learned) {
         ProfRange pr("k_picker", s);
         const float* mu = c->picker;
@@ -382,11 +392,12 @@ sj_status sj_choose_grid(const float* R, int64_t nR, const float* S, int64_t nS,
         return SJ_ERR_DEVICE;
     const ChooseOut o = *c->host;
     if (o.invalid) return SJ_ERR_RECT;
-    if (g->k == 0) g->k = learned ? o.k_pick : o.k_rule;
+    if (g->k == 0) g->k = learned ? o.k_pick : (stripes ? o.k_rule_x : o.k_rule);
     if (g->split_tau == 0 && learned) g->split_tau = o.tau_pick;
     if (info) {
         info->mean_extent = o.ebar;
-        info->k_rule = o.k_rule;
+        info->k_rule = stripes ? o.k_rule_x : o.k_rule;
+        info->mean_x_extent = o.ebar_x;
         info->k_learned = learned ? o.k_pick : 0;
         info->tau_learned = learned ? o.tau_pick : 0;
         info->used_learned = learned ? 1 : 0;

@@ -53,16 +53,24 @@ __device__ __forceinline__ bool aborted(const DevStatus* st) {
     return s_abort != 0u;
 }
 
+// The rectangle in the partition's axes.  K vertical stripes swept along y
+// (1-D partitioning) are a 1 x K grid on the transposed input: swapping each
+// rectangle's x and y on load makes the stripes the grid's rows and the
+// sweep, which runs along the grid's x axis, run along the input's y.
+__device__ __forceinline__ float4 partition_axes(float4 a, const GridDev& g) {
+    return g.transpose ? make_float4(a.y, a.x, a.w, a.z) : a;
+}
+
 struct Cells {
     int cx0, cx1, cy0, cy1;
 };
 
 __device__ __forceinline__ Cells cells_of(float4 a, const GridDev& g) {
     Cells c;
-    c.cx0 = cell_of(a.x, g.x0, g.sx, g.K);
-    c.cx1 = cell_of(a.z, g.x0, g.sx, g.K);
-    c.cy0 = cell_of(a.y, g.y0, g.sy, g.K);
-    c.cy1 = cell_of(a.w, g.y0, g.sy, g.K);
+    c.cx0 = cell_of(a.x, g.x0, g.sx, g.kx);
+    c.cx1 = cell_of(a.z, g.x0, g.sx, g.kx);
+    c.cy0 = cell_of(a.y, g.y0, g.sy, g.ky);
+    c.cy1 = cell_of(a.w, g.y0, g.sy, g.ky);
     return c;
 }
 
@@ -74,7 +82,7 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
                                                     uint32_t* __restrict__ h1,
                                                     DevStatus* __restrict__ st) {
     extern __shared__ uint32_t hist[];  // [G1]
-    const int G1 = bl.G * bl.G;
+    const int G1 = bl.cells();
     for (int i = threadIdx.x; i < G1; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * ch1;
@@ -84,17 +92,17 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
     int64_t i = lo + threadIdx.x;
     float4 nxt = i < hi ? rects[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     for (; i < hi; i += blockDim.x) {
-        const float4 a = nxt;
+        const float4 a = partition_axes(nxt, g);
         if (i + blockDim.x < hi) nxt = rects[i + blockDim.x];
         if (!rect_ok(a)) {
             bad = true;
             continue;
         }
         const Cells c = cells_of(a, g);
-        const int gx0 = c.cx0 / bl.B, gx1 = c.cx1 / bl.B;
-        const int gy0 = c.cy0 / bl.B, gy1 = c.cy1 / bl.B;
+        const int gx0 = c.cx0 / bl.Bx, gx1 = c.cx1 / bl.Bx;
+        const int gy0 = c.cy0 / bl.By, gy1 = c.cy1 / bl.By;
         for (int gy = gy0; gy <= gy1; ++gy)
-            for (int gx = gx0; gx <= gx1; ++gx) atomicAdd(&hist[gy * bl.G + gx], 1u);
+            for (int gx = gx0; gx <= gx1; ++gx) atomicAdd(&hist[gy * bl.Gx + gx], 1u);
     }
     if (bad) atomicOr(&st->flags, kStatBadRect);
     __syncthreads();
@@ -109,7 +117,7 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
                                                       DevStatus* __restrict__ st) {
     extern __shared__ uint32_t cur[];  // [G1]
     if (aborted(st)) return;
-    const int G1 = bl.G * bl.G;
+    const int G1 = bl.cells();
     const int64_t nb = gridDim.x;
     for (int i = threadIdx.x; i < G1; i += blockDim.x) cur[i] = o1[(int64_t)i * nb + blockIdx.x];
     __syncthreads();
@@ -119,7 +127,7 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
     int64_t i = lo + threadIdx.x;
     float4 nxt = i < hi ? rects[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     for (; i < hi; i += blockDim.x) {
-        float4 a = nxt;
+        float4 a = partition_axes(nxt, g);
         if (i + blockDim.x < hi) nxt = rects[i + blockDim.x];
         if (!rect_ok(a)) continue;
         a.x += 0.0f;  // -0.0 -> +0.0
@@ -127,11 +135,11 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
         a.z += 0.0f;
         a.w += 0.0f;
         const Cells c = cells_of(a, g);
-        const int gx0 = c.cx0 / bl.B, gx1 = c.cx1 / bl.B;
-        const int gy0 = c.cy0 / bl.B, gy1 = c.cy1 / bl.B;
+        const int gx0 = c.cx0 / bl.Bx, gx1 = c.cx1 / bl.Bx;
+        const int gy0 = c.cy0 / bl.By, gy1 = c.cy1 / bl.By;
         for (int gy = gy0; gy <= gy1; ++gy)
             for (int gx = gx0; gx <= gx1; ++gx) {
-                const uint32_t slot = atomicAdd(&cur[gy * bl.G + gx], 1u);
+                const uint32_t slot = atomicAdd(&cur[gy * bl.Gx + gx], 1u);
                 if ((int64_t)slot >= cap_m1) {
                     err |= kStatCapacity;
                     continue;
@@ -152,7 +160,7 @@ __global__ __launch_bounds__(1024) void k_plan(const uint32_t* __restrict__ o1, 
                                               int64_t cap_chunks, DevStatus* __restrict__ st) {
     __shared__ uint32_t lds[1024 / kWave + 1];
     if (aborted(st)) return;
-    const int G1 = bl.G * bl.G;
+    const int G1 = bl.cells();
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
     uint32_t carry = 0;
     for (int g0 = 0; g0 < G1; g0 += blockDim.x) {
@@ -209,14 +217,14 @@ __device__ __forceinline__ Chunk chunk_info(uint32_t q, const uint32_t* cp, cons
                                             const uint32_t* o1, int64_t nb1, const Blocking& bl) {
     Chunk k;
     const uint32_t cell = chunk_cell[q];
-    k.gx = (int)(cell % (uint32_t)bl.G);
-    k.gy = (int)(cell / (uint32_t)bl.G);
+    k.gx = (int)(cell % (uint32_t)bl.Gx);
+    k.gy = (int)(cell / (uint32_t)bl.Gx);
     k.nch = cp[cell + 1] - cp[cell];
     k.c = q - cp[cell];
     const uint32_t b0 = o1[(int64_t)cell * nb1], b1 = o1[(int64_t)(cell + 1) * nb1];
     k.e0 = b0 + k.c * kChunk2;
     k.e1 = k.e0 + kChunk2 < b1 ? k.e0 + kChunk2 : b1;
-    k.h2base = (uint32_t)(bl.B * bl.B) * cp[cell];
+    k.h2base = (uint32_t)bl.tiles_per_cell() * cp[cell];
     return k;
 }
 
@@ -226,12 +234,12 @@ struct Local {
 };
 
 __device__ __forceinline__ Local local_range(const Cells& c, const Chunk& k, const Blocking& bl) {
-    const int bx = k.gx * bl.B, by = k.gy * bl.B;
+    const int bx = k.gx * bl.Bx, by = k.gy * bl.By;
     Local l;
     l.x0 = max(c.cx0, bx) - bx;
-    l.x1 = min(c.cx1, bx + bl.B - 1) - bx;
+    l.x1 = min(c.cx1, bx + bl.Bx - 1) - bx;
     l.y0 = max(c.cy0, by) - by;
-    l.y1 = min(c.cy1, by + bl.B - 1) - by;
+    l.y1 = min(c.cy1, by + bl.By - 1) - by;
     return l;
 }
 
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const Entry* __restrict__ e1
                                                     DevStatus* __restrict__ st) {
     extern __shared__ uint32_t hist[];  // [B*B]
     if (aborted(st)) return;
-    const int B2 = bl.B * bl.B;
+    const int B2 = bl.tiles_per_cell();
     const uint32_t nchunks = st->n_chunks;
     for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
@@ -257,7 +265,7 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const Entry* __restrict__ e1
             if (e + blockDim.x < k.e1) nxt = e1[e + blockDim.x].b;
             const Local l = local_range(cells_of(cur, g), k, bl);
             for (int y = l.y0; y <= l.y1; ++y)
-                for (int x = l.x0; x <= l.x1; ++x) atomicAdd(&hist[y * bl.B + x], 1u);
+                for (int x = l.x0; x <= l.x1; ++x) atomicAdd(&hist[y * bl.Bx + x], 1u);
         }
         __syncthreads();
         for (int t = threadIdx.x; t < B2; t += blockDim.x)
@@ -276,7 +284,7 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ 
                                                       DevStatus* __restrict__ st) {
     extern __shared__ uint32_t cur[];  // [B*B]
     if (aborted(st)) return;
-    const int B2 = bl.B * bl.B;
+    const int B2 = bl.tiles_per_cell();
     const uint32_t nchunks = st->n_chunks;
     uint32_t err = 0;
     for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
@@ -300,11 +308,11 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ 
             }
             const Cells c = cells_of(a, g);
             const Local l = local_range(c, k, bl);
-            const int bx = k.gx * bl.B, by = k.gy * bl.B;
+            const int bx = k.gx * bl.Bx, by = k.gy * bl.By;
             for (int y = l.y0; y <= l.y1; ++y) {
                 const uint32_t fy = (by + y == c.cy0) ? kBy : 0u;
                 for (int x = l.x0; x <= l.x1; ++x) {
-                    const uint32_t slot = atomicAdd(&cur[y * bl.B + x], 1u);
+                    const uint32_t slot = atomicAdd(&cur[y * bl.Bx + x], 1u);
                     if ((int64_t)slot >= cap_m) {
                         err |= kStatCapacity;
                         continue;
@@ -326,8 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t* __restr
                                                         Blocking bl, uint32_t* __restrict__ off,
                                                         DevStatus* __restrict__ st) {
     if (aborted(st)) return;
-    const int64_t B2 = (int64_t)bl.B * bl.B;
-    const int64_t Cb = (int64_t)bl.G * bl.G * B2;
+    const int64_t B2 = bl.tiles_per_cell();
+    const int64_t Cb = (int64_t)bl.cells() * B2;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= Cb;
          t += (int64_t)gridDim.x * blockDim.x) {
         if (t == Cb) {
@@ -493,12 +501,18 @@ hipError_t scan_u32(uint32_t* data, int64_t len, uint32_t* bs, unsigned long lon
     return hipGetLastError();
 }
 
-Blocking blocking_for(int K) {
+// One axis of the two-level blocking: G coarse cells of B tiles each.
+static void axis_blocking(int K, int& G, int& B) {
+    G = K < kCoarsePref ? K : kCoarsePref;
+    B = (K + G - 1) / G;
+    if (B > kMaxB) B = (K + kCoarseMax - 1) / kCoarseMax;
+    G = (K + B - 1) / B;
+}
+
+Blocking blocking_for(int kx, int ky) {
     Blocking b;
-    b.G = K < kCoarsePref ? K : kCoarsePref;
-    b.B = (K + b.G - 1) / b.G;
-    if (b.B > kMaxB) b.B = (K + kCoarseMax - 1) / kCoarseMax;
-    b.G = (K + b.B - 1) / b.B;
+    axis_blocking(kx, b.Gx, b.Bx);
+    axis_blocking(ky, b.Gy, b.By);
     return b;
 }
 
@@ -527,7 +541,7 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
         attrs = true;
     }
     const Blocking bl = P.bl;
-    const int64_t G1 = (int64_t)bl.G * bl.G, B2 = (int64_t)bl.B * bl.B;
+    const int64_t G1 = bl.cells(), B2 = bl.tiles_per_cell();
     const int64_t ch1 = l1_chunk(n);
     const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
     P.nb1 = nb1;

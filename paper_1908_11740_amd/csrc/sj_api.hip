@@ -71,17 +71,32 @@ sj_status resolve_grid(const sj_grid* g, sj_grid& out, GridDev& gd) {
     }
     const float w = out.domain[2] - out.domain[0], h = out.domain[3] - out.domain[1];
     if (!std::isfinite(w) || !std::isfinite(h) || !(w > 0.f) || !(h > 0.f)) return SJ_ERR_ARG;
-    gd.x0 = out.domain[0];
-    gd.y0 = out.domain[1];
-    gd.sx = (float)out.k / w;
-    gd.sy = (float)out.k / h;
-    gd.K = out.k;
+    if (out.flags & SJ_STRIPES) {
+        // K vertical stripes swept along y: a 1 x K grid on the transposed
+        // input (partition axes: x' = y, y' = x)
+        gd.transpose = 1;
+        gd.x0 = out.domain[1];
+        gd.y0 = out.domain[0];
+        gd.sx = 1.0f / h;
+        gd.sy = (float)out.k / w;
+        gd.kx = 1;
+        gd.ky = out.k;
+    } else {
+        gd.transpose = 0;
+        gd.x0 = out.domain[0];
+        gd.y0 = out.domain[1];
+        gd.sx = (float)out.k / w;
+        gd.sy = (float)out.k / h;
+        gd.kx = out.k;
+        gd.ky = out.k;
+    }
     if (!std::isfinite(gd.sx) || !std::isfinite(gd.sy)) return SJ_ERR_ARG;
     return SJ_OK;
 }
 
 bool same_grid(const sj_grid& a, const sj_grid& b) {
-    return a.k == b.k && std::memcmp(a.domain, b.domain, sizeof(a.domain)) == 0;
+    return a.k == b.k && std::memcmp(a.domain, b.domain, sizeof(a.domain)) == 0 &&
+           (a.flags & SJ_STRIPES) == (b.flags & SJ_STRIPES);
 }
 
 struct DeviceState {
@@ -258,7 +273,7 @@ hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
     Part* P = &Pr;
     hipError_t e = hipSuccess;
     const Blocking bl = P->bl;
-    const int64_t G1 = (int64_t)bl.G * bl.G, B2 = (int64_t)bl.B * bl.B, Cb = G1 * B2;
+    const int64_t G1 = bl.cells(), B2 = bl.tiles_per_cell(), Cb = G1 * B2;
     const int64_t ch1 = l1_chunk(n);
     const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
     const int64_t need_chunks = need_m1 / kChunk2 + G1 + 2;
@@ -291,7 +306,7 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
     if (st != SJ_OK) return st;
     JoinWork& w = ds->w;
     JoinParams p = tuned_params(R->device, R->grid, R->m, S->m, count_only);
-    st = join_prepare(w, p, (int64_t)R->bl.G * R->bl.G * R->bl.B * R->bl.B, R->m, S->m, capacity);
+    st = join_prepare(w, p, (int64_t)R->bl.cells() * R->bl.tiles_per_cell(), R->m, S->m, capacity);
     if (st != SJ_OK) return st;
     hipError_t e = hipSuccess;
     DevStatus hs{};
@@ -392,8 +407,8 @@ sj_status sj_partition(const float* rects, int64_t n, const sj_grid* g, sj_part*
         sj_status st = device_state(dev, &ds);
         if (st != SJ_OK) return fail(st);
     }
-    const Blocking bl = blocking_for(grid.k);
-    const int64_t G1 = (int64_t)bl.G * bl.G, B2 = (int64_t)bl.B * bl.B, Cb = G1 * B2;
+    const Blocking bl = blocking_for(gd.kx, gd.ky);
+    const int64_t G1 = bl.cells(), B2 = bl.tiles_per_cell(), Cb = G1 * B2;
     const int64_t ch1 = l1_chunk(n);
     const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
     int64_t need_m1 = std::max<int64_t>(P->cap_m1, n + n / 4 + 4096);
@@ -553,9 +568,10 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
     if (!P) return SJ_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (hipStreamSynchronize(s) != hipSuccess) return SJ_ERR_DEVICE;
-    const int K = P->grid.k;
-    const int64_t B2 = (int64_t)P->bl.B * P->bl.B;
-    const int64_t Cb = (int64_t)P->bl.G * P->bl.G * B2;
+    const int kx = P->gd.kx, ky = P->gd.ky;
+    const Blocking bl = P->bl;
+    const int64_t B2 = bl.tiles_per_cell();
+    const int64_t Cb = (int64_t)bl.cells() * B2;
     std::vector<uint32_t> off((size_t)Cb + 1);
     std::vector<Entry> raw((size_t)std::max<int64_t>(P->m, 1));
     if (hipMemcpy(off.data(), P->off, (size_t)(Cb + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
@@ -563,18 +579,19 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
     if (P->m > 0 &&
         hipMemcpy(raw.data(), P->ent, (size_t)P->m * sizeof(Entry), hipMemcpyDeviceToHost) != hipSuccess)
         return SJ_ERR_DEVICE;
-    // regroup from the blocked tile order into row-major tile order
+    // regroup from the blocked tile order into row-major tile order of the
+    // partition grid (stripes: kx = 1, one row per stripe)
     int64_t at = 0;
-    for (int ty = 0; ty < K; ++ty)
-        for (int tx = 0; tx < K; ++tx) {
-            const int gx = tx / P->bl.B, gy = ty / P->bl.B;
-            const int64_t bt = ((int64_t)gy * P->bl.G + gx) * B2 +
-                               (int64_t)(ty - gy * P->bl.B) * P->bl.B + (tx - gx * P->bl.B);
-            if (offsets) offsets[(int64_t)ty * K + tx] = at;
+    for (int ty = 0; ty < ky; ++ty)
+        for (int tx = 0; tx < kx; ++tx) {
+            const int gx = tx / bl.Bx, gy = ty / bl.By;
+            const int64_t bt = ((int64_t)gy * bl.Gx + gx) * B2 +
+                               (int64_t)(ty - gy * bl.By) * bl.Bx + (tx - gx * bl.Bx);
+            if (offsets) offsets[(int64_t)ty * kx + tx] = at;
             for (uint32_t q = off[bt]; q < off[bt + 1]; ++q, ++at)
                 if (ids) ids[at] = (int32_t)(raw[q].m.x & kIdMask);
         }
-    if (offsets) offsets[(int64_t)K * K] = at;
+    if (offsets) offsets[(int64_t)kx * ky] = at;
     return SJ_OK;
 }
 

@@ -22,9 +22,10 @@ constexpr int kWave = 64;
 // duplicate test exact: cell(max(a, b)) = max(cell(a), cell(b)).
 // ---------------------------------------------------------------------------
 struct GridDev {
-    float x0, y0;  // lower corner of the gridded domain
-    float sx, sy;  // K / domain width, K / domain height
-    int K;
+    float x0, y0;   // lower corner of the gridded domain (partition axes)
+    float sx, sy;   // kx / domain width, ky / domain height
+    int kx, ky;     // cells along x and y
+    int transpose;  // 1: each rectangle's x and y are swapped on load (stripes, see sj.h)
 };
 
 __device__ __forceinline__ int cell_of(float v, float lo, float scale, int K) {
@@ -84,11 +85,13 @@ constexpr int64_t kL1Blocks = 1024;  // level-1 workgroups per input (upper boun
 constexpr int64_t kL1MinChunk = 2048;
 
 struct Blocking {
-    int G;  // coarse cells per dimension
-    int B;  // tiles per coarse cell and dimension
+    int Gx, Gy;  // coarse cells along x and y
+    int Bx, By;  // tiles per coarse cell along x and y
+    __host__ __device__ int cells() const { return Gx * Gy; }
+    __host__ __device__ int tiles_per_cell() const { return Bx * By; }
 };
 
-Blocking blocking_for(int K);
+Blocking blocking_for(int kx, int ky);
 int64_t l1_chunk(int64_t n);
 
 // ---------------------------------------------------------------------------

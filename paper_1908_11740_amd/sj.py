@@ -26,6 +26,7 @@ SJ_K_MAX = 8192
 SJ_PLAIN = 0x1
 SJ_RULE_ONLY = 0x2
 SJ_TWO_PASS = 0x4
+SJ_STRIPES = 0x8
 INT32_MAX = 2**31 - 1
 
 
@@ -44,7 +45,7 @@ class Grid(ctypes.Structure):
 class Choice(ctypes.Structure):
     _fields_ = [("mean_extent", ctypes.c_double), ("k_rule", ctypes.c_int32),
                 ("k_learned", ctypes.c_int32), ("tau_learned", ctypes.c_int32),
-                ("used_learned", ctypes.c_int32)]
+                ("used_learned", ctypes.c_int32), ("mean_x_extent", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -199,7 +200,7 @@ class Part:
 
     def download(self, stream=None):
         n, m, g = self.info()
-        C = g.k * g.k
+        C = g.k if g.flags & SJ_STRIPES else g.k * g.k
         off = (ctypes.c_int64 * (C + 1))()
         ids = (ctypes.c_int32 * max(m, 1))()
         _check(lib().sj_part_download(self._h, off, ids, _stream(stream)), "sj_part_download")
@@ -326,7 +327,7 @@ class Batch:
     (0 entries are chosen).  capacities: per-join output slices (None:
     count-only batch)."""
 
-    def __init__(self, pairs, grids=None, capacities=None, stream=None):
+    def __init__(self, pairs, grids=None, capacities=None, flags=0, stream=None):
         import numpy as np
         n = len(pairs)
         self.n = n
@@ -339,7 +340,7 @@ class Batch:
         g = (Grid * max(n, 1))()
         for j in range(n):
             k, tau = grids[j] if grids is not None else (0, 0)
-            g[j] = make_grid(k, tau)
+            g[j] = make_grid(k, tau, flags=flags)
         self._g = g
         dev = torch.device("cuda", torch.cuda.current_device())
         if capacities is None:

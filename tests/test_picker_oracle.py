@@ -35,6 +35,16 @@ def test_rule_on_generated_workloads():
     assert abs(op.rule_k(e) - 1213) <= 10
 
 
+def test_one_dimensional_rule_uses_the_x_extents():
+    # stripes ten times the mean x-extent (Sec. 4.3.1): only w counts
+    R = np.array([[0, 0, 0.2, 0.9]], np.float32)   # w = 0.2, h = 0.9
+    S = np.array([[0.5, 0.5, 0.5, 0.6]], np.float32)  # w = 0, h = 0.1
+    assert op.mean_x_extent(R, S) == pytest.approx(0.1)
+    assert op.rule_k(op.mean_x_extent(R, S)) == 1
+    R, S = datagen.uniform_1m(200_000)
+    assert op.rule_k(op.mean_x_extent(R, S)) == 1000
+
+
 def test_mean_extent_hand_case_and_domain_scaling():
     R = np.array([[0, 0, 0.2, 0.1]], np.float32)
     S = np.array([[0.5, 0.5, 0.5, 0.9], [0.1, 0.1, 0.3, 0.1]], np.float32)
