@@ -7,7 +7,9 @@ code with the GPU library and never imports it.
 
 Python wrappers around ``sj_oracle.c`` (brute force = the definition of
 Sec. 1; Algorithm 1 over the whole input, Sec. 2.1; PBSM with the parallel
-phases of Sec. 3.4 and the duplicate test of Eq. (1)).  Every wrapper returns
+phases of Sec. 3.4 and the duplicate test of Eq. (1); the epsilon-distance
+join of point sets of Sec. 1, by its definition and by the filter-and-refine
+steps: squares of side eps, PBSM, distance check).  Every wrapper returns
 the pair set as an ``(P, 2)`` int32 array sorted lexicographically by
 ``(r, s)``; the sort is a library primitive applied to the oracle's output.
 """
@@ -44,6 +46,11 @@ def _load():
         lib.oracle_partition_ids.argtypes = [f32p, i64, ctypes.c_int, f32p,
                                              ctypes.POINTER(ctypes.c_int64), i32pp]
         lib.oracle_partition_ids.restype = i64
+        lib.oracle_distance_brute.argtypes = [f32p, i64, f32p, i64, ctypes.c_float, i32pp]
+        lib.oracle_distance_brute.restype = i64
+        lib.oracle_distance_refine.argtypes = [f32p, f32p, ctypes.c_float,
+                                               ctypes.POINTER(ctypes.c_int32), i64]
+        lib.oracle_distance_refine.restype = i64
         lib.oracle_free.argtypes = [ctypes.c_void_p]
         lib.oracle_free.restype = None
         lib.oracle_max_threads.argtypes = []
@@ -142,3 +149,59 @@ def partition_ids(A, K, domain=None):
 
 def max_threads():
     return int(_load().oracle_max_threads())
+
+
+# ----------------------------------------------------------------------------
+# Epsilon-distance join of point sets (Sec. 1)
+# ----------------------------------------------------------------------------
+def _points(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.ndim != 2 or a.shape[1] != 2:
+        raise ValueError("points must be an (n, 2) float32 array of (x, y)")
+    return a
+
+
+def distance_brute(P, Q, eps):
+    """The definition: every (i, j) with dx*dx + dy*dy <= eps*eps, in float64
+    from the float32 coordinates, each operation rounded once."""
+    P, Q = _points(P), _points(Q)
+    out = ctypes.POINTER(ctypes.c_int32)()
+    n = _load().oracle_distance_brute(_fp(P), len(P), _fp(Q), len(Q), float(np.float32(eps)),
+                                      ctypes.byref(out))
+    return _take(n, out)
+
+
+def squares(P, eps, rel=2.0 ** -40):
+    """Filter rectangles of Sec. 1: the square of side eps centred on each
+    point, as the smallest float32 box containing the square widened by
+    rel * (|c| + eps/2) per coordinate c (so that no pair the distance test
+    accepts is lost to rounding).  Returns (n, 4) float32."""
+    P = _points(P).astype(np.float64)
+    h = 0.5 * float(np.float32(eps))
+    m = (np.abs(P) + h) * rel
+    lo, hi = P - h - m, P + h + m
+    lo32, hi32 = lo.astype(np.float32), hi.astype(np.float32)
+    lo32 = np.where(lo32.astype(np.float64) > lo, np.nextafter(lo32, np.float32(-np.inf)), lo32)
+    hi32 = np.where(hi32.astype(np.float64) < hi, np.nextafter(hi32, np.float32(np.inf)), hi32)
+    return np.ascontiguousarray(np.stack([lo32[:, 0], lo32[:, 1], hi32[:, 0], hi32[:, 1]], 1),
+                                dtype=np.float32)
+
+
+def refine(P, Q, eps, pairs):
+    """The refinement step: the candidate pairs that pass the distance test."""
+    P, Q = _points(P), _points(Q)
+    c = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2).copy()
+    if len(c) and (c[:, 0].max() >= len(P) or c[:, 1].max() >= len(Q) or c.min() < 0):
+        raise IndexError("candidate index out of range")
+    k = _load().oracle_distance_refine(_fp(P), _fp(Q), float(np.float32(eps)),
+                                       c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(c))
+    return c[:k]
+
+
+def distance_filter_refine(P, Q, eps, K, domain=None, threads=0):
+    """The paper's steps (Sec. 1): squares of side eps around both point
+    sets, their intersection join by PBSM on a K x K grid, then the distance
+    test on every candidate.  Returns the sorted pair set."""
+    cand = pbsm(squares(P, eps), squares(Q, eps), K, domain=domain, threads=threads, sort=False)
+    out = refine(P, Q, eps, cand)
+    return out[np.lexsort((out[:, 1], out[:, 0]))] if len(out) else out

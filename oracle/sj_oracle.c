@@ -382,3 +382,44 @@ int64_t oracle_partition_ids(const float *A, int64_t n, int K, const float *doma
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------ */
+/* Epsilon-distance join of point sets (Sec. 1), the definition:        */
+/* every (i, j) with dx*dx + dy*dy <= eps*eps, evaluated in double from */
+/* the float coordinates, each operation rounded once (the build turns  */
+/* off contraction into fused multiply-adds).  Points are (x, y) pairs.  */
+/* ------------------------------------------------------------------ */
+static int within(const float *p, const float *q, double e2) {
+    double dx = (double)p[0] - (double)q[0];
+    double dy = (double)p[1] - (double)q[1];
+    return dx * dx + dy * dy <= e2;
+}
+
+int64_t oracle_distance_brute(const float *P, int64_t nP, const float *Q, int64_t nQ, float eps,
+                              int32_t **out) {
+    plist p = {0, 0, 0};
+    double e2 = (double)eps * (double)eps;
+    for (int64_t i = 0; i < nP; i++)
+        for (int64_t j = 0; j < nQ; j++)
+            if (within(P + 2 * i, Q + 2 * j, e2))
+                if (plist_push(&p, (int32_t)i, (int32_t)j)) { free(p.v); return -1; }
+    *out = p.v;
+    return p.n;
+}
+
+/* The refinement step alone: keep the candidate pairs (2*n int32) that
+ * satisfy the distance test, in place; returns how many were kept. */
+int64_t oracle_distance_refine(const float *P, const float *Q, float eps, int32_t *pairs,
+                               int64_t n) {
+    double e2 = (double)eps * (double)eps;
+    int64_t k = 0;
+    for (int64_t c = 0; c < n; c++) {
+        int32_t i = pairs[2 * c], j = pairs[2 * c + 1];
+        if (within(P + 2 * (int64_t)i, Q + 2 * (int64_t)j, e2)) {
+            pairs[2 * k] = i;
+            pairs[2 * k + 1] = j;
+            k++;
+        }
+    }
+    return k;
+}

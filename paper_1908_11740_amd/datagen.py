@@ -31,6 +31,14 @@ Workload recipes (sizes and seeds are the defaults of the helpers below):
   seed 4000 + i, per-side sizes log-uniform in [1e6, 2e7], cluster count
   log-uniform integer in [1, 500], background uniform in [0, 0.5], extent
   median log-uniform in [1e-5, 1e-3], sigma_ln = 1.0.
+* points for the epsilon-distance join (Sec. 1 names it as a use of the
+  intersection join): ``(n, 2)`` float32 ``(x, y)``.
+    - ``points_mixture``: the centres of ``mixture`` rounded to float32.
+    - skewed 10M point case: 10,000,000 per side, the skewed 10M mixture
+      (200 clusters, seed 300, 20% background), seeds 311 / 312, eps = 1e-4.
+    - ``lattice``: integer lattice points times a spacing (exact in float32).
+    - ``near_ring``: Q[i] = P[i] + r (cos t, sin t) rounded to float32 with r
+      within a few ulps of eps, so that many pairs sit on the boundary.
 * ``batch_instance(j)``: join j of the 256-join batch; from seed 5000 + j,
   per-side sizes log-uniform in [1e3, 2e6] (independently), cluster count and
   background as for the picker corpus, extents uniform in [0, 2e-4] around
@@ -196,3 +204,43 @@ def batch_instance(j, scale=1.0):
     ns = max(1, int(sp.n_s * scale))
     return (mixture_uniform_extent(nr, mix, sp.background, 2e-4, sp.seed * 7 + 2),
             mixture_uniform_extent(ns, mix, sp.background, 2e-4, sp.seed * 7 + 3), sp)
+
+
+# ----------------------------------------------------------------------------
+# Point sets for the epsilon-distance join
+# ----------------------------------------------------------------------------
+def points_uniform(n, seed):
+    """n points uniform in [0,1)^2."""
+    rng = np.random.default_rng(seed)
+    return rng.random((int(n), 2)).astype(np.float32)
+
+
+def points_mixture(n, mix, background, seed):
+    """n mixture centres (as in ``mixture``) rounded to float32."""
+    rng = np.random.default_rng(seed)
+    return _centres(rng, int(n), mix, background).astype(np.float32)
+
+
+def skewed_points_10m(n=10_000_000):
+    """10M x 10M skewed points: the skewed 10M mixture's centres; eps = 1e-4."""
+    mix = mixture_spec(200, 300)
+    return points_mixture(n, mix, 0.2, 311), points_mixture(n, mix, 0.2, 312), 1e-4
+
+
+def lattice(nx, ny, spacing=1.0, origin=(0.0, 0.0)):
+    """Points origin + spacing * (i, j), 0 <= i < nx, 0 <= j < ny (row-major by j)."""
+    j, i = np.mgrid[0:ny, 0:nx]
+    pts = np.stack([origin[0] + spacing * i.ravel(), origin[1] + spacing * j.ravel()], 1)
+    return pts.astype(np.float32)
+
+
+def near_ring(n, eps, seed, ulps=4):
+    """P uniform in [0.25, 0.75)^2 and Q[i] = P[i] + r (cos t, sin t) rounded to
+    float32, r = eps * (1 + u 2^-23) with u a random integer in [-ulps, ulps]."""
+    rng = np.random.default_rng(seed)
+    n = int(n)
+    P = (0.25 + 0.5 * rng.random((n, 2))).astype(np.float32)
+    t = rng.random(n) * 2 * np.pi
+    r = float(eps) * (1.0 + rng.integers(-ulps, ulps + 1, n) * 2.0 ** -23)
+    Q = (P.astype(np.float64) + r[:, None] * np.stack([np.cos(t), np.sin(t)], 1)).astype(np.float32)
+    return P, Q
