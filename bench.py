@@ -29,6 +29,8 @@ WORKLOADS = {
     "skewed10m": "skewed 10M x 10M: 200-Gaussian mixture + 20% background, log-normal extents "
                  "(median 5e-5, sigma 1.0), float32",
     "uniform1m": "uniform 1M x 1M, extents U[0,2e-4], float32",
+    "distance10m": "epsilon-distance join of skewed 10M x 10M points (centres of the skewed 10M "
+                   "mixture), eps 1e-4, float32",
     "batch256": "256 independent joins, n/side log-uniform [1e3, 2e6], per-join mixture "
                 "(clusters log-uniform [1,500], background U[0,0.5]), extents U[0,2e-4], float32",
 }
@@ -206,6 +208,106 @@ def bench_batch(args, pk, sj, torch):
     b.free()
 
 
+def bench_distance(args, pk, sj, torch):
+    """Epsilon-distance join (Sec. 1): a step is one sj_distance_join over the
+    resident point sets -- squares, grid choice, partition of both sides, the
+    intersection join into the candidate buffer and the distance check."""
+    from paper_1908_11740_amd import datagen
+    log("generating", args.workload)
+    P, Q, eps = datagen.skewed_points_10m()
+    Pd, Qd = torch.from_numpy(P).cuda(), torch.from_numpy(Q).cuda()
+    nP, nQ = len(P), len(Q)
+    use_learned = args.picker == "learned" or (args.picker == "auto" and pk.weights_available())
+    if use_learned:
+        pk.load()
+    else:
+        sj.picker_unload()
+    state = {"out": torch.empty((1 << 20, 2), dtype=torch.int32, device="cuda"), "n": 0, "g": None}
+
+    def step():
+        flags = (sj.SJ_STRIPES if args.stripes else 0) | (sj.SJ_TWO_PASS if args.two_pass else 0)
+        flags |= 0 if use_learned else sj.SJ_RULE_ONLY
+        g = sj.make_grid(args.k, args.split_tau, flags=flags)
+        out = None if args.count else state["out"]
+        st, n = sj.distance_join_into(Pd, Qd, eps, out, g)
+        if st == sj.SJ_ERR_CAPACITY:
+            state["out"] = torch.empty((int(n * 1.1) + 1024, 2), dtype=torch.int32, device="cuda")
+            st, n = sj.distance_join_into(Pd, Qd, eps, state["out"], g)
+        state["n"], state["g"] = n, g
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = sum(times) * 1e3 / len(times)
+    sj.prof_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kern = sj.prof_collect()
+    sj.prof_enable(False)
+    info = sj.distance_last_info()
+    st = sj.last_join_stats()
+    K, tau, n = state["g"].k, state["g"].split_tau, state["n"]
+    nc = info["candidates"]
+    w = dict(nR=nP, nS=nQ, m1R=info["level1_entries_p"], m1S=info["level1_entries_q"],
+             mR=info["entries_p"], mS=info["entries_q"], C=K * K, P=nc, stats=st)
+    kernels = {}
+    for name, (tot, calls) in kern.items():
+        avg = tot / max(calls, 1)
+        if name == "k_point_squares":
+            b = 24 * (nP + nQ) / 2           # two launches: 8 B in, 16 B out per point
+        elif name == "k_refine":
+            b = 24 * nc + 8 * n              # candidate + two point gathers, result write
+        else:
+            b = kernel_bytes(name, w)
+        kernels[name] = {"avg_ms": round(avg, 5), "calls": calls,
+                         "alg_bytes": None if b is None else int(b),
+                         "gbs": None if b is None else round(b / (avg * 1e-3) / 1e9, 1)}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["calls"])
+    dk = kernels[dom]
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s",
+                "frac": None if dk["gbs"] is None else round(dk["gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, dom),
+                "avg_ms": dk["avg_ms"], "alg_bytes_per_launch": dk["alg_bytes"]}
+    verified = None
+    cpu = None
+    if not args.no_verify or not args.no_cpu_baseline:
+        import oracle
+        log("oracle filter-and-refine on host cores, K", K)
+        t0 = time.perf_counter()
+        ref = oracle.distance_filter_refine(P, Q, eps, K)
+        secs = time.perf_counter() - t0
+        verified = len(ref) == n
+        if not args.no_cpu_baseline:
+            cpu = {"value": round((nP + nQ) / secs, 1), "unit": "points/s",
+                   "cores": oracle.max_threads(), "kind": "oracle",
+                   "sample": f"the full workload at K={K}: squares, PBSM, distance check "
+                             f"(Sec. 1), {secs:.3f} s, {len(ref)} pairs"}
+    rec = {
+        "metric": "input points/s", "value": round((nP + nQ) / (ms * 1e-3), 1), "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "n_p": nP, "n_q": nQ, "eps": eps,
+                   "grid_k": K, "split_tau": tau,
+                   "grid_choice": "fixed" if args.k else ("learned" if use_learned else "rule"),
+                   "partitioning": "1-D stripes" if args.stripes else "2-D grid",
+                   "mode": "count" if args.count else "pairs"},
+        "pairs_per_s": round(n / (ms * 1e-3), 1), "n_pairs": int(n), "n_candidates": int(nc),
+        "pairs_match_oracle_count": verified,
+        "median_ms_per_step": round(statistics.median(times) * 1e3, 4),
+        "roofline": roofline, "kernels": kernels, "join_stats": st, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -232,6 +334,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch256":
         return bench_batch(args, pk, sj, torch)
+    if args.workload == "distance10m":
+        return bench_distance(args, pk, sj, torch)
     log("generating", args.workload)
     R, S = inputs(args.workload)
     Rd = torch.from_numpy(R).cuda()

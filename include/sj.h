@@ -364,6 +364,49 @@ sj_status sj_generate(float* rects, int64_t n, const float* mu, const float* sig
                       float ext_a, float ext_b, uint64_t seed, uint32_t side, void* stream);
 
 /*
+ * Epsilon-distance join of two point sets (Sec. 1: a distance join between
+ * point sets reduces to the intersection join of squares of side eps
+ * centred on the points, followed by a distance check).
+ *
+ * Result: every (i, j) with dx*dx + dy*dy <= eps*eps, where dx = P[i].x -
+ * Q[j].x and dy = P[i].y - Q[j].y, evaluated in float64 from the float32
+ * values with each operation rounded once (no fused multiply-add).  The set
+ * does not depend on the grid or schedule; its order is unspecified.
+ *
+ *   P, Q       nP x 2 and nQ x 2 float32 points (x, y), device, 8-byte
+ *              aligned; every coordinate finite (else SJ_ERR_RECT).
+ *   eps        finite, >= 0 (else SJ_ERR_ARG).
+ *   g          in/out grid for the squares: when g->k is 0, k and split_tau
+ *              are chosen as by sj_choose_grid on the squares and written
+ *              back; domain and flags (SJ_PLAIN, SJ_TWO_PASS, SJ_STRIPES,
+ *              SJ_RULE_ONLY) apply as for rectangles.
+ *   out        capacity sj_pair slots (device, caller-owned), or NULL with
+ *              capacity 0: count only, nothing written, SJ_OK.
+ *   n_pairs    (host) the number of result pairs.  If out is not NULL and
+ *              the count exceeds capacity the call returns SJ_ERR_CAPACITY
+ *              and the first capacity slots hold an unspecified subset.
+ * The squares (widened by a relative 2^-44 so that rounding cannot lose a
+ * pair), their partitions and the candidate pairs live in library-owned
+ * device buffers that are reused and grown across calls.  Synchronises the
+ * stream.  Size limits as for rectangles.
+ */
+sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
+                           sj_grid* g, sj_pair* out, int64_t capacity, int64_t* n_pairs,
+                           void* stream);
+
+/* Work of the last sj_distance_join on the calling thread's current device
+ * (all zero before the first): candidate pairs of the filter (before the
+ * distance check) and the tile entries of the two partitions of squares
+ * (final and first-level, as sj_part_info and sj_part_stats report them). */
+typedef struct {
+    int64_t candidates;
+    int64_t entries_p, entries_q;
+    int64_t level1_entries_p, level1_entries_q;
+} sj_distance_info;
+
+sj_status sj_distance_last_info(sj_distance_info* info);
+
+/*
  * Opt-in per-kernel timer (tracing).  sj_prof_enable(1) clears the totals and
  * brackets every subsequent kernel launch of the library with a pair of HIP
  * events on the launch's stream; sj_prof_enable(0) stops it.  sj_prof_collect

@@ -67,6 +67,12 @@ FEAT_DIM = 2 * FEAT_SIDE
 _lib = None
 
 
+class DistanceInfo(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int64), ("entries_p", ctypes.c_int64),
+                ("entries_q", ctypes.c_int64), ("level1_entries_p", ctypes.c_int64),
+                ("level1_entries_q", ctypes.c_int64)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -134,9 +140,13 @@ def lib():
         L.sj_mlp_backward.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, vp,
                                       vp, vp]
         L.sj_mlp_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, ctypes.c_int32, vp]
+        L.sj_distance_join.argtypes = [vp, i64, vp, i64, f32, ctypes.POINTER(Grid), vp, i64,
+                                       i64p, vp]
+        L.sj_distance_last_info.argtypes = [ctypes.POINTER(DistanceInfo)]
         for f in ("sj_partition", "sj_join", "sj_join_count", "sj_part_info", "sj_part_download",
                   "sj_features", "sj_choose_grid", "sj_picker_load", "sj_mlp_forward",
-                  "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam"):
+                  "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam", "sj_distance_join",
+                  "sj_distance_last_info"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -294,6 +304,54 @@ def last_join_stats():
     st = JoinStats()
     _check(lib().sj_last_join_stats(ctypes.byref(st)), "sj_last_join_stats")
     return {f: getattr(st, f) for f, _ in JoinStats._fields_}
+
+
+def _points(t):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.dim() == 2
+            and t.shape[1] == 2 and t.is_contiguous()):
+        raise ValueError("points must be a contiguous (n, 2) float32 CUDA tensor")
+    return t
+
+
+def distance_join_into(P, Q, eps, out, grid, stream=None):
+    """sj_distance_join into `out` ((cap, 2) int32 device tensor or None for a
+    count).  grid: a Grid, updated in place when its k is 0.  Returns
+    (status, n_pairs); SJ_ERR_CAPACITY is returned, not raised."""
+    _points(P)
+    _points(Q)
+    n = ctypes.c_int64(0)
+    cap = 0 if out is None else out.shape[0]
+    s = lib().sj_distance_join(_ptr(P), P.shape[0], _ptr(Q), Q.shape[0], float(eps),
+                               ctypes.byref(grid), _ptr(out), cap, ctypes.byref(n),
+                               _stream(stream))
+    if s not in (SJ_OK, SJ_ERR_CAPACITY):
+        _check(s, "sj_distance_join")
+    return s, n.value
+
+
+def distance_join(P, Q, eps, k=0, split_tau=0, domain=None, flags=0, capacity=None,
+                  stream=None):
+    """Epsilon-distance join of two (n, 2) float32 point sets: every (i, j)
+    with |P[i] - Q[j]| <= eps, as an (M, 2) int32 device tensor (unspecified
+    order), and the grid used (dict)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    g = make_grid(k, split_tau, domain, flags)
+    cap = (1 << 16) if capacity is None else int(capacity)
+    out = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    s, n = distance_join_into(P, Q, eps, out, g, stream)
+    if s == SJ_ERR_CAPACITY:
+        out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        s, n = distance_join_into(P, Q, eps, out, g, stream)
+        _check(s, "sj_distance_join")
+    return out[:n], {"k": g.k, "split_tau": g.split_tau}
+
+
+def distance_last_info():
+    """Work of the last distance join on the current device (dict): candidate
+    pairs and the tile entries of the two partitions of squares."""
+    d = DistanceInfo()
+    _check(lib().sj_distance_last_info(ctypes.byref(d)), "sj_distance_last_info")
+    return {f: getattr(d, f) for f, _ in DistanceInfo._fields_}
 
 
 def generate(n, mu=None, sigma=None, weights=None, background=1.0, extent="lognormal",
