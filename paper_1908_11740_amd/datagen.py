@@ -31,6 +31,13 @@ Workload recipes (sizes and seeds are the defaults of the helpers below):
   seed 4000 + i, per-side sizes log-uniform in [1e6, 2e7], cluster count
   log-uniform integer in [1, 500], background uniform in [0, 0.5], extent
   median log-uniform in [1e-5, 1e-3], sigma_ln = 1.0.
+* ``anisotropic``: mixture centres as above; each rectangle is long and thin,
+  long side = median * sqrt(ratio) and short side = median / sqrt(ratio),
+  each times an independent log-normal(0, sigma_ln) factor; horizontal
+  (w long) when the centre lies left of x = 0.5, vertical right of it -- a
+  stand-in for road maps, where the better sweeping axis differs by region.
+    - anisotropic 4M case: 4,000,000 per side, 100 clusters (seed 400),
+      10% background, median 2e-4, ratio 25, sigma_ln 0.5, seeds 401 / 402.
 * points for the epsilon-distance join (Sec. 1 names it as a use of the
   intersection join): ``(n, 2)`` float32 ``(x, y)``.
     - ``points_mixture``: the centres of ``mixture`` rounded to float32.
@@ -244,3 +251,26 @@ def near_ring(n, eps, seed, ulps=4):
     r = float(eps) * (1.0 + rng.integers(-ulps, ulps + 1, n) * 2.0 ** -23)
     Q = (P.astype(np.float64) + r[:, None] * np.stack([np.cos(t), np.sin(t)], 1)).astype(np.float32)
     return P, Q
+
+
+# ----------------------------------------------------------------------------
+# Anisotropic rectangles (per-tile sweeping axis)
+# ----------------------------------------------------------------------------
+def anisotropic(n, mix, background, median, ratio, sigma_ln, seed):
+    """Mixture centres; long thin rectangles, horizontal left of x = 0.5 and
+    vertical right of it."""
+    rng = np.random.default_rng(seed)
+    n = int(n)
+    c = _centres(rng, n, mix, background)
+    r = np.sqrt(float(ratio))
+    long_ = median * r * rng.lognormal(0.0, sigma_ln, size=n)
+    short = median / r * rng.lognormal(0.0, sigma_ln, size=n)
+    horiz = c[:, 0] < 0.5
+    return _boxes(c, np.where(horiz, long_, short), np.where(horiz, short, long_))
+
+
+def anisotropic_4m(n=4_000_000):
+    """4M x 4M long thin rectangles, orientation by half of the domain."""
+    mix = mixture_spec(100, 400)
+    return (anisotropic(n, mix, 0.1, 2e-4, 25.0, 0.5, 401),
+            anisotropic(n, mix, 0.1, 2e-4, 25.0, 0.5, 402))
