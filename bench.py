@@ -29,6 +29,8 @@ WORKLOADS = {
     "skewed10m": "skewed 10M x 10M: 200-Gaussian mixture + 20% background, log-normal extents "
                  "(median 5e-5, sigma 1.0), float32",
     "uniform1m": "uniform 1M x 1M, extents U[0,2e-4], float32",
+    "aniso4m": "anisotropic 4M x 4M: 100-Gaussian mixture + 10% background, long thin rectangles "
+               "(median 2e-4, aspect 25, horizontal left of x = 0.5, vertical right of it), float32",
     "distance10m": "epsilon-distance join of skewed 10M x 10M points (centres of the skewed 10M "
                    "mixture), eps 1e-4, float32",
     "batch256": "256 independent joins, n/side log-uniform [1e3, 2e6], per-join mixture "
@@ -51,6 +53,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
     ap.add_argument("--stripes", action="store_true",
                     help="one-dimensional partitioning: K vertical stripes swept along y")
+    ap.add_argument("--sweep-x", action="store_true",
+                    help="sweep every tile along x (no per-tile sweeping-axis model)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--count", action="store_true", help="count-only join mode")
@@ -68,6 +72,8 @@ def inputs(name):
     from paper_1908_11740_amd import datagen
     if name == "skewed10m":
         return datagen.skewed_10m()
+    if name == "aniso4m":
+        return datagen.anisotropic_4m()
     return datagen.uniform_1m()
 
 
@@ -86,6 +92,7 @@ def kernel_bytes(name, w):
         "k_l2_scatter": 20 * m1 + 20 * m,
         "k_classify": 8 * w["C"] + 16 * (st["small_tiles"] + st["medium_tiles"]),
         "k_dense_sort": 40 * st["dense_entries"],
+        "k_axis": 8 * (st["medium_entries"] + st["dense_entries"]),
         "k_compact": 16 * w["P"],
     }
     if st["single_pass"]:
@@ -348,7 +355,7 @@ def main():
              "out": torch.empty((1 << 20, 2), dtype=torch.int32, device="cuda")}
 
     def step(plain):
-        stripes = sj.SJ_STRIPES if args.stripes else 0
+        stripes = (sj.SJ_STRIPES if args.stripes else 0) | (sj.SJ_SWEEP_X if args.sweep_x else 0)
         if args.k:
             K, tau = args.k, args.split_tau
         else:
@@ -466,6 +473,7 @@ def main():
                    "grid_choice": "fixed" if args.k else ("learned" if use_learned and main_mode == "tuned"
                                                           and not args.stripes else "rule"),
                    "partitioning": "1-D stripes" if args.stripes else "2-D grid",
+                   "sweep_axis": "y" if args.stripes else ("x" if args.sweep_x else "per-tile model"),
                    "schedule": main_mode, "mode": "count" if args.count else "pairs",
                    "autotuned": r["tuning"]},
         "pairs_per_s": round(P / (ms * 1e-3), 1),

@@ -79,6 +79,10 @@ typedef enum {
                                    duplicate test of Eq. (1) reduces to the reference point's
                                    x (Sec. 3.2).  sj_choose_grid's rule then uses the mean
                                    x-extent (Sec. 4.3.1)                                   */
+#define SJ_SWEEP_X 0x10u        /* sj_join: sweep every tile along x.  Without it, tiles
+                                   joined as medium or dense work units choose their
+                                   sweeping axis with the model of Sec. 3.3 (Eq. (2));
+                                   never changes the result                                */
 
 /*
  * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.3.2).
@@ -92,7 +96,7 @@ typedef enum {
  *   domain     x0, y0, x1, y1 of the gridded region; all zero = the unit
  *              square [0,1)^2 (the paper normalises data to [0,1], Sec. 4.1).
  *              Rectangles outside it are clamped into the border tiles.
- *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS, SJ_STRIPES.
+ *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS, SJ_STRIPES, SJ_SWEEP_X.
  * Tile (tx, ty) holds the rectangles whose cell ranges
  * [cell(x_l), cell(x_u)] x [cell(y_l), cell(y_u)] contain it, with
  * cell(v) = clamp(floor((v - x0) * K / (x1 - x0)), 0, K - 1) in float32.
@@ -244,6 +248,10 @@ sj_status sj_batch_join(int32_t n_joins, const float* const* R, const int64_t* n
  * into LDS units), medium (one workgroup each) and dense (sorted in global
  * memory, swept in pivot ranges).  The plain schedule classifies no tiles
  * (its per-tile fields are 0).  pairs_* are -1 unless single_pass.
+ * small_cap and med_cap are the class bounds used (small: n <= small_cap,
+ * medium: n <= med_cap).  axis_tiles counts the tiles that evaluated the
+ * sweeping-axis model (the medium and dense ones, unless SJ_SWEEP_X, the
+ * plain schedule or stripes), axis_y those of them swept along y.
  */
 typedef struct {
     int64_t n_pairs;
@@ -251,9 +259,32 @@ typedef struct {
     int64_t small_entries, medium_entries, dense_entries;
     int64_t pairs_small, pairs_medium, pairs_dense;
     int32_t single_pass;
+    int32_t small_cap, med_cap;
+    int64_t axis_tiles, axis_y;
 } sj_join_stats;
 
 sj_status sj_last_join_stats(sj_join_stats* out);
+
+/*
+ * The sweeping-axis model of Sec. 3.3 for chosen tiles of two partitioned
+ * inputs (the join evaluates the same model on its medium and dense tiles).
+ * Per axis, the tile is cut into k divisions and I = sum_i H_R[i] * H_S[i]
+ * (Eq. (2)) over histograms of the sampled rectangles meeting each division;
+ * the sweep runs along y when I^y < I^x.  Sample: the rectangles whose input
+ * index is a multiple of 100.  k: clamp(floor(tile extent / mean extent of
+ * the tile's sampled rectangles), 1, 1000), the mean of (w + h) / 2 in cell
+ * units with w, h clipped to 2 cells and summed in fixed point (2^-30).
+ * Division of v in tile column t: clamp(floor(fl(fl(u - t) * k)), 0, k-1),
+ * u = fl(fl(v - x0) * sx) the float32 cell coordinate.  A tile whose sample
+ * misses R or S reports k = 0, I^x = I^y = 0 and axis x.
+ *   R, S     partitions on the same 2-D grid (not SJ_STRIPES), else
+ *            SJ_ERR_GRID_MISMATCH / SJ_ERR_ARG.
+ *   tiles    host, n x (tx, ty) int32 with 0 <= tx, ty < k, else SJ_ERR_ARG.
+ *   out      host, n x (k, I^x, I^y, axis) int64; axis 1 = y.
+ * Synchronises the stream.
+ */
+sj_status sj_sweep_axis(const sj_part* R, const sj_part* S, const int32_t* tiles, int64_t n,
+                        int64_t* out, void* stream);
 
 /*
  * Choosing the grid (statistics rule of Sec. 4.3.1 / 4.3.3, or the learned

@@ -58,7 +58,9 @@ enum Ctr : int {
     kDenseUnits = 5,
     kSmallEntries = 6,  // statistics: entries of the small and medium tiles
     kMedEntries = 7,
-    kNumCtr = 8
+    kAxisTiles = 8,     // statistics: tiles that evaluated the sweeping-axis model ...
+    kAxisY = 9,         // ... and those of them swept along y
+    kNumCtr = 10
 };
 
 constexpr int kWaveBuf = 256;        // staged pairs per wave (>= 64 lanes x kCand)
@@ -105,7 +107,17 @@ struct Args {
     unsigned long long* sc_total; // [kTotals] hit totals
     int64_t sc_nch;               // chunks per region
     int cls;                      // work class of the launch (pair totals per class)
+    uint32_t* medt;               // blocked tile index of each medium tile (axis model)
+    int axis_model;               // medium / dense tiles choose their sweeping axis
+    GridDev gd;                   // grid and blocking of the two partitions
+    Blocking bl;
 };
+
+// A medium or dense tile record carries its sweeping axis in bit 31 of one
+// field (set by k_axis): medium (R start, nr | axis, S start, ns), dense
+// (tile | axis, base, nr, ns).  Counts and blocked tile indices stay below
+// 2^31.
+constexpr uint32_t kAxisBit = 0x80000000u;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
@@ -465,9 +477,14 @@ __device__ __forceinline__ int seg_rank(const uint32_t* key, int lo, int hi, int
 // prefetch() runs once the unit's entries have arrived: the caller issues
 // the loads of its next unit there, so they overlap this unit's sort and
 // sweep.
+//
+// swap: the unit is one tile swept along y (sweeping-axis model): every box
+// is taken with x and y exchanged, so the sort and the sweep below run along
+// y; the write-back exchanges them again.  The duplicate test of Eq. (1) is
+// symmetric in x and y, so the pairs reported do not change.
 template <int NT, int Q, int TC, int MODE, class TileOf, class Prefetch>
 __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const TileOf& tile_of,
-                             const Prefetch& prefetch, Sink<MODE, true>& sk) {
+                             const Prefetch& prefetch, Sink<MODE, true>& sk, bool swap = false) {
     constexpr int E = NT * Q;
     const int tid = threadIdx.x;
     if (c > TC) {  // more tiles than the LDS tile table holds: cannot happen
@@ -600,6 +617,10 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
             pg[q] = g;
         }
     }
+    if (swap) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) pb[q] = make_float4(pb[q].y, pb[q].x, pb[q].w, pb[q].z);
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int e = tid + q * NT;
@@ -694,7 +715,8 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
         for (int q = 0; q < Q; ++q) {
             const int e = tid + q * NT;
             if (MODE == kCount && a.writeback && e < NE) {
-                const float4 b = L.bx[e];
+                float4 b = L.bx[e];
+                if (swap) b = make_float4(b.y, b.x, b.w, b.z);
                 if (e < NR) {
                     a.entR[pg[q]].b = b;
                     a.entR[pg[q]].m = make_uint4(L.id[e], 0u, 0u, 0u);
@@ -1295,7 +1317,10 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
     uint32_t mrank = s_ws[2][w] + im - nmed;
 #pragma unroll
     for (int q = 0; q < kClassPer; ++q) {
-        if (cls[q] == 2) a.med[mb + mrank++] = ti[q];
+        if (cls[q] == 2) {
+            if (a.axis_model) a.medt[mb + mrank] = (uint32_t)(t0 + q);
+            a.med[mb + mrank++] = ti[q];
+        }
         if (cls[q] == 1) {
             a.tinfo[tb + rank] = ti[q];
             const uint32_t u = s_uidx[rank];
@@ -1310,6 +1335,243 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
                 a.units[ub + u] = make_uint2(tb + rank, lo - rank + 1);
             }
             ++rank;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sweeping-axis model (Sec. 3.3, Eq. (2)) of one tile, evaluated by one
+// workgroup of kAxisNT threads.  Sample: the entries whose rectangle index is
+// a multiple of phi = 100.  k divisions per tile extent, k = clamp(floor(
+// tile extent / mean sampled extent), 1, 1000), the mean of (w + h) / 2 in
+// cell units from fixed-point sums (2^-30 of a cell, w and h clipped to 2
+// cells), so it does not depend on the order of the tile's list.  Per axis
+// and side a histogram counts the sampled rectangles meeting each division
+// (difference array in LDS, then a prefix sum); I = sum_i H_R[i] * H_S[i].
+// ---------------------------------------------------------------------------
+constexpr int kAxisNT = 256;
+constexpr uint32_t kAxisPhi = 100;
+constexpr int kAxisKMax = 1000;
+constexpr int kAxisPer = (kAxisKMax + kAxisNT - 1) / kAxisNT;  // divisions per thread
+
+struct AxisLds {
+    int hist[4][kAxisKMax + 1];  // difference arrays: R x, R y, S x, S y
+    int wsum[kAxisNT / kWave][4];
+    unsigned long long red[kAxisNT / kWave][2];
+    uint32_t cnt[kAxisNT / kWave][2];
+};
+
+struct AxisOut {
+    int k;
+    unsigned long long ix, iy;
+};
+
+// extent hi - lo in cell units, clipped to 2 cells, in units of 2^-30 cell
+__device__ __forceinline__ unsigned long long fixed_extent(float lo, float hi, float scale) {
+    const float e = fminf(__fmul_rn(__fsub_rn(hi, lo), scale), 2.0f);
+    return (unsigned long long)__fmul_rn(e, 1073741824.0f);  // exact scaling; truncation = floor
+}
+
+// division of coordinate v in tile column t
+__device__ __forceinline__ int division(float v, float origin, float scale, int t, int k) {
+    const float u = __fmul_rn(__fsub_rn(v, origin), scale);
+    float f = floorf(__fmul_rn(__fsub_rn(u, (float)t), (float)k));
+    f = fminf(fmaxf(f, 0.0f), (float)(k - 1));
+    return (int)f;
+}
+
+__device__ __forceinline__ void blocked_xy(const Blocking& bl, uint32_t t, int& tx, int& ty) {
+    const uint32_t B2 = (uint32_t)bl.tiles_per_cell();
+    const uint32_t cell = t / B2, r = t % B2;
+    tx = (int)(cell % (uint32_t)bl.Gx) * bl.Bx + (int)(r % (uint32_t)bl.Bx);
+    ty = (int)(cell / (uint32_t)bl.Gx) * bl.By + (int)(r / (uint32_t)bl.Bx);
+}
+
+__device__ AxisOut axis_eval(const Entry* __restrict__ eR, uint32_t nr, const Entry* __restrict__ eS,
+                             uint32_t ns, int tx, int ty, const GridDev& g, AxisLds& L) {
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    constexpr int NW = kAxisNT / kWave;
+    const uint32_t n = nr + ns;
+    // A. sample sizes and fixed-point extent sum
+    uint32_t cR = 0, cS = 0;
+    unsigned long long ext = 0;
+    for (uint32_t i = tid; i < n; i += kAxisNT) {
+        const bool isR = i < nr;
+        const Entry* e = isR ? eR + i : eS + (i - nr);
+        if ((e->m.x & kIdMask) % kAxisPhi == 0u) {
+            const float4 b = e->b;
+            ext += fixed_extent(b.x, b.z, g.sx) + fixed_extent(b.y, b.w, g.sy);
+            if (isR) ++cR;
+            else ++cS;
+        }
+    }
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        cR += __shfl_xor(cR, d, kWave);
+        cS += __shfl_xor(cS, d, kWave);
+        ext += __shfl_xor(ext, d, kWave);
+    }
+    if (lane == 0) {
+        L.cnt[w][0] = cR;
+        L.cnt[w][1] = cS;
+        L.red[w][0] = ext;
+    }
+    __syncthreads();
+    uint32_t nRs = 0, nSs = 0;
+    unsigned long long tot = 0;
+    for (int q = 0; q < NW; ++q) {
+        nRs += L.cnt[q][0];
+        nSs += L.cnt[q][1];
+        tot += L.red[q][0];
+    }
+    __syncthreads();
+    AxisOut o{0, 0ull, 0ull};
+    if (nRs == 0 || nSs == 0) return o;  // the same for every thread
+    int k = kAxisKMax;
+    if (tot) {
+        const unsigned long long q = ((2ull * (nRs + nSs)) << 30) / tot;
+        k = q < 1ull ? 1 : (q > (unsigned long long)kAxisKMax ? kAxisKMax : (int)q);
+    }
+    // B. difference arrays of the four histograms
+    for (int i = tid; i < 4 * (kAxisKMax + 1); i += kAxisNT) (&L.hist[0][0])[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kAxisNT) {
+        const bool isR = i < nr;
+        const Entry* e = isR ? eR + i : eS + (i - nr);
+        if ((e->m.x & kIdMask) % kAxisPhi == 0u) {
+            const float4 b = e->b;
+            int* hx = L.hist[isR ? 0 : 2];
+            int* hy = L.hist[isR ? 1 : 3];
+            atomicAdd(&hx[division(b.x, g.x0, g.sx, tx, k)], 1);
+            atomicAdd(&hx[division(b.z, g.x0, g.sx, tx, k) + 1], -1);
+            atomicAdd(&hy[division(b.y, g.y0, g.sy, ty, k)], 1);
+            atomicAdd(&hy[division(b.w, g.y0, g.sy, ty, k) + 1], -1);
+        }
+    }
+    __syncthreads();
+    // C. prefix sums over the divisions (thread j owns kAxisPer of them) and
+    //    the products of Eq. (2)
+    const int d0 = tid * kAxisPer;
+    int part[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kAxisPer; ++q) {
+        const int d = d0 + q;
+        if (d < k) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) part[h] += L.hist[h][d];
+        }
+    }
+    int inc[4] = {part[0], part[1], part[2], part[3]};
+    for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int t = __shfl_up(inc[h], d, kWave);
+            if (lane >= d) inc[h] += t;
+        }
+    }
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) L.wsum[w][h] = inc[h];
+    }
+    __syncthreads();
+    int run[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        run[h] = inc[h] - part[h];
+        for (int q = 0; q < w; ++q) run[h] += L.wsum[q][h];
+    }
+    unsigned long long ix = 0, iy = 0;
+#pragma unroll
+    for (int q = 0; q < kAxisPer; ++q) {
+        const int d = d0 + q;
+        if (d < k) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) run[h] += L.hist[h][d];
+            ix += (unsigned long long)run[0] * (unsigned long long)run[2];
+            iy += (unsigned long long)run[1] * (unsigned long long)run[3];
+        }
+    }
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        ix += __shfl_xor(ix, d, kWave);
+        iy += __shfl_xor(iy, d, kWave);
+    }
+    if (lane == 0) {
+        L.red[w][0] = ix;
+        L.red[w][1] = iy;
+    }
+    __syncthreads();
+    o.k = k;
+    for (int q = 0; q < NW; ++q) {
+        o.ix += L.red[q][0];
+        o.iy += L.red[q][1];
+    }
+    __syncthreads();
+    return o;
+}
+
+// The join's medium and dense tiles: evaluate the model, mark the tiles to
+// sweep along y (bit 31 of the record), count both.
+__global__ __launch_bounds__(kAxisNT) void k_axis(Args a) {
+    __shared__ AxisLds L;
+    const uint32_t nm = min(a.ctr[kMedCount], (uint32_t)a.cap_med);
+    const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
+    uint32_t nt = 0, ny = 0;
+    for (uint32_t j = blockIdx.x; j < nm + nd; j += gridDim.x) {
+        const bool med = j < nm;
+        const uint4 rec = med ? a.med[j] : a.dense[j - nm];
+        uint32_t t, nr, ns;
+        const Entry *eR, *eS;
+        if (med) {
+            t = a.medt[j];
+            eR = a.entR + rec.x;
+            nr = rec.y;
+            eS = a.entS + rec.z;
+            ns = rec.w;
+        } else {
+            t = rec.x;
+            eR = a.entR + a.offR[t];
+            nr = rec.z;
+            eS = a.entS + a.offS[t];
+            ns = rec.w;
+        }
+        int tx, ty;
+        blocked_xy(a.bl, t, tx, ty);
+        const AxisOut o = axis_eval(eR, nr, eS, ns, tx, ty, a.gd, L);
+        if (threadIdx.x == 0) {
+            ++nt;
+            if (o.iy < o.ix) {
+                ++ny;
+                if (med) a.med[j].y = rec.y | kAxisBit;
+                else a.dense[j - nm].x = rec.x | kAxisBit;
+            }
+        }
+    }
+    if (threadIdx.x == 0 && nt) {
+        atomicAdd(&a.ctr[kAxisTiles], nt);
+        if (ny) atomicAdd(&a.ctr[kAxisY], ny);
+    }
+}
+
+// The model for listed tiles (sj_sweep_axis).
+__global__ __launch_bounds__(kAxisNT) void k_axis_query(const uint32_t* __restrict__ offR,
+                                                        const uint32_t* __restrict__ offS,
+                                                        const Entry* __restrict__ entR,
+                                                        const Entry* __restrict__ entS, GridDev gd,
+                                                        Blocking bl, const int2* __restrict__ tiles,
+                                                        int64_t n, long long* __restrict__ out) {
+    __shared__ AxisLds L;
+    for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const int2 xy = tiles[j];
+        const uint32_t cell = (uint32_t)(xy.y / bl.By) * (uint32_t)bl.Gx + (uint32_t)(xy.x / bl.Bx);
+        const uint32_t t = cell * (uint32_t)bl.tiles_per_cell() +
+                           (uint32_t)(xy.y % bl.By) * (uint32_t)bl.Bx + (uint32_t)(xy.x % bl.Bx);
+        const uint32_t r0 = offR[t], s0 = offS[t];
+        const AxisOut o =
+            axis_eval(entR + r0, offR[t + 1] - r0, entS + s0, offS[t + 1] - s0, xy.x, xy.y, gd, L);
+        if (threadIdx.x == 0) {
+            out[4 * j] = o.k;
+            out[4 * j + 1] = (long long)o.ix;
+            out[4 * j + 2] = (long long)o.iy;
+            out[4 * j + 3] = o.iy < o.ix ? 1 : 0;
         }
     }
 }
@@ -1349,7 +1611,13 @@ __global__ __launch_bounds__(NT) void k_lds_units(Args a) {
     }
     for (uint32_t u = blockIdx.x; u < nu; u += G) {
         const int64_t slot = MEDIUM ? a.base_med + u : (int64_t)u;
-        const uint4 c0 = pf0, c1 = pf1, c2 = pf2;
+        uint4 c0 = pf0;
+        const uint4 c1 = pf1, c2 = pf2;
+        bool swap = false;
+        if (MEDIUM) {  // sweeping axis of the tile in bit 31 of its R count
+            swap = (c0.y & kAxisBit) != 0;
+            c0.y &= ~kAxisBit;
+        }
         const int c = MEDIUM ? 1 : (int)ud.y;
         const uint4* tl = a.tinfo + ud.x;
         // chunk j of the table: thread tid asks for its own tile k = tid + j * NT
@@ -1372,7 +1640,7 @@ __global__ __launch_bounds__(NT) void k_lds_units(Args a) {
             }
         };
         sk.begin(a, slot);
-        run_lds_unit<NT, Q, TC, MODE>(a, L, c, tile_of, prefetch, sk);
+        run_lds_unit<NT, Q, TC, MODE>(a, L, c, tile_of, prefetch, sk, swap);
         sk.end(a, slot);
         if (!MEDIUM) {
             const uint2 t = ud_next;
@@ -1430,13 +1698,17 @@ __device__ void bitonic_lds(unsigned long long* k, int P) {
     }
 }
 
+__device__ __forceinline__ float lower_edge(const float4& b, bool y) { return y ? b.y : b.x; }
+
 __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
     __shared__ unsigned long long keys[kDenseSortMax];
     const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
     for (uint32_t seg = blockIdx.x; seg < 2 * nd; seg += gridDim.x) {
         const uint4 dd = a.dense[seg >> 1];
         const bool sideS = seg & 1;
-        const uint32_t src = sideS ? a.offS[dd.x] : a.offR[dd.x];
+        const bool swap = (dd.x & kAxisBit) != 0;  // swept along y: sort by y_l
+        const uint32_t tile = dd.x & ~kAxisBit;
+        const uint32_t src = sideS ? a.offS[tile] : a.offR[tile];
         const uint32_t L = sideS ? dd.w : dd.z;
         const uint32_t dst = dd.y + (sideS ? dd.z : 0u);
         const Entry* ent = sideS ? a.entS : a.entR;
@@ -1446,7 +1718,8 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             while (P < (int)L) P <<= 1;
             for (int i = threadIdx.x; i < P; i += blockDim.x)
                 keys[i] = i < (int)L
-                              ? ((unsigned long long)order_key(ent[src + i].b.x) << 32) | (uint32_t)i
+                              ? ((unsigned long long)order_key(lower_edge(ent[src + i].b, swap)) << 32) |
+                                    (uint32_t)i
                               : ~0ull;
             __syncthreads();
             bitonic_lds(keys, P);
@@ -1460,7 +1733,8 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             for (uint32_t c0 = 0; c0 < L; c0 += kDenseSortMax) {
                 const int n = (int)min((uint32_t)kDenseSortMax, L - c0);
                 for (int i = threadIdx.x; i < kDenseSortMax; i += blockDim.x)
-                    keys[i] = i < n ? ((unsigned long long)order_key(ent[src + c0 + i].b.x) << 32) |
+                    keys[i] = i < n ? ((unsigned long long)order_key(lower_edge(ent[src + c0 + i].b, swap))
+                                       << 32) |
                                           (c0 + (uint32_t)i)
                                     : ~0ull;
                 __syncthreads();
@@ -1501,7 +1775,8 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
         }
         for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
             const uint32_t q = (uint32_t)fin[i];
-            a.dbox[dst + i] = ent[src + q].b;
+            const float4 b = ent[src + q].b;
+            a.dbox[dst + i] = swap ? make_float4(b.y, b.x, b.w, b.z) : b;
             a.didf[dst + i] = ent[src + q].m.x;
         }
         __syncthreads();
@@ -1818,6 +2093,10 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     a.capacity = out ? capacity : 0;
     const bool single = p.single && !p.plain && !p.count_only && w.sc_nch > 0;
     a.writeback = (!single && !p.count_only) ? 1 : 0;
+    a.axis_model = (p.axis_model && !p.plain) ? 1 : 0;
+    a.medt = w.medt;
+    a.gd = R.gd;
+    a.bl = R.bl;
     if (single) {
         a.sc_buf = w.sc_buf;
         a.sc_fills = w.sc_fills;
@@ -1842,6 +2121,10 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
         ProfRange pr("k_classify", s);
         hipLaunchKernelGGL(k_classify, dim3((unsigned)classify_blocks(p.C)), dim3(kClassNT), 0, s,
                            a);
+    }
+    if (a.axis_model) {
+        ProfRange pr("k_axis", s);
+        hipLaunchKernelGGL(k_axis, dim3(w.num_cus * 4), dim3(kAxisNT), 0, s, a);
     }
     {
         ProfRange pr("k_dense_sort", s);
@@ -1909,7 +2192,18 @@ hipError_t join_stats(const JoinWork& w, bool single, sj_join_stats* o) {
     o->pairs_small = pc[0];
     o->pairs_medium = pc[1];
     o->pairs_dense = pc[2];
+    o->axis_tiles = c[kAxisTiles];
+    o->axis_y = c[kAxisY];
     return hipSuccess;
+}
+
+hipError_t axis_query(const Part& R, const Part& S, const int32_t* tiles, int64_t n, int64_t* out,
+                      int num_cus, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(n, (int64_t)num_cus * 8);
+    hipLaunchKernelGGL(k_axis_query, dim3(g), dim3(kAxisNT), 0, s, R.off, S.off, R.ent, S.ent, R.gd,
+                       R.bl, (const int2*)tiles, n, (long long*)out);
+    return hipGetLastError();
 }
 
 int scratch_regions() { return kRegions; }

@@ -177,6 +177,8 @@ JoinParams join_params(const sj_grid& g, bool count_only) {
     p.split_tau = g.split_tau > 0 ? g.split_tau : 256;
     if (p.plain || g.split_tau == INT32_MAX) p.split_tau = INT32_MAX;
     p.single = !p.plain && !count_only && (g.flags & SJ_TWO_PASS) == 0;
+    // the model picks between x and y; stripes sweep along y by construction
+    p.axis_model = !p.plain && (g.flags & (SJ_SWEEP_X | SJ_STRIPES)) == 0;
     return p;
 }
 
@@ -212,6 +214,7 @@ sj_status join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_
         if ((e = grow(w.tinfo, w.cap_tiles, active)) != hipSuccess) return from_hip(e);
         if ((e = grow(w.units, w.cap_units, p.units_bound)) != hipSuccess) return from_hip(e);
         if ((e = grow(w.med, w.cap_med, p.med_bound)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.medt, w.cap_medt, w.cap_med)) != hipSuccess) return from_hip(e);
     }
     if ((e = grow(w.dense, w.cap_dense, ndense)) != hipSuccess) return from_hip(e);
     w.cap_dunits = std::max<int64_t>(
@@ -324,6 +327,8 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
         }
         hs = *ds->host;
         w.last_single = p.single;
+        w.last_small_cap = p.plain ? 0 : p.small_cap;
+        w.last_med_cap = p.plain ? 0 : p.med_cap;
         // the scratch of the single pass ran out although the output fits:
         // join again in two passes
         if (p.single && (hs.flags & kStatScratch) && !(hs.flags & ~kStatScratch) &&
@@ -634,7 +639,40 @@ sj_status sj_last_join_stats(sj_join_stats* out) {
     if (join_stats(w, w.last_single, out) != hipSuccess) return SJ_ERR_DEVICE;
     out->n_pairs = (int64_t)it->second.host->n_pairs;
     out->single_pass = w.last_single ? 1 : 0;
+    out->small_cap = w.last_small_cap;
+    out->med_cap = w.last_med_cap;
     return SJ_OK;
+}
+
+sj_status sj_sweep_axis(const sj_part* R, const sj_part* S, const int32_t* tiles, int64_t n,
+                        int64_t* out, void* stream) {
+    if (!R || !S || n < 0 || (n > 0 && (!tiles || !out))) return SJ_ERR_ARG;
+    if (!same_grid(R->grid, S->grid)) return SJ_ERR_GRID_MISMATCH;
+    if (R->device != S->device || (R->grid.flags & SJ_STRIPES)) return SJ_ERR_ARG;
+    const int K = R->grid.k;
+    for (int64_t j = 0; j < n; ++j)
+        if (tiles[2 * j] < 0 || tiles[2 * j] >= K || tiles[2 * j + 1] < 0 || tiles[2 * j + 1] >= K)
+            return SJ_ERR_ARG;
+    if (n == 0) return SJ_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceState* ds = nullptr;
+    sj_status st = device_state(R->device, &ds);
+    if (st != SJ_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t* dt = nullptr;
+    int64_t* dout = nullptr;
+    hipError_t e = hipMalloc((void**)&dt, (size_t)n * 2 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&dout, (size_t)n * 4 * sizeof(int64_t));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dt, tiles, (size_t)n * 2 * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = axis_query(*R, *S, dt, n, dout, ds->w.num_cus, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, dout, (size_t)n * 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (dt) (void)hipFree(dt);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess) set_err("sweep axis", e);
+    return from_hip(e);
 }
 
 }  // extern "C"

@@ -147,6 +147,7 @@ struct JoinParams {
     bool plain;      // one workgroup per tile, no batching, no splitting
     bool count_only;
     bool single;     // one sweep into scratch chunks + compaction (else count, scan, write)
+    bool axis_model; // medium and dense tiles choose their sweeping axis (Eq. (2))
 };
 
 struct JoinWork {
@@ -156,6 +157,8 @@ struct JoinWork {
     uint2* units = nullptr;         // [cap_units] (first index into tinfo, count)
     uint4* med = nullptr;           // [cap_med] medium-tile segments
     int64_t cap_med = 0;
+    uint32_t* medt = nullptr;       // [cap_medt] blocked tile index of each medium tile
+    int64_t cap_medt = 0;
     uint4* dense = nullptr;         // [cap_dense] (tile, base in dense buffer, nr, ns)
     uint32_t* dense_unit_prefix = nullptr;  // [cap_dense+1]
     int64_t cap_tiles = 0, cap_units = 0, cap_dense = 0, cap_prefix = 0, cap_dunits = 0;
@@ -179,6 +182,7 @@ struct JoinWork {
     unsigned long long* sc_total = nullptr;  // [scratch_totals()] pair totals
     int64_t sc_nch = 0;
     bool last_single = false;       // the last join ran in one pass
+    int last_small_cap = 0, last_med_cap = 0;  // class bounds of the last join
     uint32_t* ctr = nullptr;
     DevStatus* st = nullptr;
     void* host_status = nullptr;    // pinned DevStatus mirror
@@ -189,6 +193,10 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
                     sj_pair* out, int64_t capacity, hipStream_t s);
 int64_t join_slots(const JoinParams& p, const JoinWork& w);
 hipError_t join_stats(const JoinWork& w, bool single, sj_join_stats* out);
+// Eq. (2) for the listed tiles (device: n x (tx, ty) int32 in, n x 4 int64
+// out: divisions k, I^x, I^y, axis) on the grid of R and S.
+hipError_t axis_query(const Part& R, const Part& S, const int32_t* tiles, int64_t n, int64_t* out,
+                      int num_cus, hipStream_t s);
 int scratch_regions();
 int scratch_chunk_pairs();
 int scratch_totals();

@@ -27,6 +27,7 @@ SJ_PLAIN = 0x1
 SJ_RULE_ONLY = 0x2
 SJ_TWO_PASS = 0x4
 SJ_STRIPES = 0x8
+SJ_SWEEP_X = 0x10
 INT32_MAX = 2**31 - 1
 
 
@@ -58,7 +59,9 @@ class JoinStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in (
         "n_pairs", "small_tiles", "small_units", "medium_tiles", "dense_tiles", "dense_units",
         "small_entries", "medium_entries", "dense_entries", "pairs_small", "pairs_medium",
-        "pairs_dense")] + [("single_pass", ctypes.c_int32)]
+        "pairs_dense")] + [("single_pass", ctypes.c_int32), ("small_cap", ctypes.c_int32),
+                           ("med_cap", ctypes.c_int32), ("axis_tiles", ctypes.c_int64),
+                           ("axis_y", ctypes.c_int64)]
 
 
 FEAT_SIDE = 1029
@@ -140,12 +143,13 @@ def lib():
         L.sj_mlp_backward.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp, vp, vp,
                                       vp, vp]
         L.sj_mlp_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, ctypes.c_int32, vp]
+        L.sj_sweep_axis.argtypes = [vp, vp, vp, i64, vp, vp]
         L.sj_distance_join.argtypes = [vp, i64, vp, i64, f32, ctypes.POINTER(Grid), vp, i64,
                                        i64p, vp]
         L.sj_distance_last_info.argtypes = [ctypes.POINTER(DistanceInfo)]
         for f in ("sj_partition", "sj_join", "sj_join_count", "sj_part_info", "sj_part_download",
                   "sj_features", "sj_choose_grid", "sj_picker_load", "sj_mlp_forward",
-                  "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam", "sj_distance_join",
+                  "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam", "sj_distance_join", "sj_sweep_axis",
                   "sj_distance_last_info"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -352,6 +356,18 @@ def distance_last_info():
     d = DistanceInfo()
     _check(lib().sj_distance_last_info(ctypes.byref(d)), "sj_distance_last_info")
     return {f: getattr(d, f) for f, _ in DistanceInfo._fields_}
+
+
+def sweep_axis(R, S, tiles, stream=None):
+    """The sweeping-axis model (Sec. 3.3, Eq. (2)) for tiles (n, 2) int (tx, ty):
+    an (n, 4) int64 array of (k, I^x, I^y, axis), axis 1 = y."""
+    import numpy as np
+    t = np.ascontiguousarray(tiles, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros((len(t), 4), dtype=np.int64)
+    _check(lib().sj_sweep_axis(R.handle, S.handle, t.ctypes.data_as(ctypes.c_void_p), len(t),
+                               out.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+           "sj_sweep_axis")
+    return out
 
 
 def generate(n, mu=None, sigma=None, weights=None, background=1.0, extent="lognormal",
