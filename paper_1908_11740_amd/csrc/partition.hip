@@ -327,6 +327,152 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ 
     if (err) atomicOr(&st->flags, err);
 }
 
+// Level-2 scatter with the chunk's output staged in LDS.  Scattered 32-byte
+// stores run at well under half of HBM speed on this GPU, so a chunk's tile
+// entries are first ranked in LDS (8 bytes each: destination, and the source
+// position in the chunk with the two start bits), then written out in
+// destination order, so that consecutive lanes store consecutive entries of
+// a tile's sub-segment; the boxes are re-read from the chunk, which the
+// first pass has just brought into L2.  A chunk whose output exceeds the
+// stage takes the direct path of k_l2_scatter.
+constexpr int kStage = 6144;          // staged entries per chunk
+constexpr int kStageMaxB2 = 2048;     // tiles per coarse cell the staged kernel handles
+constexpr int kStagePer = kStageMaxB2 / kL1NT;
+
+__global__ __launch_bounds__(kL1NT) void k_l2_scatter_staged(
+    const Entry* __restrict__ e1, const uint32_t* __restrict__ o1, int64_t nb1,
+    const uint32_t* __restrict__ cp, const uint32_t* __restrict__ chunk_cell, GridDev g, Blocking bl,
+    const uint32_t* __restrict__ o2, Entry* __restrict__ ent, int64_t cap_m,
+    DevStatus* __restrict__ st) {
+    __shared__ uint32_t s_dst[kStage];   // destination of each staged entry
+    __shared__ uint32_t s_src[kStage];   // source position in the chunk | start bits
+    __shared__ uint32_t lcur[kStageMaxB2];  // staging cursor per tile
+    __shared__ uint32_t goff[kStageMaxB2];  // global minus staging offset per tile
+    __shared__ uint32_t s_wsum[kL1NT / kWave];
+    __shared__ uint32_t s_total;
+    if (aborted(st)) return;
+    const int B2 = bl.tiles_per_cell();
+    const uint32_t nchunks = st->n_chunks;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    // the scan leaves the total in the status word, not after the last count
+    const uint32_t last = (uint32_t)B2 * nchunks, m_total = (uint32_t)st->m_total;
+    uint32_t err = 0;
+    for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+        const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
+        // per-tile counts of this chunk from the scanned level-2 histogram
+        uint32_t gb[kStagePer], cnt[kStagePer], sum = 0;
+#pragma unroll
+        for (int u = 0; u < kStagePer; ++u) {
+            const int t = tid * kStagePer + u;
+            gb[u] = 0;
+            cnt[u] = 0;
+            if (t < B2) {
+                const uint32_t idx = k.h2base + (uint32_t)t * k.nch + k.c;
+                gb[u] = o2[idx];
+                cnt[u] = (idx + 1 < last ? o2[idx + 1] : m_total) - gb[u];
+            }
+            sum += cnt[u];
+        }
+        uint32_t inc = sum;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += t;
+        }
+        if (lane == kWave - 1) s_wsum[w] = inc;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t a = 0;
+            for (int i = 0; i < kL1NT / kWave; ++i) {
+                const uint32_t v = s_wsum[i];
+                s_wsum[i] = a;
+                a += v;
+            }
+            s_total = a;
+        }
+        __syncthreads();
+        const uint32_t total = s_total;
+        if (total > (uint32_t)kStage) {
+            // direct path: each entry straight to its tile's next slot
+            for (int u = 0; u < kStagePer; ++u) {
+                const int t = tid * kStagePer + u;
+                if (t < B2) lcur[t] = gb[u];
+            }
+            __syncthreads();
+            for (uint32_t e = k.e0 + tid; e < k.e1; e += kL1NT) {
+                const float4 a = e1[e].b;
+                const uint32_t id = e1[e].m.x;
+                const Cells c = cells_of(a, g);
+                const Local l = local_range(c, k, bl);
+                const int bx = k.gx * bl.Bx, by = k.gy * bl.By;
+                for (int y = l.y0; y <= l.y1; ++y) {
+                    const uint32_t fy = (by + y == c.cy0) ? kBy : 0u;
+                    for (int x = l.x0; x <= l.x1; ++x) {
+                        const uint32_t slot = atomicAdd(&lcur[y * bl.Bx + x], 1u);
+                        if ((int64_t)slot >= cap_m) {
+                            err |= kStatCapacity;
+                            continue;
+                        }
+                        ent[slot].b = a;
+                        ent[slot].m = make_uint4(id | fy | ((bx + x == c.cx0) ? kBx : 0u), 0u, 0u, 0u);
+                    }
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        {
+            uint32_t run = s_wsum[w] + inc - sum;
+#pragma unroll
+            for (int u = 0; u < kStagePer; ++u) {
+                const int t = tid * kStagePer + u;
+                if (t < B2) {
+                    lcur[t] = run;
+                    goff[t] = gb[u] - run;  // modular: goff + staged index = destination
+                }
+                run += cnt[u];
+            }
+        }
+        __syncthreads();
+        // rank every tile entry of the chunk in LDS
+        uint32_t e = k.e0 + tid;
+        float4 nb = e < k.e1 ? e1[e].b : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (; e < k.e1; e += kL1NT) {
+            const float4 a = nb;
+            if (e + kL1NT < k.e1) nb = e1[e + kL1NT].b;
+            const Cells c = cells_of(a, g);
+            const Local l = local_range(c, k, bl);
+            const int bx = k.gx * bl.Bx, by = k.gy * bl.By;
+            for (int y = l.y0; y <= l.y1; ++y) {
+                const uint32_t fy = (by + y == c.cy0) ? kBy : 0u;
+                for (int x = l.x0; x <= l.x1; ++x) {
+                    const int t = y * bl.Bx + x;
+                    const uint32_t ls = atomicAdd(&lcur[t], 1u);
+                    if (ls >= total) {  // counts disagree with the histogram: cannot happen
+                        err |= kStatInternal;
+                        continue;
+                    }
+                    s_dst[ls] = goff[t] + ls;
+                    s_src[ls] = (e - k.e0) | fy | ((bx + x == c.cx0) ? kBx : 0u);
+                }
+            }
+        }
+        __syncthreads();
+        // write out in destination order
+        for (uint32_t i = tid; i < total; i += kL1NT) {
+            const uint32_t d = s_dst[i], sv = s_src[i];
+            const uint32_t src = k.e0 + (sv & ~(kBx | kBy));
+            if ((int64_t)d >= cap_m) {
+                err |= kStatCapacity;
+                continue;
+            }
+            ent[d].b = e1[src].b;
+            ent[d].m = make_uint4(e1[src].m.x | (sv & (kBx | kBy)), 0u, 0u, 0u);
+        }
+        __syncthreads();
+    }
+    if (err) atomicOr(&st->flags, err);
+}
+
 // Segment start of every blocked tile: the start of its first chunk's
 // sub-segment; the last entry is the total.
 __global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t* __restrict__ cp,
@@ -583,9 +729,13 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     }
     {
         ProfRange pr("k_l2_scatter", s);
-        hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1,
-                           P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m,
-                           P.st);
+        if (B2 <= kStageMaxB2)
+            hipLaunchKernelGGL(k_l2_scatter_staged, dim3(nb2), dim3(kL1NT), 0, s, P.e1, P.h1, nb1,
+                               P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m, P.st);
+        else
+            hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1,
+                               P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m,
+                               P.st);
     }
     {
         ProfRange pr("k_tile_offsets", s);
