@@ -327,28 +327,32 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ 
     if (err) atomicOr(&st->flags, err);
 }
 
-// Level-2 scatter with the chunk's output staged in LDS.  Scattered 32-byte
-// stores run at well under half of HBM speed on this GPU, so a chunk's tile
-// entries are first ranked in LDS (8 bytes each: destination, and the source
-// position in the chunk with the two start bits), then written out in
-// destination order, so that consecutive lanes store consecutive entries of
-// a tile's sub-segment; the boxes are re-read from the chunk, which the
-// first pass has just brought into L2.  A chunk whose output exceeds the
-// stage takes the direct path of k_l2_scatter.
-constexpr int kStage = 6144;          // staged entries per chunk
+// Level-2 scatter with the chunk staged in LDS.  Scattered 32-byte stores run
+// at well under half of HBM speed on this GPU, so a workgroup keeps its
+// chunk's level-1 entries (box, id word) in LDS, ranks the chunk's tile
+// entries per tile (destination; source position in the chunk with the two
+// start bits), and then writes them in destination order, so that
+// consecutive lanes store consecutive entries of a tile's sub-segment.  A
+// chunk whose output exceeds the stage takes the direct path.
+constexpr int kStageNT = 1024;        // one workgroup per CU: the stage takes most of the LDS
+constexpr int kStage = 6144;          // staged tile entries per chunk
 constexpr int kStageMaxB2 = 2048;     // tiles per coarse cell the staged kernel handles
-constexpr int kStagePer = kStageMaxB2 / kL1NT;
+constexpr int kStagePer = kStageMaxB2 / kStageNT;
+constexpr uint32_t kSrcFx = 1u << 12, kSrcFy = 1u << 13;  // start bits of a staged entry
+static_assert(kChunk2 <= (1 << 12), "chunk positions take 12 bits");
 
-__global__ __launch_bounds__(kL1NT) void k_l2_scatter_staged(
+__global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
     const Entry* __restrict__ e1, const uint32_t* __restrict__ o1, int64_t nb1,
     const uint32_t* __restrict__ cp, const uint32_t* __restrict__ chunk_cell, GridDev g, Blocking bl,
     const uint32_t* __restrict__ o2, Entry* __restrict__ ent, int64_t cap_m,
     DevStatus* __restrict__ st) {
-    __shared__ uint32_t s_dst[kStage];   // destination of each staged entry
-    __shared__ uint32_t s_src[kStage];   // source position in the chunk | start bits
-    __shared__ uint32_t lcur[kStageMaxB2];  // staging cursor per tile
-    __shared__ uint32_t goff[kStageMaxB2];  // global minus staging offset per tile
-    __shared__ uint32_t s_wsum[kL1NT / kWave];
+    __shared__ float4 s_box[kChunk2];      // the chunk's level-1 entries
+    __shared__ uint32_t s_id[kChunk2];
+    __shared__ uint32_t s_dst[kStage];     // destination of each staged tile entry
+    __shared__ uint16_t s_src[kStage];     // its position in the chunk | start bits
+    __shared__ uint32_t lcur[kStageMaxB2]; // staging cursor per tile
+    __shared__ uint32_t goff[kStageMaxB2]; // destination minus staging offset per tile
+    __shared__ uint32_t s_wsum[kStageNT / kWave];
     __shared__ uint32_t s_total;
     if (aborted(st)) return;
     const int B2 = bl.tiles_per_cell();
@@ -381,94 +385,82 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter_staged(
         if (lane == kWave - 1) s_wsum[w] = inc;
         __syncthreads();
         if (tid == 0) {
-            uint32_t a = 0;
-            for (int i = 0; i < kL1NT / kWave; ++i) {
+            uint32_t acc = 0;
+            for (int i = 0; i < kStageNT / kWave; ++i) {
                 const uint32_t v = s_wsum[i];
-                s_wsum[i] = a;
-                a += v;
+                s_wsum[i] = acc;
+                acc += v;
             }
-            s_total = a;
+            s_total = acc;
         }
         __syncthreads();
         const uint32_t total = s_total;
-        if (total > (uint32_t)kStage) {
-            // direct path: each entry straight to its tile's next slot
-            for (int u = 0; u < kStagePer; ++u) {
-                const int t = tid * kStagePer + u;
-                if (t < B2) lcur[t] = gb[u];
-            }
-            __syncthreads();
-            for (uint32_t e = k.e0 + tid; e < k.e1; e += kL1NT) {
-                const float4 a = e1[e].b;
-                const uint32_t id = e1[e].m.x;
-                const Cells c = cells_of(a, g);
-                const Local l = local_range(c, k, bl);
-                const int bx = k.gx * bl.Bx, by = k.gy * bl.By;
-                for (int y = l.y0; y <= l.y1; ++y) {
-                    const uint32_t fy = (by + y == c.cy0) ? kBy : 0u;
-                    for (int x = l.x0; x <= l.x1; ++x) {
-                        const uint32_t slot = atomicAdd(&lcur[y * bl.Bx + x], 1u);
-                        if ((int64_t)slot >= cap_m) {
-                            err |= kStatCapacity;
-                            continue;
-                        }
-                        ent[slot].b = a;
-                        ent[slot].m = make_uint4(id | fy | ((bx + x == c.cx0) ? kBx : 0u), 0u, 0u, 0u);
-                    }
-                }
-            }
-            __syncthreads();
-            continue;
-        }
+        const bool staged = total <= (uint32_t)kStage;
         {
             uint32_t run = s_wsum[w] + inc - sum;
 #pragma unroll
             for (int u = 0; u < kStagePer; ++u) {
                 const int t = tid * kStagePer + u;
                 if (t < B2) {
-                    lcur[t] = run;
+                    lcur[t] = staged ? run : gb[u];
                     goff[t] = gb[u] - run;  // modular: goff + staged index = destination
                 }
                 run += cnt[u];
             }
         }
         __syncthreads();
-        // rank every tile entry of the chunk in LDS
-        uint32_t e = k.e0 + tid;
-        float4 nb = e < k.e1 ? e1[e].b : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (; e < k.e1; e += kL1NT) {
-            const float4 a = nb;
-            if (e + kL1NT < k.e1) nb = e1[e + kL1NT].b;
+        // rank every tile entry of the chunk (direct path: store it at once)
+        for (uint32_t e = k.e0 + tid; e < k.e1; e += kStageNT) {
+            const float4 a = e1[e].b;
+            const uint32_t id = e1[e].m.x;
+            const uint32_t p = e - k.e0;
+            if (staged) {
+                s_box[p] = a;
+                s_id[p] = id;
+            }
             const Cells c = cells_of(a, g);
             const Local l = local_range(c, k, bl);
             const int bx = k.gx * bl.Bx, by = k.gy * bl.By;
             for (int y = l.y0; y <= l.y1; ++y) {
-                const uint32_t fy = (by + y == c.cy0) ? kBy : 0u;
+                const bool fy = by + y == c.cy0;
                 for (int x = l.x0; x <= l.x1; ++x) {
+                    const bool fx = bx + x == c.cx0;
                     const int t = y * bl.Bx + x;
                     const uint32_t ls = atomicAdd(&lcur[t], 1u);
+                    if (!staged) {
+                        if ((int64_t)ls >= cap_m) {
+                            err |= kStatCapacity;
+                            continue;
+                        }
+                        ent[ls].b = a;
+                        ent[ls].m = make_uint4(id | (fy ? kBy : 0u) | (fx ? kBx : 0u), 0u, 0u, 0u);
+                        continue;
+                    }
                     if (ls >= total) {  // counts disagree with the histogram: cannot happen
                         err |= kStatInternal;
                         continue;
                     }
                     s_dst[ls] = goff[t] + ls;
-                    s_src[ls] = (e - k.e0) | fy | ((bx + x == c.cx0) ? kBx : 0u);
+                    s_src[ls] = (uint16_t)(p | (fx ? kSrcFx : 0u) | (fy ? kSrcFy : 0u));
                 }
             }
         }
         __syncthreads();
-        // write out in destination order
-        for (uint32_t i = tid; i < total; i += kL1NT) {
-            const uint32_t d = s_dst[i], sv = s_src[i];
-            const uint32_t src = k.e0 + (sv & ~(kBx | kBy));
-            if ((int64_t)d >= cap_m) {
-                err |= kStatCapacity;
-                continue;
+        if (staged) {
+            // write out in destination order
+            for (uint32_t i = tid; i < total; i += kStageNT) {
+                const uint32_t d = s_dst[i], sv = s_src[i];
+                if ((int64_t)d >= cap_m) {
+                    err |= kStatCapacity;
+                    continue;
+                }
+                const uint32_t p = sv & (kSrcFx - 1u);
+                ent[d].b = s_box[p];
+                ent[d].m = make_uint4(s_id[p] | ((sv & kSrcFx) ? kBx : 0u) | ((sv & kSrcFy) ? kBy : 0u),
+                                      0u, 0u, 0u);
             }
-            ent[d].b = e1[src].b;
-            ent[d].m = make_uint4(e1[src].m.x | (sv & (kBx | kBy)), 0u, 0u, 0u);
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (err) atomicOr(&st->flags, err);
 }
@@ -730,7 +722,8 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     {
         ProfRange pr("k_l2_scatter", s);
         if (B2 <= kStageMaxB2)
-            hipLaunchKernelGGL(k_l2_scatter_staged, dim3(nb2), dim3(kL1NT), 0, s, P.e1, P.h1, nb1,
+            hipLaunchKernelGGL(k_l2_scatter_staged, dim3(num_cus), dim3(kStageNT), 0, s, P.e1,
+                               P.h1, nb1,
                                P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m, P.st);
         else
             hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1,
