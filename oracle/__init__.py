@@ -51,6 +51,8 @@ def _load():
         lib.oracle_distance_refine.argtypes = [f32p, f32p, ctypes.c_float,
                                                ctypes.POINTER(ctypes.c_int32), i64]
         lib.oracle_distance_refine.restype = i64
+        lib.oracle_gbda.argtypes = [f32p, i64, f32p, i64, ctypes.c_int, f32p, i32pp]
+        lib.oracle_gbda.restype = i64
         lib.oracle_free.argtypes = [ctypes.c_void_p]
         lib.oracle_free.restype = None
         lib.oracle_max_threads.argtypes = []
@@ -126,6 +128,20 @@ def pbsm(R, S, K, domain=None, threads=0, timings=False, sort=True):
     if timings:
         return pairs, tp.value, tj.value
     return pairs
+
+
+def gbda(R, S, K, domain=None):
+    """The class-based duplicate avoidance (GBDA) variant of PBSM: per tile,
+    the 9 class-class joins that can hold a pair whose reference point is in
+    the tile, Algorithm 1 on each, no duplicate test."""
+    R, S = _rects(R), _rects(S)
+    dom = None if domain is None else np.ascontiguousarray(domain, dtype=np.float32)
+    out = ctypes.POINTER(ctypes.c_int32)()
+    n = _load().oracle_gbda(_fp(R), len(R), _fp(S), len(S), int(K),
+                            _fp(dom) if dom is not None else None, ctypes.byref(out))
+    if n == -2:
+        raise ValueError("K must be >= 1")
+    return _take(n, out, sort=False)
 
 
 def partition_ids(A, K, domain=None):

@@ -423,3 +423,93 @@ int64_t oracle_distance_refine(const float *P, const float *Q, float eps, int32_
     }
     return k;
 }
+
+/* ------------------------------------------------------------------ */
+/* GBDA (grouping-based duplicate avoidance, the mini-joins the paper  */
+/* sketches before Sec. 3.3): in tile T a rectangle is of class A if   */
+/* its x- and y-projections both begin inside T, B if only x does, C   */
+/* if only y does, D if neither ("begins inside T" = its lower corner's */
+/* cell index equals the tile's, the integer form of the tile bounds). */
+/* Of the 16 class-class joins only the 9 in which some rectangle      */
+/* begins inside T along x and some along y can produce a pair whose   */
+/* reference point lies in T; they are joined with Algorithm 1 and no  */
+/* duplicate test.                                                     */
+/* ------------------------------------------------------------------ */
+static int gbda_class(const entry *e, const tile_ctx *c) {
+    int bx = cell_of(e->xl, c->x0, c->sx, c->K) == c->tx;
+    int by = cell_of(e->yl, c->y0, c->sy, c->K) == c->ty;
+    return (bx ? 0 : 2) + (by ? 0 : 1); /* A 0, B 1, C 2, D 3 */
+}
+
+static int gbda_valid(int a, int b) {
+    int bxa = a < 2, bya = (a & 1) == 0, bxb = b < 2, byb = (b & 1) == 0;
+    return (bxa || bxb) && (bya || byb);
+}
+
+int64_t oracle_gbda(const float *R, int64_t nR, const float *S, int64_t nS, int K,
+                    const float *domain, int32_t **out) {
+    if (K < 1) return -2;
+    tile_ctx g;
+    double d[4] = {0.0, 0.0, 1.0, 1.0};
+    if (domain && !(domain[0] == 0 && domain[1] == 0 && domain[2] == 0 && domain[3] == 0))
+        for (int k = 0; k < 4; k++) d[k] = domain[k];
+    g.x0 = d[0];
+    g.y0 = d[1];
+    g.sx = K / (d[2] - d[0]);
+    g.sy = K / (d[3] - d[1]);
+    g.K = K;
+    g.tx = g.ty = 0;
+    partitioned PR = {0, 0, 0}, PS = {0, 0, 0};
+    plist p = {0, 0, 0};
+    int64_t ret = -1;
+    entry *grp = NULL;
+    if (partition_input(R, nR, &g, 1, &PR) || partition_input(S, nS, &g, 1, &PS)) goto done;
+    const int64_t C = (int64_t)K * K;
+    for (int64_t T = 0; T < C; T++) {
+        tile_ctx c = g;
+        c.tx = (int)(T % K);
+        c.ty = (int)(T / K);
+        const entry *Rt = PR.seg + PR.off[T], *St = PS.seg + PS.off[T];
+        int64_t nr = PR.off[T + 1] - PR.off[T], ns = PS.off[T + 1] - PS.off[T];
+        if (!nr || !ns) continue;
+        /* the four class groups of each list, each sorted by x_l */
+        entry *gr = (entry *)malloc((size_t)(nr + ns) * sizeof(entry));
+        if (!gr) goto done;
+        free(grp);
+        grp = gr;
+        int64_t rs[5] = {0}, ss[5] = {0};
+        for (int cl = 0, at = 0; cl < 4; cl++) {
+            rs[cl] = at;
+            for (int64_t i = 0; i < nr; i++)
+                if (gbda_class(&Rt[i], &c) == cl) grp[at++] = Rt[i];
+            rs[cl + 1] = at;
+        }
+        for (int cl = 0, at = 0; cl < 4; cl++) {
+            ss[cl] = at;
+            for (int64_t i = 0; i < ns; i++)
+                if (gbda_class(&St[i], &c) == cl) grp[nr + at++] = St[i];
+            ss[cl + 1] = at;
+        }
+        for (int cl = 0; cl < 4; cl++) {
+            qsort(grp + rs[cl], (size_t)(rs[cl + 1] - rs[cl]), sizeof(entry), by_xl);
+            qsort(grp + nr + ss[cl], (size_t)(ss[cl + 1] - ss[cl]), sizeof(entry), by_xl);
+        }
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++)
+                if (gbda_valid(a, b) &&
+                    sweep_sorted(grp + rs[a], rs[a + 1] - rs[a], grp + nr + ss[b], ss[b + 1] - ss[b],
+                                 NULL, &p))
+                    goto done;
+    }
+    ret = p.n;
+    *out = p.v;
+    p.v = NULL;
+done:
+    free(grp);
+    free(p.v);
+    free(PR.off);
+    free(PR.seg);
+    free(PS.off);
+    free(PS.seg);
+    return ret;
+}
