@@ -55,6 +55,8 @@ def parse():
                     help="one-dimensional partitioning: K vertical stripes swept along y")
     ap.add_argument("--sweep-x", action="store_true",
                     help="sweep every tile along x (no per-tile sweeping-axis model)")
+    ap.add_argument("--gbda", action="store_true",
+                    help="join dense tiles as the 9 GBDA class mini-joins (no duplicate test)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--count", action="store_true", help="count-only join mode")
@@ -357,7 +359,8 @@ def main():
              "out": torch.empty((1 << 20, 2), dtype=torch.int32, device="cuda")}
 
     def step(plain):
-        stripes = (sj.SJ_STRIPES if args.stripes else 0) | (sj.SJ_SWEEP_X if args.sweep_x else 0)
+        stripes = ((sj.SJ_STRIPES if args.stripes else 0) | (sj.SJ_SWEEP_X if args.sweep_x else 0) |
+                   (sj.SJ_GBDA if args.gbda else 0))
         if args.k:
             K, tau = args.k, args.split_tau
         else:
@@ -476,6 +479,7 @@ def main():
                                                           and not args.stripes else "rule"),
                    "partitioning": "1-D stripes" if args.stripes else "2-D grid",
                    "sweep_axis": "y" if args.stripes else ("x" if args.sweep_x else "per-tile model"),
+                   "dense_tiles": "GBDA mini-joins" if args.gbda else "Eq. (1) test",
                    "schedule": main_mode, "mode": "count" if args.count else "pairs",
                    "autotuned": r["tuning"]},
         "pairs_per_s": round(P / (ms * 1e-3), 1),

@@ -83,6 +83,12 @@ typedef enum {
                                    joined as medium or dense work units choose their
                                    sweeping axis with the model of Sec. 3.3 (Eq. (2));
                                    never changes the result                                */
+#define SJ_GBDA 0x20u           /* sj_join: join each dense tile as the 9 class-class mini-joins
+                                   of grouping-based duplicate avoidance (classes by where a
+                                   rectangle's projections begin relative to the tile; only the
+                                   9 class pairs that can hold a pair whose reference point is
+                                   in the tile), each split into pivot ranges, with no
+                                   duplicate test; never changes the result                */
 
 /*
  * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.3.2).
@@ -96,7 +102,7 @@ typedef enum {
  *   domain     x0, y0, x1, y1 of the gridded region; all zero = the unit
  *              square [0,1)^2 (the paper normalises data to [0,1], Sec. 4.1).
  *              Rectangles outside it are clamped into the border tiles.
- *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS, SJ_STRIPES, SJ_SWEEP_X.
+ *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS, SJ_STRIPES, SJ_SWEEP_X, SJ_GBDA.
  * Tile (tx, ty) holds the rectangles whose cell ranges
  * [cell(x_l), cell(x_u)] x [cell(y_l), cell(y_u)] contain it, with
  * cell(v) = clamp(floor((v - x0) * K / (x1 - x0)), 0, K - 1) in float32.

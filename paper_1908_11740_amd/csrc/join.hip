@@ -111,7 +111,20 @@ struct Args {
     int axis_model;               // medium / dense tiles choose their sweeping axis
     GridDev gd;                   // grid and blocking of the two partitions
     Blocking bl;
+    int gbda;                     // dense tiles: the 9 class-class mini-joins, no duplicate test
+    uint32_t* dgrp;               // [cap_dense * 10] class group starts of each dense tile (R, S)
+    uint32_t* dmj;                // [cap_dense * 10] units before each mini-join of a dense tile
 };
+
+// GBDA classes of an entry in its tile, from the start bits of Eq. (1):
+// A = both projections begin in the tile, B = only x, C = only y, D = neither.
+// The 9 class pairs (R class, S class) that can hold a pair whose reference
+// point lies in the tile: some rectangle begins in it along x, some along y.
+__device__ __forceinline__ uint32_t gbda_class(uint32_t idw) {
+    return ((idw & kBx) ? 0u : 2u) + ((idw & kBy) ? 0u : 1u);
+}
+__constant__ uint8_t kMiniJoin[9][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 0},
+                                         {1, 2}, {2, 0}, {2, 1}, {3, 0}};
 
 // A medium or dense tile record carries its sweeping axis in bit 31 of one
 // field (set by k_axis): medium (R start, nr | axis, S start, ns), dense
@@ -318,7 +331,7 @@ __device__ __forceinline__ int search_x(const F& xl, int lo, int hi, float v, bo
 constexpr int kCand = 4;
 constexpr int kChunkC = 8;  // consecutive candidates per lane and round (LDS units)
 
-template <int MODE, bool BLOCK, class Acc>
+template <int MODE, bool BLOCK, bool REF = true, class Acc>
 __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_end, uint32_t* next,
                              Sink<MODE, BLOCK>& sk) {
     bool scanning = false, exhausted = false, isR = false;
@@ -369,7 +382,7 @@ __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_e
 #pragma unroll
             for (int k = 0; k < kCand; ++k) {
                 go = go && (j + k < jend) && (c[k].x <= pxu);
-                hit[k] = go && (pyl <= c[k].w) && (c[k].y <= pyu) && ref_point_here(pid, qid[k]);
+                hit[k] = go && (pyl <= c[k].w) && (c[k].y <= pyu) && (!REF || ref_point_here(pid, qid[k]));
                 used += go ? 1 : 0;
                 const uint32_t other = qid[k] & kIdMask;
                 er[k] = isR ? me : other;
@@ -1702,6 +1715,7 @@ __device__ __forceinline__ float lower_edge(const float4& b, bool y) { return y 
 
 __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
     __shared__ unsigned long long keys[kDenseSortMax];
+    __shared__ uint32_t s_cls[4];
     const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
     for (uint32_t seg = blockIdx.x; seg < 2 * nd; seg += gridDim.x) {
         const uint4 dd = a.dense[seg >> 1];
@@ -1712,15 +1726,35 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
         const uint32_t L = sideS ? dd.w : dd.z;
         const uint32_t dst = dd.y + (sideS ? dd.z : 0u);
         const Entry* ent = sideS ? a.entS : a.entR;
+        // key: (GBDA class,) order key of the lower edge, position
+        auto key_of = [&](uint32_t i) -> unsigned long long {
+            const Entry& en = ent[src + i];
+            const unsigned long long ok = order_key(lower_edge(en.b, swap));
+            return a.gbda ? ((unsigned long long)gbda_class(en.m.x) << 62) | (ok << 30) | i
+                          : (ok << 32) | i;
+        };
+        const unsigned long long pos_mask = a.gbda ? 0x3FFFFFFFull : 0xFFFFFFFFull;
+        if (a.gbda) {  // class group starts of this list
+            if (threadIdx.x < 4) s_cls[threadIdx.x] = 0u;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < L; i += blockDim.x)
+                atomicAdd(&s_cls[gbda_class(ent[src + i].m.x)], 1u);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t* g = a.dgrp + (size_t)(seg >> 1) * 10 + (sideS ? 5 : 0);
+                uint32_t acc = 0;
+                for (int c = 0; c < 4; ++c) {
+                    g[c] = acc;
+                    acc += s_cls[c];
+                }
+                g[4] = acc;
+            }
+        }
         const unsigned long long* fin;  // final sorted keys (low 32 bits = position)
         if (L <= (uint32_t)kDenseSortMax) {
             int P = 1;
             while (P < (int)L) P <<= 1;
-            for (int i = threadIdx.x; i < P; i += blockDim.x)
-                keys[i] = i < (int)L
-                              ? ((unsigned long long)order_key(lower_edge(ent[src + i].b, swap)) << 32) |
-                                    (uint32_t)i
-                              : ~0ull;
+            for (int i = threadIdx.x; i < P; i += blockDim.x) keys[i] = i < (int)L ? key_of(i) : ~0ull;
             __syncthreads();
             bitonic_lds(keys, P);
             fin = keys;
@@ -1733,10 +1767,7 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             for (uint32_t c0 = 0; c0 < L; c0 += kDenseSortMax) {
                 const int n = (int)min((uint32_t)kDenseSortMax, L - c0);
                 for (int i = threadIdx.x; i < kDenseSortMax; i += blockDim.x)
-                    keys[i] = i < n ? ((unsigned long long)order_key(lower_edge(ent[src + c0 + i].b, swap))
-                                       << 32) |
-                                          (c0 + (uint32_t)i)
-                                    : ~0ull;
+                    keys[i] = i < n ? key_of(c0 + (uint32_t)i) : ~0ull;
                 __syncthreads();
                 bitonic_lds(keys, kDenseSortMax);
                 for (int i = threadIdx.x; i < n; i += blockDim.x) A[c0 + i] = keys[i];
@@ -1774,7 +1805,7 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             fin = A;
         }
         for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
-            const uint32_t q = (uint32_t)fin[i];
+            const uint32_t q = (uint32_t)(fin[i] & pos_mask);
             const float4 b = ent[src + q].b;
             a.dbox[dst + i] = swap ? make_float4(b.y, b.x, b.w, b.z) : b;
             a.didf[dst + i] = ent[src + q].m.x;
@@ -1795,7 +1826,21 @@ __global__ __launch_bounds__(1024) void k_dense_plan(Args a) {
         if (d < nd) {
             const uint4 dd = a.dense[d];
             const uint32_t n = dd.z + dd.w;
-            v = a.plain ? 1u : (n + (uint32_t)a.split_tau - 1u) / (uint32_t)a.split_tau;
+            if (a.gbda) {
+                // units of the 9 mini-joins (R class X x S class Y), each split
+                // into ranges of split_tau pivots; units before each in dmj
+                const uint32_t* g = a.dgrp + (size_t)d * 10;
+                uint32_t* mj = a.dmj + (size_t)d * 10;
+                for (int j = 0; j < 9; ++j) {
+                    mj[j] = v;
+                    const int X = kMiniJoin[j][0], Y = kMiniJoin[j][1];
+                    const uint32_t nx = g[X + 1] - g[X], ny = g[5 + Y + 1] - g[5 + Y];
+                    if (nx && ny) v += (nx + ny + (uint32_t)a.split_tau - 1u) / (uint32_t)a.split_tau;
+                }
+                mj[9] = v;
+            } else {
+                v = a.plain ? 1u : (n + (uint32_t)a.split_tau - 1u) / (uint32_t)a.split_tau;
+            }
         }
         uint32_t inc = v;
         for (int s = 1; s < kWave; s <<= 1) {
@@ -1850,6 +1895,32 @@ struct GlobAcc {
     }
 };
 
+// One GBDA mini-join of a dense tile: R class group [rb, rb+nr), S class
+// group [sb, sb+ns) of the sorted dense buffer; pivots: R group, then S group.
+struct GbdaAcc {
+    const float4* bxs;
+    const uint32_t* idf;
+    int rb, nr, sb, ns;
+    __device__ float4 box(int j) const { return bxs[j]; }
+    __device__ uint32_t id(int j) const { return idf[j]; }
+    __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxu, float& pyl, float& pyu,
+                          uint32_t& pid) const {
+        isR = p < nr;
+        const int e = isR ? rb + p : sb + (p - nr);
+        const float4 b = bxs[e];
+        pxu = b.z;
+        pyl = b.y;
+        pyu = b.w;
+        pid = idf[e];
+        auto X = [&](int q) { return bxs[q].x; };
+        const int lo = isR ? sb : rb;
+        const int hi = isR ? sb + ns : rb + nr;
+        j = search_x(X, lo, hi, b.x, isR);
+        jend = hi;
+        return true;
+    }
+};
+
 template <int MODE>
 __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
     __shared__ unsigned long long wbuf[(kDenseNT / kWave) * kWaveBuf];
@@ -1872,18 +1943,33 @@ __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
             else hi = mid;
         }
         const uint4 dd = a.dense[lo];
-        const int n = (int)(dd.z + dd.w);
-        int p0 = 0, p1 = n;
-        if (!a.plain) {
-            p0 = (int)(u - a.dprefix[lo]) * a.split_tau;
-            p1 = min(p0 + a.split_tau, n);
-        }
         const int64_t slot = a.base_dense + u;
         sk.begin(a, slot);
         if (threadIdx.x == 0) s_next = 0u;
         __syncthreads();
-        GlobAcc acc{a.dbox, a.didf, (int)dd.y, (int)dd.z, (int)dd.w};
-        sweep_pivots<MODE, true>(a, acc, p0, p1, &s_next, sk);
+        if (a.gbda) {
+            // mini-join j of the tile and its range of pivots
+            const uint32_t r = u - a.dprefix[lo];
+            const uint32_t* mj = a.dmj + (size_t)lo * 10;
+            int jm = 0;
+            while (jm < 8 && mj[jm + 1] <= r) ++jm;
+            const int X = kMiniJoin[jm][0], Y = kMiniJoin[jm][1];
+            const uint32_t* g = a.dgrp + (size_t)lo * 10;
+            const int nx = (int)(g[X + 1] - g[X]), ny = (int)(g[5 + Y + 1] - g[5 + Y]);
+            const int p0 = (int)(r - mj[jm]) * a.split_tau;
+            const int p1 = min(p0 + a.split_tau, nx + ny);
+            GbdaAcc acc{a.dbox, a.didf, (int)(dd.y + g[X]), nx, (int)(dd.y + dd.z + g[5 + Y]), ny};
+            sweep_pivots<MODE, true, false>(a, acc, p0, p1, &s_next, sk);
+        } else {
+            const int n = (int)(dd.z + dd.w);
+            int p0 = 0, p1 = n;
+            if (!a.plain) {
+                p0 = (int)(u - a.dprefix[lo]) * a.split_tau;
+                p1 = min(p0 + a.split_tau, n);
+            }
+            GlobAcc acc{a.dbox, a.didf, (int)dd.y, (int)dd.z, (int)dd.w};
+            sweep_pivots<MODE, true>(a, acc, p0, p1, &s_next, sk);
+        }
         sk.end(a, slot);
     }
     sk.finish(a, wg);
@@ -2094,6 +2180,9 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     const bool single = p.single && !p.plain && !p.count_only && w.sc_nch > 0;
     a.writeback = (!single && !p.count_only) ? 1 : 0;
     a.axis_model = (p.axis_model && !p.plain) ? 1 : 0;
+    a.gbda = (p.gbda && !p.plain) ? 1 : 0;
+    a.dgrp = w.dgrp;
+    a.dmj = w.dmj;
     a.medt = w.medt;
     a.gd = R.gd;
     a.bl = R.bl;

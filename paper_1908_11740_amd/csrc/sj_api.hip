@@ -179,6 +179,7 @@ JoinParams join_params(const sj_grid& g, bool count_only) {
     p.single = !p.plain && !count_only && (g.flags & SJ_TWO_PASS) == 0;
     // the model picks between x and y; stripes sweep along y by construction
     p.axis_model = !p.plain && (g.flags & (SJ_SWEEP_X | SJ_STRIPES)) == 0;
+    p.gbda = !p.plain && (g.flags & SJ_GBDA) != 0;
     return p;
 }
 
@@ -217,8 +218,16 @@ sj_status join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_
         if ((e = grow(w.medt, w.cap_medt, w.cap_med)) != hipSuccess) return from_hip(e);
     }
     if ((e = grow(w.dense, w.cap_dense, ndense)) != hipSuccess) return from_hip(e);
+    // dense units: ceil(list / tau) per tile; with GBDA ceil per mini-join,
+    // where each class group takes part in at most 4 of the 9
     w.cap_dunits = std::max<int64_t>(
-        w.cap_dunits, p.plain ? w.cap_dense : (mR + mS) / std::max(1, p.split_tau) + w.cap_dense + 1);
+        w.cap_dunits, p.plain ? w.cap_dense
+                              : (p.gbda ? 4 : 1) * (mR + mS) / std::max(1, p.split_tau) +
+                                    (p.gbda ? 9 : 1) * w.cap_dense + 1);
+    if (p.gbda) {
+        if ((e = grow(w.dgrp, w.cap_dgrp, 10 * w.cap_dense)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.dmj, w.cap_dmj, 10 * w.cap_dense)) != hipSuccess) return from_hip(e);
+    }
     {
         const int64_t slots = join_slots(p, w);
         if ((e = grow(w.ucnt, w.cap_ucnt, slots + 1)) != hipSuccess) return from_hip(e);

@@ -148,6 +148,7 @@ struct JoinParams {
     bool count_only;
     bool single;     // one sweep into scratch chunks + compaction (else count, scan, write)
     bool axis_model; // medium and dense tiles choose their sweeping axis (Eq. (2))
+    bool gbda;       // dense tiles: the 9 GBDA class mini-joins, no duplicate test
 };
 
 struct JoinWork {
@@ -161,6 +162,9 @@ struct JoinWork {
     int64_t cap_medt = 0;
     uint4* dense = nullptr;         // [cap_dense] (tile, base in dense buffer, nr, ns)
     uint32_t* dense_unit_prefix = nullptr;  // [cap_dense+1]
+    uint32_t* dgrp = nullptr;       // [cap_dgrp] GBDA class group starts, 10 per dense tile
+    uint32_t* dmj = nullptr;        // [cap_dmj] GBDA mini-join unit prefix, 10 per dense tile
+    int64_t cap_dgrp = 0, cap_dmj = 0;
     int64_t cap_tiles = 0, cap_units = 0, cap_dense = 0, cap_prefix = 0, cap_dunits = 0;
     uint32_t* ucnt = nullptr;       // per-unit pair counts -> output offsets
     int64_t cap_ucnt = 0;

@@ -28,6 +28,7 @@ SJ_RULE_ONLY = 0x2
 SJ_TWO_PASS = 0x4
 SJ_STRIPES = 0x8
 SJ_SWEEP_X = 0x10
+SJ_GBDA = 0x20
 INT32_MAX = 2**31 - 1
 
 

@@ -1,0 +1,88 @@
+"""GPU parity of GBDA on dense tiles (SJ_GBDA: each dense tile joined as the
+9 class-class mini-joins, no duplicate test): the pair set equals the
+oracle's on every schedule, with and without the sweeping-axis model, on
+layouts with many rectangles of every class; dense tiles become more,
+finer work units."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_11740_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1908_11740_amd import sj  # noqa: E402
+from gpu_util import gpu_join  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+G = sj.SJ_GBDA
+SCHED = {"gbda": dict(flags=G), "gbda_tau1": dict(flags=G, split_tau=1),
+         "gbda_tau64": dict(flags=G, split_tau=64), "gbda_twopass": dict(flags=G | sj.SJ_TWO_PASS),
+         "gbda_x": dict(flags=G | sj.SJ_SWEEP_X), "gbda_nosplit": dict(flags=G, split_tau=sj.INT32_MAX)}
+
+
+@pytest.fixture(scope="module")
+def small():
+    R, S, _ = datagen.small_case()
+    return R, S, oracle.bruteforce(R, S)
+
+
+@pytest.fixture(scope="module")
+def big_rects():
+    R = datagen.uniform(6000, 0.3, 21)
+    S = datagen.uniform(5000, 0.3, 22)
+    return R, S, oracle.pbsm(R, S, 8)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 16])
+@pytest.mark.parametrize("sched", sorted(SCHED))
+def test_small_case(small, K, sched):
+    R, S, ref = small
+    say("gbda small K", K, sched)
+    assert np.array_equal(gpu_join(R, S, K, **SCHED[sched]), ref)
+
+
+@pytest.mark.parametrize("K", [1, 3, 4, 8])
+@pytest.mark.parametrize("sched", sorted(SCHED))
+def test_large_rectangles_every_class(big_rects, K, sched):
+    R, S, ref = big_rects
+    say("gbda big K", K, sched)
+    assert np.array_equal(gpu_join(R, S, K, **SCHED[sched]), ref)
+    assert gpu_join(R, S, K, count=True, **SCHED[sched]) == len(ref)
+
+
+def test_anisotropic_dense_tiles_and_units():
+    mix = datagen.mixture_spec(12, 731)
+    R = datagen.anisotropic(150_000, mix, 0.1, 2e-3, 25.0, 0.5, 61)
+    S = datagen.anisotropic(150_000, mix, 0.1, 2e-3, 25.0, 0.5, 62)
+    ref = oracle.pbsm(R, S, 32)
+    for K in (1, 2, 8):
+        units = {}
+        for name, kw in (("plain-dense", {}), ("gbda", dict(flags=G))):
+            assert np.array_equal(gpu_join(R, S, K, **kw), ref), (K, name)
+            st = sj.last_join_stats()
+            units[name] = (st["dense_tiles"], st["dense_units"])
+        assert units["gbda"][0] == units["plain-dense"][0] > 0
+        assert units["gbda"][1] >= units["plain-dense"][1]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_adversarial(seed):
+    from test_oracle import adversarial
+    rng = np.random.default_rng(1200 + seed)
+    K = int(rng.choice([1, 2, 3, 5]))
+    A = adversarial(int(rng.integers(200, 3000)), 11 * seed, K)
+    B = adversarial(int(rng.integers(200, 3000)), 11 * seed + 1, K)
+    ref = oracle.bruteforce(A, B)
+    for sched in ("gbda", "gbda_tau1"):
+        assert np.array_equal(gpu_join(A, B, K, **SCHED[sched]), ref), sched
