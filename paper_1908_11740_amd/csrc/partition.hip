@@ -151,6 +151,118 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
     if (err) atomicOr(&st->flags, err);
 }
 
+// Level-1 scatter with the chunk staged in LDS (grids of at most
+// kL1StageMaxG1 coarse cells, chunks of kL1StageChunk rectangles): the same
+// scheme as the staged level-2 scatter.  The chunk's rectangles (partition
+// axes, -0 -> +0) are kept in LDS, their coarse-cell entries ranked per cell,
+// then written in destination order.  A chunk whose output exceeds the
+// stage writes directly.
+constexpr int kL1Stage = 5120;  // staged level-1 entries per chunk
+static_assert(kL1StageChunk <= (1 << 16), "chunk positions take 16 bits");
+
+__global__ __launch_bounds__(1024) void k_l1_scatter_staged(
+    const float4* __restrict__ rects, int64_t n, GridDev g, Blocking bl, int64_t ch1, int64_t nb1,
+    const uint32_t* __restrict__ o1, Entry* __restrict__ e1, int64_t cap_m1,
+    DevStatus* __restrict__ st) {
+    constexpr int NT = 1024;
+    __shared__ float4 s_box[kL1StageChunk];
+    __shared__ uint32_t s_dst[kL1Stage];
+    __shared__ uint16_t s_src[kL1Stage];
+    __shared__ uint32_t lcur[kL1StageMaxG1];
+    __shared__ uint32_t goff[kL1StageMaxG1];
+    __shared__ uint32_t s_wsum[NT / kWave];
+    __shared__ uint32_t s_total;
+    if (aborted(st)) return;
+    const int G1 = bl.cells();
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int64_t last = (int64_t)G1 * nb1;
+    const uint32_t m1_total = (uint32_t)st->m1_total;
+    uint32_t err = 0;
+    for (int64_t q = blockIdx.x; q < nb1; q += gridDim.x) {
+        const int64_t lo = q * ch1;
+        const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
+        // entries of this chunk per coarse cell (one cell per thread)
+        uint32_t gb = 0, cnt = 0;
+        if (tid < G1) {
+            const int64_t idx = (int64_t)tid * nb1 + q;
+            gb = o1[idx];
+            cnt = (idx + 1 < last ? o1[idx + 1] : m1_total) - gb;
+        }
+        uint32_t inc = cnt;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += t;
+        }
+        if (lane == kWave - 1) s_wsum[w] = inc;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            for (int i = 0; i < NT / kWave; ++i) {
+                const uint32_t v = s_wsum[i];
+                s_wsum[i] = acc;
+                acc += v;
+            }
+            s_total = acc;
+        }
+        __syncthreads();
+        const uint32_t total = s_total;
+        const bool staged = total <= (uint32_t)kL1Stage;
+        if (tid < G1) {
+            const uint32_t run = s_wsum[w] + inc - cnt;
+            lcur[tid] = staged ? run : gb;
+            goff[tid] = gb - run;  // modular: goff + staged index = destination
+        }
+        __syncthreads();
+        for (int64_t i = lo + tid; i < hi; i += NT) {
+            float4 a = partition_axes(rects[i], g);
+            if (!rect_ok(a)) continue;
+            a.x += 0.0f;  // -0.0 -> +0.0
+            a.y += 0.0f;
+            a.z += 0.0f;
+            a.w += 0.0f;
+            const uint32_t p = (uint32_t)(i - lo);
+            if (staged) s_box[p] = a;
+            const Cells c = cells_of(a, g);
+            const int gx0 = c.cx0 / bl.Bx, gx1 = c.cx1 / bl.Bx;
+            const int gy0 = c.cy0 / bl.By, gy1 = c.cy1 / bl.By;
+            for (int gy = gy0; gy <= gy1; ++gy)
+                for (int gx = gx0; gx <= gx1; ++gx) {
+                    const int cell = gy * bl.Gx + gx;
+                    const uint32_t ls = atomicAdd(&lcur[cell], 1u);
+                    if (!staged) {
+                        if ((int64_t)ls >= cap_m1) {
+                            err |= kStatCapacity;
+                            continue;
+                        }
+                        e1[ls].b = a;
+                        e1[ls].m = make_uint4((uint32_t)i, 0u, 0u, 0u);
+                        continue;
+                    }
+                    if (ls >= total) {  // counts disagree with the histogram: cannot happen
+                        err |= kStatInternal;
+                        continue;
+                    }
+                    s_dst[ls] = goff[cell] + ls;
+                    s_src[ls] = (uint16_t)p;
+                }
+        }
+        __syncthreads();
+        if (staged) {
+            for (uint32_t i = tid; i < total; i += NT) {
+                const uint32_t d = s_dst[i], p = s_src[i];
+                if ((int64_t)d >= cap_m1) {
+                    err |= kStatCapacity;
+                    continue;
+                }
+                e1[d].b = s_box[p];
+                e1[d].m = make_uint4((uint32_t)(lo + p), 0u, 0u, 0u);
+            }
+            __syncthreads();
+        }
+    }
+    if (err) atomicOr(&st->flags, err);
+}
+
 // ---------------------------------------------------------------------------
 // Level-2 chunk plan (one workgroup): chunks per coarse cell and their prefix.
 // ---------------------------------------------------------------------------
@@ -654,7 +766,8 @@ Blocking blocking_for(int kx, int ky) {
     return b;
 }
 
-int64_t l1_chunk(int64_t n) {
+int64_t l1_chunk(int64_t n, int64_t G1) {
+    if (G1 <= kL1StageMaxG1) return kL1StageChunk;  // the staged level-1 scatter
     int64_t c = (n + kL1Blocks - 1) / kL1Blocks;
     if (c < kL1MinChunk) c = kL1MinChunk;
     return c;
@@ -680,7 +793,7 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     }
     const Blocking bl = P.bl;
     const int64_t G1 = bl.cells(), B2 = bl.tiles_per_cell();
-    const int64_t ch1 = l1_chunk(n);
+    const int64_t ch1 = l1_chunk(n, G1);
     const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
     P.nb1 = nb1;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)P.st, 0u,
@@ -701,8 +814,12 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     }
     if (n > 0) {
         ProfRange pr("k_l1_scatter", s);
-        hipLaunchKernelGGL(k_l1_scatter, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
-                           P.gd, bl, ch1, P.h1, P.e1, P.cap_m1, P.st);
+        if (G1 <= kL1StageMaxG1)
+            hipLaunchKernelGGL(k_l1_scatter_staged, dim3(num_cus), dim3(1024), 0, s, rects, n, P.gd,
+                               bl, ch1, nb1, P.h1, P.e1, P.cap_m1, P.st);
+        else
+            hipLaunchKernelGGL(k_l1_scatter, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
+                               P.gd, bl, ch1, P.h1, P.e1, P.cap_m1, P.st);
     }
     {
         ProfRange pr("k_plan", s);

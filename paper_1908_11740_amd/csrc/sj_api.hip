@@ -286,7 +286,7 @@ hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
     hipError_t e = hipSuccess;
     const Blocking bl = P->bl;
     const int64_t G1 = bl.cells(), B2 = bl.tiles_per_cell(), Cb = G1 * B2;
-    const int64_t ch1 = l1_chunk(n);
+    const int64_t ch1 = l1_chunk(n, G1);
     const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
     const int64_t need_chunks = need_m1 / kChunk2 + G1 + 2;
     if ((e = grow(P->h1, P->cap_h1, G1 * nb1 + 1)) != hipSuccess ||
@@ -423,7 +423,7 @@ sj_status sj_partition(const float* rects, int64_t n, const sj_grid* g, sj_part*
     }
     const Blocking bl = blocking_for(gd.kx, gd.ky);
     const int64_t G1 = bl.cells(), B2 = bl.tiles_per_cell(), Cb = G1 * B2;
-    const int64_t ch1 = l1_chunk(n);
+    const int64_t ch1 = l1_chunk(n, G1);
     const int64_t nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
     int64_t need_m1 = std::max<int64_t>(P->cap_m1, n + n / 4 + 4096);
     int64_t need_m = std::max<int64_t>(P->cap_m, 2 * n + 4096);

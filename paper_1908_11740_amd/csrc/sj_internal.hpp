@@ -83,6 +83,8 @@ constexpr int kMaxB = (SJ_K_MAX + kCoarseMax - 1) / kCoarseMax;  // B <= 128: le
 constexpr uint32_t kChunk2 = 4096;  // level-1 entries per level-2 chunk
 constexpr int64_t kL1Blocks = 1024;  // level-1 workgroups per input (upper bound: 4 per CU)
 constexpr int64_t kL1MinChunk = 2048;
+constexpr int kL1StageChunk = 4096;     // level-1 chunk of the staged scatter (rectangles)
+constexpr int kL1StageMaxG1 = 1024;     // coarse cells the staged level-1 scatter handles
 
 struct Blocking {
     int Gx, Gy;  // coarse cells along x and y
@@ -92,7 +94,7 @@ struct Blocking {
 };
 
 Blocking blocking_for(int kx, int ky);
-int64_t l1_chunk(int64_t n);
+int64_t l1_chunk(int64_t n, int64_t G1);
 
 // ---------------------------------------------------------------------------
 // Partitioned input (device buffers) -- the opaque sj_part.
