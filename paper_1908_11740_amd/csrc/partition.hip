@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ 
 // chunk whose output exceeds the stage takes the direct path.
 constexpr int kStageNT = 1024;        // one workgroup per CU: the stage takes most of the LDS
 constexpr int kStage = 6144;          // staged tile entries per chunk
-constexpr int kStageMaxB2 = 2048;     // tiles per coarse cell the staged kernel handles
+constexpr int kStageMaxB2 = 4096;     // tiles per coarse cell the staged kernel handles
 constexpr int kStagePer = kStageMaxB2 / kStageNT;
 constexpr uint32_t kSrcFx = 1u << 12, kSrcFy = 1u << 13;  // start bits of a staged entry
 static_assert(kChunk2 <= (1 << 12), "chunk positions take 12 bits");
