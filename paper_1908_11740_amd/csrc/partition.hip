@@ -766,8 +766,15 @@ Blocking blocking_for(int kx, int ky) {
     return b;
 }
 
+// The staged level-1 scatter takes chunks of kL1StageChunk rectangles; its
+// level-1 histogram has G1 counters per chunk, so very large inputs keep the
+// direct scatter with at most kL1Blocks chunks.
+bool l1_staged(int64_t n, int64_t G1) {
+    return G1 <= kL1StageMaxG1 && n <= (int64_t)kL1StageChunk * kL1StageMaxChunks;
+}
+
 int64_t l1_chunk(int64_t n, int64_t G1) {
-    if (G1 <= kL1StageMaxG1) return kL1StageChunk;  // the staged level-1 scatter
+    if (l1_staged(n, G1)) return kL1StageChunk;
     int64_t c = (n + kL1Blocks - 1) / kL1Blocks;
     if (c < kL1MinChunk) c = kL1MinChunk;
     return c;
@@ -814,7 +821,7 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     }
     if (n > 0) {
         ProfRange pr("k_l1_scatter", s);
-        if (G1 <= kL1StageMaxG1)
+        if (l1_staged(n, G1))
             hipLaunchKernelGGL(k_l1_scatter_staged, dim3(num_cus), dim3(1024), 0, s, rects, n, P.gd,
                                bl, ch1, nb1, P.h1, P.e1, P.cap_m1, P.st);
         else

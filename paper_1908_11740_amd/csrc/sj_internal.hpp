@@ -85,6 +85,7 @@ constexpr int64_t kL1Blocks = 1024;  // level-1 workgroups per input (upper boun
 constexpr int64_t kL1MinChunk = 2048;
 constexpr int kL1StageChunk = 4096;     // level-1 chunk of the staged scatter (rectangles)
 constexpr int kL1StageMaxG1 = 1024;     // coarse cells the staged level-1 scatter handles
+constexpr int64_t kL1StageMaxChunks = 16384;  // ... and chunks (inputs up to 64M rectangles)
 
 struct Blocking {
     int Gx, Gy;  // coarse cells along x and y
