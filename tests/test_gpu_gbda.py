@@ -86,3 +86,38 @@ def test_adversarial(seed):
     ref = oracle.bruteforce(A, B)
     for sched in ("gbda", "gbda_tau1"):
         assert np.array_equal(gpu_join(A, B, K, **SCHED[sched]), ref), sched
+
+
+@pytest.mark.parametrize("K", [1, 2, 5, 40])
+def test_stripes_with_gbda(small, K):
+    # stripes: every entry begins in the single x-cell, so the classes are A
+    # and B only and the mini-joins are A-A, A-B and B-A (the 1-D form)
+    R, S, ref = small
+    for kw in (dict(flags=G | sj.SJ_STRIPES), dict(flags=G | sj.SJ_STRIPES, split_tau=16)):
+        assert np.array_equal(gpu_join(R, S, K, **kw), ref), (K, kw)
+
+
+def test_batch_with_gbda_and_axis_model():
+    import torch as th
+    pairs = []
+    ref = []
+    for j in range(6):
+        mix = datagen.mixture_spec(4, 880 + j)
+        R = datagen.anisotropic(20_000 + 3000 * j, mix, 0.1, 4e-3, 16.0, 0.5, 2 * j + 1)
+        S = datagen.anisotropic(15_000 + 2000 * j, mix, 0.1, 4e-3, 16.0, 0.5, 2 * j + 2)
+        pairs.append((th.from_numpy(R).cuda(), th.from_numpy(S).cuda()))
+        ref.append(oracle.pbsm(R, S, 16))
+    grids = [(1 + j, 0) for j in range(6)]  # tiny grids: dense tiles
+    b = sj.Batch(pairs, grids=grids, flags=G)  # count only
+    st, n = b.run()
+    assert st == sj.SJ_OK and [int(v) for v in n] == [len(r) for r in ref]
+    b.free()
+    caps = [int(v) for v in n]
+    b = sj.Batch(pairs, grids=grids, capacities=caps, flags=G)
+    st, n = b.run()
+    assert st == sj.SJ_OK
+    for j in range(6):
+        got = b.pairs(j, int(n[j])).cpu().numpy()
+        got = got[np.lexsort((got[:, 1], got[:, 0]))]
+        assert np.array_equal(got, ref[j]), j
+    b.free()
