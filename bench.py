@@ -257,6 +257,14 @@ def bench_distance(args, pk, sj, torch):
     for _ in range(max(1, args.warmup)):
         step()
     torch.cuda.synchronize()
+    tuning = None
+    if not args.no_tune:
+        # autotuner on the join of the squares: cached for this grid and size class
+        tg = sj.make_grid(state["g"].k, state["g"].split_tau, flags=state["g"].flags)
+        tuning = sj.distance_tune(Pd, Qd, eps, tg, reps=2)
+        log("autotuned", tuning)
+        step()
+        torch.cuda.synchronize()
     times = []
     for _ in range(args.steps):
         t0 = time.perf_counter()
@@ -291,7 +299,7 @@ def bench_distance(args, pk, sj, torch):
     dom = dominant(kernels)
     dk = kernels[dom]
     profiled = not (args.k or args.split_tau or args.stripes or args.two_pass or args.count or
-                    args.picker != "auto")
+                    args.no_tune or args.picker != "auto")
     roofline = {"kernel": dom, "bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s",
                 "frac": None if dk["gbs"] is None else round(dk["gbs"] / HBM_PEAK_GBS, 4),
@@ -320,7 +328,7 @@ def bench_distance(args, pk, sj, torch):
                    "grid_k": K, "split_tau": tau,
                    "grid_choice": "fixed" if args.k else ("learned" if use_learned else "rule"),
                    "partitioning": "1-D stripes" if args.stripes else "2-D grid",
-                   "mode": "count" if args.count else "pairs"},
+                   "mode": "count" if args.count else "pairs", "autotuned": tuning},
         "pairs_per_s": round(n / (ms * 1e-3), 1), "n_pairs": int(n), "n_candidates": int(nc),
         "pairs_match_oracle_count": verified,
         "median_ms_per_step": round(statistics.median(times) * 1e3, 4),

@@ -431,6 +431,18 @@ sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t n
                            sj_grid* g, sj_pair* out, int64_t capacity, int64_t* n_pairs,
                            void* stream);
 
+/*
+ * Autotune the join schedule of an epsilon-distance join (as sj_tune does for
+ * two partitions): builds the squares, the grid (when g->k is 0; written
+ * back) and the partitions as sj_distance_join does, then times every
+ * candidate schedule on them with the full candidate output and caches the
+ * fastest for that grid and size class, so that later sj_distance_join calls
+ * on the same inputs use it.  best (host, may be NULL) receives it.
+ * Arguments as for sj_distance_join; reps >= 1.  Synchronises the stream.
+ */
+sj_status sj_distance_tune(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
+                           sj_grid* g, int32_t reps, sj_tuning* best, void* stream);
+
 /* Work of the last sj_distance_join on the calling thread's current device
  * (all zero before the first): candidate pairs of the filter (before the
  * distance check) and the tile entries of the two partitions of squares

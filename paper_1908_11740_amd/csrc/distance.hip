@@ -187,19 +187,12 @@ using namespace sj;
 
 extern "C" {
 
-sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
-                           sj_grid* g, sj_pair* out, int64_t capacity, int64_t* n_pairs,
-                           void* stream) {
-    if (!g || !n_pairs || nP < 0 || nQ < 0 || (nP > 0 && !P) || (nQ > 0 && !Q) || capacity < 0 ||
-        (!out && capacity != 0) || !(eps >= 0.f) || !std::isfinite(eps))
-        return SJ_ERR_ARG;
-    if (((uintptr_t)P & 7u) || ((uintptr_t)Q & 7u)) return SJ_ERR_ARG;
-    if (nP >= ((int64_t)1 << 30) || nQ >= ((int64_t)1 << 30)) return SJ_ERR_TOO_LARGE;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return SJ_ERR_DEVICE;
-    const hipStream_t s = (hipStream_t)stream;
-    std::lock_guard<std::mutex> lk(g_dmu);
-    DistState& d = g_ds[dev];
+namespace {
+
+// Squares of both point sets, the grid (chosen when g->k is 0) and the two
+// partitions, in the device state d.  The caller holds g_dmu.
+sj_status prepare(DistState& d, const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
+                  sj_grid* g, hipStream_t s) {
     if (!d.count) {
         if (hipMalloc((void**)&d.count, sizeof(unsigned long long)) != hipSuccess) return SJ_ERR_OOM;
         if (hipHostMalloc((void**)&d.host, sizeof(unsigned long long), hipHostMallocDefault) !=
@@ -225,12 +218,38 @@ sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t n
     }
     sj_status st = SJ_OK;
     if (g->k == 0) {
-        st = sj_choose_grid((const float*)d.sqP, nP, (const float*)d.sqQ, nQ, g, nullptr, stream);
+        st = sj_choose_grid((const float*)d.sqP, nP, (const float*)d.sqQ, nQ, g, nullptr, s);
         if (st != SJ_OK) return st;
     }
-    st = sj_partition((const float*)d.sqP, nP, g, &d.PP, stream);
+    st = sj_partition((const float*)d.sqP, nP, g, &d.PP, s);
     if (st != SJ_OK) return st;
-    st = sj_partition((const float*)d.sqQ, nQ, g, &d.PQ, stream);
+    return sj_partition((const float*)d.sqQ, nQ, g, &d.PQ, s);
+}
+
+sj_status check_args(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
+                     const sj_grid* g) {
+    if (!g || nP < 0 || nQ < 0 || (nP > 0 && !P) || (nQ > 0 && !Q) || !(eps >= 0.f) ||
+        !std::isfinite(eps))
+        return SJ_ERR_ARG;
+    if (((uintptr_t)P & 7u) || ((uintptr_t)Q & 7u)) return SJ_ERR_ARG;
+    if (nP >= ((int64_t)1 << 30) || nQ >= ((int64_t)1 << 30)) return SJ_ERR_TOO_LARGE;
+    return SJ_OK;
+}
+
+}  // namespace
+
+sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
+                           sj_grid* g, sj_pair* out, int64_t capacity, int64_t* n_pairs,
+                           void* stream) {
+    sj_status st = check_args(P, nP, Q, nQ, eps, g);
+    if (st != SJ_OK) return st;
+    if (!n_pairs || capacity < 0 || (!out && capacity != 0)) return SJ_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SJ_ERR_DEVICE;
+    const hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_dmu);
+    DistState& d = g_ds[dev];
+    st = prepare(d, P, nP, Q, nQ, eps, g, s);
     if (st != SJ_OK) return st;
     int64_t nc = 0;
     st = sj_join(d.PP, d.PQ, d.cand, d.cap_cand, &nc, stream);
@@ -257,6 +276,27 @@ sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t n
         return SJ_ERR_DEVICE;
     *n_pairs = (int64_t)*d.host;
     return (out && *n_pairs > capacity) ? SJ_ERR_CAPACITY : SJ_OK;
+}
+
+sj_status sj_distance_tune(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
+                           sj_grid* g, int32_t reps, sj_tuning* best, void* stream) {
+    sj_status st = check_args(P, nP, Q, nQ, eps, g);
+    if (st != SJ_OK) return st;
+    if (reps < 1) return SJ_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SJ_ERR_DEVICE;
+    const hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_dmu);
+    DistState& d = g_ds[dev];
+    st = prepare(d, P, nP, Q, nQ, eps, g, s);
+    if (st != SJ_OK) return st;
+    // the candidate buffer holds every candidate, so each schedule is timed
+    // with its full output
+    int64_t nc = 0;
+    st = sj_join_count(d.PP, d.PQ, &nc, stream);
+    if (st != SJ_OK) return st;
+    if (grow_to(d.cand, d.cap_cand, std::max<int64_t>(nc, 1)) != hipSuccess) return SJ_ERR_OOM;
+    return sj_tune(d.PP, d.PQ, d.cand, d.cap_cand, reps, best, stream);
 }
 
 sj_status sj_distance_last_info(sj_distance_info* info) {

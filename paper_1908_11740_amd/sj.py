@@ -148,10 +148,12 @@ def lib():
         L.sj_distance_join.argtypes = [vp, i64, vp, i64, f32, ctypes.POINTER(Grid), vp, i64,
                                        i64p, vp]
         L.sj_distance_last_info.argtypes = [ctypes.POINTER(DistanceInfo)]
+        L.sj_distance_tune.argtypes = [vp, i64, vp, i64, f32, ctypes.POINTER(Grid), ctypes.c_int32,
+                                       ctypes.POINTER(Tuning), vp]
         for f in ("sj_partition", "sj_join", "sj_join_count", "sj_part_info", "sj_part_download",
                   "sj_features", "sj_choose_grid", "sj_picker_load", "sj_mlp_forward",
                   "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam", "sj_distance_join", "sj_sweep_axis",
-                  "sj_distance_last_info"):
+                  "sj_distance_last_info", "sj_distance_tune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -349,6 +351,19 @@ def distance_join(P, Q, eps, k=0, split_tau=0, domain=None, flags=0, capacity=No
         s, n = distance_join_into(P, Q, eps, out, g, stream)
         _check(s, "sj_distance_join")
     return out[:n], {"k": g.k, "split_tau": g.split_tau}
+
+
+def distance_tune(P, Q, eps, grid, reps=2, stream=None):
+    """sj_distance_tune: time every join schedule on the distance join's
+    partitions and cache the fastest; grid (a Grid) is updated when its k is
+    0.  Returns the winning schedule as a dict."""
+    _points(P)
+    _points(Q)
+    t = Tuning()
+    _check(lib().sj_distance_tune(_ptr(P), P.shape[0], _ptr(Q), Q.shape[0], float(eps),
+                                  ctypes.byref(grid), int(reps), ctypes.byref(t), _stream(stream)),
+           "sj_distance_tune")
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
 
 def distance_last_info():

@@ -170,3 +170,18 @@ def test_full_size_sampled():
     g2 = sj.make_grid(max(1, grid["k"] // 3), flags=sj.SJ_TWO_PASS)
     s, n2 = sj.distance_join_into(Pd, Qd, eps, None, g2)
     assert s == sj.SJ_OK and n2 == n
+
+
+def test_tuned_schedule_keeps_the_result():
+    mix = datagen.mixture_spec(30, 41)
+    P = datagen.points_mixture(120_000, mix, 0.2, 42)
+    Q = datagen.points_mixture(100_000, mix, 0.2, 43)
+    eps = 1.5e-3
+    ref = oracle.distance_filter_refine(P, Q, eps, 128)
+    Pd, Qd = to_dev(P), to_dev(Q)
+    g = sj.make_grid(0)
+    best = sj.distance_tune(Pd, Qd, eps, g, reps=1)
+    assert g.k >= 1 and best["block"] in (64, 128, 256, 512)
+    got, _ = sj.distance_join(Pd, Qd, eps)
+    assert np.array_equal(sort_pairs(got.cpu().numpy()), ref)
+    sj.tune_clear()
