@@ -57,6 +57,8 @@ def parse():
                     help="sweep every tile along x (no per-tile sweeping-axis model)")
     ap.add_argument("--gbda", action="store_true",
                     help="join dense tiles as the 9 GBDA class mini-joins (no duplicate test)")
+    ap.add_argument("--sorted", action="store_true",
+                    help="write the pairs in lexicographic (r, s) order (SJ_SORTED_OUTPUT)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--count", action="store_true", help="count-only join mode")
@@ -378,7 +380,7 @@ def main():
 
     def step(plain):
         stripes = ((sj.SJ_STRIPES if args.stripes else 0) | (sj.SJ_SWEEP_X if args.sweep_x else 0) |
-                   (sj.SJ_GBDA if args.gbda else 0))
+                   (sj.SJ_GBDA if args.gbda else 0) | (sj.SJ_SORTED_OUTPUT if args.sorted else 0))
         if args.k:
             K, tau = args.k, args.split_tau
         else:
@@ -461,7 +463,8 @@ def main():
     # the committed counter summary covers the default configuration only
     profiled = (main_mode == "tuned" and not (args.k or args.split_tau or args.stripes or
                                               args.sweep_x or args.gbda or args.two_pass or
-                                              args.count or args.no_tune) and args.picker == "auto")
+                                              args.count or args.no_tune or args.sorted) and
+                args.picker == "auto")
     roofline = {"kernel": dom, "bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s",
                 "frac": None if dk["gbs"] is None else round(dk["gbs"] / HBM_PEAK_GBS, 4),
@@ -502,6 +505,7 @@ def main():
                    "partitioning": "1-D stripes" if args.stripes else "2-D grid",
                    "sweep_axis": "y" if args.stripes else ("x" if args.sweep_x else "per-tile model"),
                    "dense_tiles": "GBDA mini-joins" if args.gbda else "Eq. (1) test",
+                   "pair_order": "sorted (r, s)" if args.sorted else "unspecified",
                    "schedule": main_mode, "mode": "count" if args.count else "pairs",
                    "autotuned": r["tuning"]},
         "pairs_per_s": round(P / (ms * 1e-3), 1),

@@ -89,6 +89,10 @@ typedef enum {
                                    9 class pairs that can hold a pair whose reference point is
                                    in the tile), each split into pivot ranges, with no
                                    duplicate test; never changes the result                */
+#define SJ_SORTED_OUTPUT 0x40u  /* sj_join, sj_distance_join: the pairs are written in
+                                   lexicographic (r, s) order (sj_sort_pairs after the
+                                   join), so the output bytes do not depend on the grid or
+                                   schedule; without it the order is unspecified           */
 
 /*
  * The uniform grid (Sec. 2.2; K x K tiles, Sec. 4.3.2).
@@ -102,7 +106,8 @@ typedef enum {
  *   domain     x0, y0, x1, y1 of the gridded region; all zero = the unit
  *              square [0,1)^2 (the paper normalises data to [0,1], Sec. 4.1).
  *              Rectangles outside it are clamped into the border tiles.
- *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS, SJ_STRIPES, SJ_SWEEP_X, SJ_GBDA.
+ *   flags      SJ_PLAIN, SJ_RULE_ONLY, SJ_TWO_PASS, SJ_STRIPES, SJ_SWEEP_X, SJ_GBDA,
+ *              SJ_SORTED_OUTPUT.
  * Tile (tx, ty) holds the rectangles whose cell ranges
  * [cell(x_l), cell(x_u)] x [cell(y_l), cell(y_u)] contain it, with
  * cell(v) = clamp(floor((v - x0) * K / (x1 - x0)), 0, K - 1) in float32.
@@ -270,6 +275,20 @@ typedef struct {
 } sj_join_stats;
 
 sj_status sj_last_join_stats(sj_join_stats* out);
+
+/*
+ * Canonical order of a result set (Sec. 1 defines J as a set; this gives it
+ * one reproducible order): sorts pairs[0..n) in place by (r, s),
+ * lexicographically, with a device radix sort of the 64-bit keys
+ * (r << 32) | s over the digits that r < n_r and s < n_s can set.
+ *   pairs     device, n sj_pair, 8-byte aligned; every r in [0, n_r) and
+ *             every s in [0, n_s) (the caller's input sizes), else the
+ *             order is unspecified.
+ *   n         < 2^32 (else SJ_ERR_TOO_LARGE).
+ * Enqueued on the stream (no synchronisation); a library-owned buffer of n
+ * pairs is kept per device.  Stable, so equal pairs keep their order.
+ */
+sj_status sj_sort_pairs(sj_pair* pairs, int64_t n, int64_t n_r, int64_t n_s, void* stream);
 
 /*
  * The sweeping-axis model of Sec. 3.3 for chosen tiles of two partitioned

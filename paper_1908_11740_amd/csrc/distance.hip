@@ -275,7 +275,9 @@ sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t n
         hipStreamSynchronize(s) != hipSuccess)
         return SJ_ERR_DEVICE;
     *n_pairs = (int64_t)*d.host;
-    return (out && *n_pairs > capacity) ? SJ_ERR_CAPACITY : SJ_OK;
+    if (out && *n_pairs > capacity) return SJ_ERR_CAPACITY;
+    if (out && (g->flags & SJ_SORTED_OUTPUT)) return sj_sort_pairs(out, *n_pairs, nP, nQ, stream);
+    return SJ_OK;
 }
 
 sj_status sj_distance_tune(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,

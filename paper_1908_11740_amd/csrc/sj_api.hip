@@ -355,6 +355,8 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
     }
     *n_pairs = (int64_t)hs.n_pairs;
     if (!count_only && (int64_t)hs.n_pairs > capacity) return SJ_ERR_CAPACITY;
+    if (!count_only && (R->grid.flags & SJ_SORTED_OUTPUT))
+        return sj_sort_pairs(out, *n_pairs, R->n, S->n, s);
     return SJ_OK;
 }
 

@@ -29,6 +29,7 @@ SJ_TWO_PASS = 0x4
 SJ_STRIPES = 0x8
 SJ_SWEEP_X = 0x10
 SJ_GBDA = 0x20
+SJ_SORTED_OUTPUT = 0x40
 INT32_MAX = 2**31 - 1
 
 
@@ -145,6 +146,7 @@ def lib():
                                       vp, vp]
         L.sj_mlp_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, ctypes.c_int32, vp]
         L.sj_sweep_axis.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.sj_sort_pairs.argtypes = [vp, i64, i64, i64, vp]
         L.sj_distance_join.argtypes = [vp, i64, vp, i64, f32, ctypes.POINTER(Grid), vp, i64,
                                        i64p, vp]
         L.sj_distance_last_info.argtypes = [ctypes.POINTER(DistanceInfo)]
@@ -153,7 +155,7 @@ def lib():
         for f in ("sj_partition", "sj_join", "sj_join_count", "sj_part_info", "sj_part_download",
                   "sj_features", "sj_choose_grid", "sj_picker_load", "sj_mlp_forward",
                   "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam", "sj_distance_join", "sj_sweep_axis",
-                  "sj_distance_last_info", "sj_distance_tune"):
+                  "sj_distance_last_info", "sj_distance_tune", "sj_sort_pairs"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -372,6 +374,17 @@ def distance_last_info():
     d = DistanceInfo()
     _check(lib().sj_distance_last_info(ctypes.byref(d)), "sj_distance_last_info")
     return {f: getattr(d, f) for f, _ in DistanceInfo._fields_}
+
+
+def sort_pairs(pairs, n_r, n_s, stream=None):
+    """sj_sort_pairs: sort an (n, 2) int32 device tensor of (r, s) pairs in
+    place, lexicographically; r < n_r and s < n_s."""
+    if not (isinstance(pairs, torch.Tensor) and pairs.is_cuda and pairs.dtype == torch.int32 and
+            pairs.dim() == 2 and pairs.shape[1] == 2 and pairs.is_contiguous()):
+        raise ValueError("pairs must be a contiguous (n, 2) int32 CUDA tensor")
+    _check(lib().sj_sort_pairs(_ptr(pairs), pairs.shape[0], int(n_r), int(n_s), _stream(stream)),
+           "sj_sort_pairs")
+    return pairs
 
 
 def sweep_axis(R, S, tiles, stream=None):
