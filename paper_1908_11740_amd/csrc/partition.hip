@@ -16,7 +16,8 @@
 //   level 1        workgroup w counts, in LDS, the coarse cells its chunk of
 //                  rectangles covers; a scan over (cell, w) gives every
 //                  workgroup a sub-segment per coarse cell; the second read
-//                  writes (box, id) into it (LDS cursors).
+//                  writes (box, id) into it, as a box array and an id array
+//                  (the level-2 count reads the boxes only).
 //   level 2        every coarse cell is cut into chunks of at most kChunk2
 //                  level-1 entries; each chunk counts, in LDS, the tiles of
 //                  its cell its entries cover; a scan over (cell, tile, chunk)
@@ -113,7 +114,8 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
 __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__ rects, int64_t n,
                                                       GridDev g, Blocking bl, int64_t ch1,
                                                       const uint32_t* __restrict__ o1,
-                                                      Entry* __restrict__ e1, int64_t cap_m1,
+                                                      float4* __restrict__ e1,
+                                                      uint32_t* __restrict__ e1i, int64_t cap_m1,
                                                       DevStatus* __restrict__ st) {
     extern __shared__ uint32_t cur[];  // [G1]
     if (aborted(st)) return;
@@ -144,8 +146,8 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
                     err |= kStatCapacity;
                     continue;
                 }
-                e1[slot].b = a;
-                e1[slot].m = make_uint4((uint32_t)i, 0u, 0u, 0u);
+                e1[slot] = a;
+                e1i[slot] = (uint32_t)i;
             }
     }
     if (err) atomicOr(&st->flags, err);
@@ -162,7 +164,8 @@ static_assert(kL1StageChunk <= (1 << 16), "chunk positions take 16 bits");
 
 __global__ __launch_bounds__(1024) void k_l1_scatter_staged(
     const float4* __restrict__ rects, int64_t n, GridDev g, Blocking bl, int64_t ch1, int64_t nb1,
-    const uint32_t* __restrict__ o1, Entry* __restrict__ e1, int64_t cap_m1,
+    const uint32_t* __restrict__ o1, float4* __restrict__ e1, uint32_t* __restrict__ e1i,
+    int64_t cap_m1,
     DevStatus* __restrict__ st) {
     constexpr int NT = 1024;
     __shared__ float4 s_box[kL1StageChunk];
@@ -234,8 +237,8 @@ __global__ __launch_bounds__(1024) void k_l1_scatter_staged(
                             err |= kStatCapacity;
                             continue;
                         }
-                        e1[ls].b = a;
-                        e1[ls].m = make_uint4((uint32_t)i, 0u, 0u, 0u);
+                        e1[ls] = a;
+                        e1i[ls] = (uint32_t)i;
                         continue;
                     }
                     if (ls >= total) {  // counts disagree with the histogram: cannot happen
@@ -254,8 +257,8 @@ __global__ __launch_bounds__(1024) void k_l1_scatter_staged(
                     err |= kStatCapacity;
                     continue;
                 }
-                e1[d].b = s_box[p];
-                e1[d].m = make_uint4((uint32_t)(lo + p), 0u, 0u, 0u);
+                e1[d] = s_box[p];
+                e1i[d] = (uint32_t)(lo + p);
             }
             __syncthreads();
         }
@@ -355,7 +358,7 @@ __device__ __forceinline__ Local local_range(const Cells& c, const Chunk& k, con
     return l;
 }
 
-__global__ __launch_bounds__(kL1NT) void k_l2_count(const Entry* __restrict__ e1,
+__global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e1,
                                                     const uint32_t* __restrict__ o1, int64_t nb1,
                                                     const uint32_t* __restrict__ cp,
                                                     const uint32_t* __restrict__ chunk_cell,
@@ -371,10 +374,10 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const Entry* __restrict__ e1
         for (int i = threadIdx.x; i < B2; i += blockDim.x) hist[i] = 0u;
         __syncthreads();
         uint32_t e = k.e0 + threadIdx.x;
-        float4 nxt = e < k.e1 ? e1[e].b : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 nxt = e < k.e1 ? e1[e] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (; e < k.e1; e += blockDim.x) {
             const float4 cur = nxt;
-            if (e + blockDim.x < k.e1) nxt = e1[e + blockDim.x].b;
+            if (e + blockDim.x < k.e1) nxt = e1[e + blockDim.x];
             const Local l = local_range(cells_of(cur, g), k, bl);
             for (int y = l.y0; y <= l.y1; ++y)
                 for (int x = l.x0; x <= l.x1; ++x) atomicAdd(&hist[y * bl.Bx + x], 1u);
@@ -386,7 +389,8 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const Entry* __restrict__ e1
     }
 }
 
-__global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ e1,
+__global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__ e1,
+                                                      const uint32_t* __restrict__ e1i,
                                                       const uint32_t* __restrict__ o1, int64_t nb1,
                                                       const uint32_t* __restrict__ cp,
                                                       const uint32_t* __restrict__ chunk_cell,
@@ -408,15 +412,15 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const Entry* __restrict__ 
         float4 nb = make_float4(0.f, 0.f, 0.f, 0.f);
         uint32_t nid = 0;
         if (e < k.e1) {
-            nb = e1[e].b;
-            nid = e1[e].m.x;
+            nb = e1[e];
+            nid = e1i[e];
         }
         for (; e < k.e1; e += blockDim.x) {
             const float4 a = nb;
             const uint32_t id = nid;
             if (e + blockDim.x < k.e1) {  // the next entry is loaded while this one is placed
-                nb = e1[e + blockDim.x].b;
-                nid = e1[e + blockDim.x].m.x;
+                nb = e1[e + blockDim.x];
+                nid = e1i[e + blockDim.x];
             }
             const Cells c = cells_of(a, g);
             const Local l = local_range(c, k, bl);
@@ -454,7 +458,8 @@ constexpr uint32_t kSrcFx = 1u << 12, kSrcFy = 1u << 13;  // start bits of a sta
 static_assert(kChunk2 <= (1 << 12), "chunk positions take 12 bits");
 
 __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
-    const Entry* __restrict__ e1, const uint32_t* __restrict__ o1, int64_t nb1,
+    const float4* __restrict__ e1, const uint32_t* __restrict__ e1i, const uint32_t* __restrict__ o1,
+    int64_t nb1,
     const uint32_t* __restrict__ cp, const uint32_t* __restrict__ chunk_cell, GridDev g, Blocking bl,
     const uint32_t* __restrict__ o2, Entry* __restrict__ ent, int64_t cap_m,
     DevStatus* __restrict__ st) {
@@ -523,8 +528,8 @@ __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
         __syncthreads();
         // rank every tile entry of the chunk (direct path: store it at once)
         for (uint32_t e = k.e0 + tid; e < k.e1; e += kStageNT) {
-            const float4 a = e1[e].b;
-            const uint32_t id = e1[e].m.x;
+            const float4 a = e1[e];
+            const uint32_t id = e1i[e];
             const uint32_t p = e - k.e0;
             if (staged) {
                 s_box[p] = a;
@@ -823,10 +828,10 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
         ProfRange pr("k_l1_scatter", s);
         if (l1_staged(n, G1))
             hipLaunchKernelGGL(k_l1_scatter_staged, dim3(num_cus), dim3(1024), 0, s, rects, n, P.gd,
-                               bl, ch1, nb1, P.h1, P.e1, P.cap_m1, P.st);
+                               bl, ch1, nb1, P.h1, P.e1, P.e1i, P.cap_m1, P.st);
         else
             hipLaunchKernelGGL(k_l1_scatter, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
-                               P.gd, bl, ch1, P.h1, P.e1, P.cap_m1, P.st);
+                               P.gd, bl, ch1, P.h1, P.e1, P.e1i, P.cap_m1, P.st);
     }
     {
         ProfRange pr("k_plan", s);
@@ -847,10 +852,10 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
         ProfRange pr("k_l2_scatter", s);
         if (B2 <= kStageMaxB2)
             hipLaunchKernelGGL(k_l2_scatter_staged, dim3(num_cus), dim3(kStageNT), 0, s, P.e1,
-                               P.h1, nb1,
+                               P.e1i, P.h1, nb1,
                                P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m, P.st);
         else
-            hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1,
+            hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1, P.e1i,
                                P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m,
                                P.st);
     }

@@ -299,6 +299,7 @@ hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
             hipSuccess)
         return e;
     if ((e = grow(P->e1, P->cap_m1, need_m1)) != hipSuccess) return e;
+    if ((e = grow(P->e1i, P->cap_m1i, P->cap_m1)) != hipSuccess) return e;
     if ((e = grow(P->ent, P->cap_m, need_m)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -613,7 +614,7 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
 
 void sj_part_free(sj_part* P) {
     if (!P) return;
-    void* bufs[] = {P->h1, P->e1, P->cp, P->chunk_cell, P->h2, P->ent, P->off, P->scan_tmp, P->st};
+    void* bufs[] = {P->h1, P->e1, P->e1i, P->cp, P->chunk_cell, P->h2, P->ent, P->off, P->scan_tmp, P->st};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete P;

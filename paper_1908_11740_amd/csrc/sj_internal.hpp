@@ -112,8 +112,9 @@ struct Part {
     int64_t nb1 = 0;        // level-1 workgroups of the last call
     uint32_t* h1 = nullptr;   // [cap_h1]  level-1 histograms -> offsets (scanned in place)
     int64_t cap_h1 = 0;
-    Entry* e1 = nullptr;      // [cap_m1]  level-1 entries
-    int64_t cap_m1 = 0;
+    float4* e1 = nullptr;     // [cap_m1]  level-1 entries: boxes ...
+    uint32_t* e1i = nullptr;  // [cap_m1]  ... and rectangle indices
+    int64_t cap_m1 = 0, cap_m1i = 0;
     uint32_t* cp = nullptr;   // [G*G + 1] chunk prefix per coarse cell
     int64_t cap_cp = 0;
     uint32_t* chunk_cell = nullptr;  // [cap_chunks] coarse cell of each chunk
