@@ -39,7 +39,8 @@ hipError_t grow_buf(T*& p, int64_t& cap, int64_t need, bool zero = false) {
 }
 
 void free_part(Part& P) {  // st belongs to the batch's status array
-    void* bufs[] = {P.h1, P.e1, P.e1i, P.cp, P.chunk_cell, P.h2, P.ent, P.off, P.scan_tmp};
+    void* bufs[] = {P.h1, P.e1, P.e1i, P.cp, P.chunk_cell, P.h2, P.entb, P.enti, P.off,
+                    P.scan_tmp};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     P = Part{};

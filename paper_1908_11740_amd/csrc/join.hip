@@ -74,8 +74,10 @@ constexpr int kDenseNT = 256;
 struct Args {
     const uint32_t* offR;
     const uint32_t* offS;
-    Entry* entR;      // tile slabs; the counting pass writes each slab back sorted
-    Entry* entS;
+    float4* entR;     // tile slabs: boxes; the counting pass writes each slab back sorted
+    float4* entS;
+    uint32_t* idR;    // ... and id words (position | start bits)
+    uint32_t* idS;
     int64_t C;        // blocked tiles
     int small_cap;    // small tiles: nr + ns <= small_cap
     int unit_cap;     // entries per small unit (target)
@@ -624,9 +626,8 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
             const int k = L.tk[e];
             const uint32_t g = isR ? L.rg[k] + (uint32_t)e - L.rl[k]
                                    : L.sg[k] + (uint32_t)(e - NR) - L.sl[k];
-            const Entry* en = isR ? a.entR + g : a.entS + g;
-            pb[q] = en->b;
-            pi[q] = en->m.x;
+            pb[q] = (isR ? a.entR : a.entS)[g];
+            pi[q] = (isR ? a.idR : a.idS)[g];
             pg[q] = g;
         }
     }
@@ -731,11 +732,11 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
                 float4 b = L.bx[e];
                 if (swap) b = make_float4(b.y, b.x, b.w, b.z);
                 if (e < NR) {
-                    a.entR[pg[q]].b = b;
-                    a.entR[pg[q]].m = make_uint4(L.id[e], 0u, 0u, 0u);
+                    a.entR[pg[q]] = b;
+                    a.idR[pg[q]] = L.id[e];
                 } else {
-                    a.entS[pg[q]].b = b;
-                    a.entS[pg[q]].m = make_uint4(L.id[e], 0u, 0u, 0u);
+                    a.entS[pg[q]] = b;
+                    a.idS[pg[q]] = L.id[e];
                 }
             }
         }
@@ -996,9 +997,8 @@ __device__ bool stage_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const W
             const bool isR = e < NR;
             const int k = T.tk[e];
             const uint32_t g = isR ? W.rg[k] + (uint32_t)e - T.rl[k] : W.sg[k] + (uint32_t)(e - NR) - T.sl[k];
-            const Entry* en = isR ? a.entR + g : a.entS + g;
-            st.pb[q] = en->b;
-            st.pi[q] = en->m.x;
+            st.pb[q] = (isR ? a.entR : a.entS)[g];
+            st.pi[q] = (isR ? a.idR : a.idS)[g];
             st.pg[q] = g;
         }
     }
@@ -1058,11 +1058,11 @@ __device__ void sweep_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const W
                     const float4 b = W.bx[e];
                     const uint32_t idv = W.id[e];
                     if (e < NR) {
-                        a.entR[st.pg[q]].b = b;
-                        a.entR[st.pg[q]].m = make_uint4(idv, 0u, 0u, 0u);
+                        a.entR[st.pg[q]] = b;
+                        a.idR[st.pg[q]] = idv;
                     } else {
-                        a.entS[st.pg[q]].b = b;
-                        a.entS[st.pg[q]].m = make_uint4(idv, 0u, 0u, 0u);
+                        a.entS[st.pg[q]] = b;
+                        a.idS[st.pg[q]] = idv;
                     }
                 }
             }
@@ -1400,8 +1400,10 @@ __device__ __forceinline__ void blocked_xy(const Blocking& bl, uint32_t t, int& 
     ty = (int)(cell / (uint32_t)bl.Gx) * bl.By + (int)(r / (uint32_t)bl.Bx);
 }
 
-__device__ AxisOut axis_eval(const Entry* __restrict__ eR, uint32_t nr, const Entry* __restrict__ eS,
-                             uint32_t ns, int tx, int ty, const GridDev& g, AxisLds& L) {
+__device__ AxisOut axis_eval(const float4* __restrict__ bR, const uint32_t* __restrict__ iR,
+                             uint32_t nr, const float4* __restrict__ bS,
+                             const uint32_t* __restrict__ iS, uint32_t ns, int tx, int ty,
+                             const GridDev& g, AxisLds& L) {
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     constexpr int NW = kAxisNT / kWave;
     const uint32_t n = nr + ns;
@@ -1410,9 +1412,9 @@ __device__ AxisOut axis_eval(const Entry* __restrict__ eR, uint32_t nr, const En
     unsigned long long ext = 0;
     for (uint32_t i = tid; i < n; i += kAxisNT) {
         const bool isR = i < nr;
-        const Entry* e = isR ? eR + i : eS + (i - nr);
-        if ((e->m.x & kIdMask) % kAxisPhi == 0u) {
-            const float4 b = e->b;
+        const uint32_t j = isR ? i : i - nr;
+        if (((isR ? iR : iS)[j] & kIdMask) % kAxisPhi == 0u) {
+            const float4 b = (isR ? bR : bS)[j];
             ext += fixed_extent(b.x, b.z, g.sx) + fixed_extent(b.y, b.w, g.sy);
             if (isR) ++cR;
             else ++cS;
@@ -1449,9 +1451,9 @@ __device__ AxisOut axis_eval(const Entry* __restrict__ eR, uint32_t nr, const En
     __syncthreads();
     for (uint32_t i = tid; i < n; i += kAxisNT) {
         const bool isR = i < nr;
-        const Entry* e = isR ? eR + i : eS + (i - nr);
-        if ((e->m.x & kIdMask) % kAxisPhi == 0u) {
-            const float4 b = e->b;
+        const uint32_t j = isR ? i : i - nr;
+        if (((isR ? iR : iS)[j] & kIdMask) % kAxisPhi == 0u) {
+            const float4 b = (isR ? bR : bS)[j];
             int* hx = L.hist[isR ? 0 : 2];
             int* hy = L.hist[isR ? 1 : 3];
             atomicAdd(&hx[division(b.x, g.x0, g.sx, tx, k)], 1);
@@ -1531,24 +1533,24 @@ __global__ __launch_bounds__(kAxisNT) void k_axis(Args a) {
     for (uint32_t j = blockIdx.x; j < nm + nd; j += gridDim.x) {
         const bool med = j < nm;
         const uint4 rec = med ? a.med[j] : a.dense[j - nm];
-        uint32_t t, nr, ns;
-        const Entry *eR, *eS;
+        uint32_t t, nr, ns, r0, s0;
         if (med) {
             t = a.medt[j];
-            eR = a.entR + rec.x;
+            r0 = rec.x;
             nr = rec.y;
-            eS = a.entS + rec.z;
+            s0 = rec.z;
             ns = rec.w;
         } else {
             t = rec.x;
-            eR = a.entR + a.offR[t];
+            r0 = a.offR[t];
             nr = rec.z;
-            eS = a.entS + a.offS[t];
+            s0 = a.offS[t];
             ns = rec.w;
         }
         int tx, ty;
         blocked_xy(a.bl, t, tx, ty);
-        const AxisOut o = axis_eval(eR, nr, eS, ns, tx, ty, a.gd, L);
+        const AxisOut o = axis_eval(a.entR + r0, a.idR + r0, nr, a.entS + s0, a.idS + s0, ns, tx, ty,
+                                    a.gd, L);
         if (threadIdx.x == 0) {
             ++nt;
             if (o.iy < o.ix) {
@@ -1567,8 +1569,10 @@ __global__ __launch_bounds__(kAxisNT) void k_axis(Args a) {
 // The model for listed tiles (sj_sweep_axis).
 __global__ __launch_bounds__(kAxisNT) void k_axis_query(const uint32_t* __restrict__ offR,
                                                         const uint32_t* __restrict__ offS,
-                                                        const Entry* __restrict__ entR,
-                                                        const Entry* __restrict__ entS, GridDev gd,
+                                                        const float4* __restrict__ entR,
+                                                        const uint32_t* __restrict__ idR,
+                                                        const float4* __restrict__ entS,
+                                                        const uint32_t* __restrict__ idS, GridDev gd,
                                                         Blocking bl, const int2* __restrict__ tiles,
                                                         int64_t n, long long* __restrict__ out) {
     __shared__ AxisLds L;
@@ -1579,7 +1583,8 @@ __global__ __launch_bounds__(kAxisNT) void k_axis_query(const uint32_t* __restri
                            (uint32_t)(xy.y % bl.By) * (uint32_t)bl.Bx + (uint32_t)(xy.x % bl.Bx);
         const uint32_t r0 = offR[t], s0 = offS[t];
         const AxisOut o =
-            axis_eval(entR + r0, offR[t + 1] - r0, entS + s0, offS[t + 1] - s0, xy.x, xy.y, gd, L);
+            axis_eval(entR + r0, idR + r0, offR[t + 1] - r0, entS + s0, idS + s0, offS[t + 1] - s0,
+                      xy.x, xy.y, gd, L);
         if (threadIdx.x == 0) {
             out[4 * j] = o.k;
             out[4 * j + 1] = (long long)o.ix;
@@ -1725,12 +1730,12 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
         const uint32_t src = sideS ? a.offS[tile] : a.offR[tile];
         const uint32_t L = sideS ? dd.w : dd.z;
         const uint32_t dst = dd.y + (sideS ? dd.z : 0u);
-        const Entry* ent = sideS ? a.entS : a.entR;
+        const float4* ent = sideS ? a.entS : a.entR;
+        const uint32_t* eid = sideS ? a.idS : a.idR;
         // key: (GBDA class,) order key of the lower edge, position
         auto key_of = [&](uint32_t i) -> unsigned long long {
-            const Entry& en = ent[src + i];
-            const unsigned long long ok = order_key(lower_edge(en.b, swap));
-            return a.gbda ? ((unsigned long long)gbda_class(en.m.x) << 62) | (ok << 30) | i
+            const unsigned long long ok = order_key(lower_edge(ent[src + i], swap));
+            return a.gbda ? ((unsigned long long)gbda_class(eid[src + i]) << 62) | (ok << 30) | i
                           : (ok << 32) | i;
         };
         const unsigned long long pos_mask = a.gbda ? 0x3FFFFFFFull : 0xFFFFFFFFull;
@@ -1738,7 +1743,7 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             if (threadIdx.x < 4) s_cls[threadIdx.x] = 0u;
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < L; i += blockDim.x)
-                atomicAdd(&s_cls[gbda_class(ent[src + i].m.x)], 1u);
+                atomicAdd(&s_cls[gbda_class(eid[src + i])], 1u);
             __syncthreads();
             if (threadIdx.x == 0) {
                 uint32_t* g = a.dgrp + (size_t)(seg >> 1) * 10 + (sideS ? 5 : 0);
@@ -1806,9 +1811,9 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
         }
         for (uint32_t i = threadIdx.x; i < L; i += blockDim.x) {
             const uint32_t q = (uint32_t)(fin[i] & pos_mask);
-            const float4 b = ent[src + q].b;
+            const float4 b = ent[src + q];
             a.dbox[dst + i] = swap ? make_float4(b.y, b.x, b.w, b.z) : b;
-            a.didf[dst + i] = ent[src + q].m.x;
+            a.didf[dst + i] = eid[src + q];
         }
         __syncthreads();
     }
@@ -2146,8 +2151,10 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     Args a{};
     a.offR = R.off;
     a.offS = S.off;
-    a.entR = R.ent;
-    a.entS = S.ent;
+    a.entR = R.entb;
+    a.entS = S.entb;
+    a.idR = R.enti;
+    a.idS = S.enti;
     a.C = p.C;
     a.small_cap = p.small_cap;
     a.unit_cap = p.unit_cap;
@@ -2290,7 +2297,8 @@ hipError_t axis_query(const Part& R, const Part& S, const int32_t* tiles, int64_
                       int num_cus, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const unsigned g = (unsigned)std::min<int64_t>(n, (int64_t)num_cus * 8);
-    hipLaunchKernelGGL(k_axis_query, dim3(g), dim3(kAxisNT), 0, s, R.off, S.off, R.ent, S.ent, R.gd,
+    hipLaunchKernelGGL(k_axis_query, dim3(g), dim3(kAxisNT), 0, s, R.off, S.off, R.entb, R.enti,
+                       S.entb, S.enti, R.gd,
                        R.bl, (const int2*)tiles, n, (long long*)out);
     return hipGetLastError();
 }

@@ -396,7 +396,8 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__
                                                       const uint32_t* __restrict__ chunk_cell,
                                                       GridDev g, Blocking bl,
                                                       const uint32_t* __restrict__ o2,
-                                                      Entry* __restrict__ ent, int64_t cap_m,
+                                                      float4* __restrict__ entb,
+                                                      uint32_t* __restrict__ enti, int64_t cap_m,
                                                       DevStatus* __restrict__ st) {
     extern __shared__ uint32_t cur[];  // [B*B]
     if (aborted(st)) return;
@@ -433,8 +434,8 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__
                         err |= kStatCapacity;
                         continue;
                     }
-                    ent[slot].b = a;
-                    ent[slot].m = make_uint4(id | fy | ((bx + x == c.cx0) ? kBx : 0u), 0u, 0u, 0u);
+                    entb[slot] = a;
+                    enti[slot] = id | fy | ((bx + x == c.cx0) ? kBx : 0u);
                 }
             }
         }
@@ -461,8 +462,8 @@ __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
     const float4* __restrict__ e1, const uint32_t* __restrict__ e1i, const uint32_t* __restrict__ o1,
     int64_t nb1,
     const uint32_t* __restrict__ cp, const uint32_t* __restrict__ chunk_cell, GridDev g, Blocking bl,
-    const uint32_t* __restrict__ o2, Entry* __restrict__ ent, int64_t cap_m,
-    DevStatus* __restrict__ st) {
+    const uint32_t* __restrict__ o2, float4* __restrict__ entb, uint32_t* __restrict__ enti,
+    int64_t cap_m, DevStatus* __restrict__ st) {
     __shared__ float4 s_box[kChunk2];      // the chunk's level-1 entries
     __shared__ uint32_t s_id[kChunk2];
     __shared__ uint32_t s_dst[kStage];     // destination of each staged tile entry
@@ -549,8 +550,8 @@ __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
                             err |= kStatCapacity;
                             continue;
                         }
-                        ent[ls].b = a;
-                        ent[ls].m = make_uint4(id | (fy ? kBy : 0u) | (fx ? kBx : 0u), 0u, 0u, 0u);
+                        entb[ls] = a;
+                        enti[ls] = id | (fy ? kBy : 0u) | (fx ? kBx : 0u);
                         continue;
                     }
                     if (ls >= total) {  // counts disagree with the histogram: cannot happen
@@ -572,9 +573,8 @@ __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
                     continue;
                 }
                 const uint32_t p = sv & (kSrcFx - 1u);
-                ent[d].b = s_box[p];
-                ent[d].m = make_uint4(s_id[p] | ((sv & kSrcFx) ? kBx : 0u) | ((sv & kSrcFy) ? kBy : 0u),
-                                      0u, 0u, 0u);
+                entb[d] = s_box[p];
+                enti[d] = s_id[p] | ((sv & kSrcFx) ? kBx : 0u) | ((sv & kSrcFy) ? kBy : 0u);
             }
             __syncthreads();
         }
@@ -853,11 +853,12 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
         if (B2 <= kStageMaxB2)
             hipLaunchKernelGGL(k_l2_scatter_staged, dim3(num_cus), dim3(kStageNT), 0, s, P.e1,
                                P.e1i, P.h1, nb1,
-                               P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m, P.st);
+                               P.cp, P.chunk_cell, P.gd, bl, P.h2, P.entb, P.enti, P.cap_m,
+                               P.st);
         else
             hipLaunchKernelGGL(k_l2_scatter, dim3(nb2), dim3(kL1NT), B2 * 4, s, P.e1, P.e1i,
-                               P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.ent, P.cap_m,
-                               P.st);
+                               P.h1, nb1, P.cp, P.chunk_cell, P.gd, bl, P.h2, P.entb, P.enti,
+                               P.cap_m, P.st);
     }
     {
         ProfRange pr("k_tile_offsets", s);

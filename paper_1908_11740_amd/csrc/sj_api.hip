@@ -300,7 +300,8 @@ hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
         return e;
     if ((e = grow(P->e1, P->cap_m1, need_m1)) != hipSuccess) return e;
     if ((e = grow(P->e1i, P->cap_m1i, P->cap_m1)) != hipSuccess) return e;
-    if ((e = grow(P->ent, P->cap_m, need_m)) != hipSuccess) return e;
+    if ((e = grow(P->entb, P->cap_m, need_m)) != hipSuccess) return e;
+    if ((e = grow(P->enti, P->cap_mi, P->cap_m)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -590,11 +591,11 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
     const int64_t B2 = bl.tiles_per_cell();
     const int64_t Cb = (int64_t)bl.cells() * B2;
     std::vector<uint32_t> off((size_t)Cb + 1);
-    std::vector<Entry> raw((size_t)std::max<int64_t>(P->m, 1));
+    std::vector<uint32_t> raw((size_t)std::max<int64_t>(P->m, 1));
     if (hipMemcpy(off.data(), P->off, (size_t)(Cb + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess)
         return SJ_ERR_DEVICE;
     if (P->m > 0 &&
-        hipMemcpy(raw.data(), P->ent, (size_t)P->m * sizeof(Entry), hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(raw.data(), P->enti, (size_t)P->m * 4, hipMemcpyDeviceToHost) != hipSuccess)
         return SJ_ERR_DEVICE;
     // regroup from the blocked tile order into row-major tile order of the
     // partition grid (stripes: kx = 1, one row per stripe)
@@ -606,7 +607,7 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
                                (int64_t)(ty - gy * bl.By) * bl.Bx + (tx - gx * bl.Bx);
             if (offsets) offsets[(int64_t)ty * kx + tx] = at;
             for (uint32_t q = off[bt]; q < off[bt + 1]; ++q, ++at)
-                if (ids) ids[at] = (int32_t)(raw[q].m.x & kIdMask);
+                if (ids) ids[at] = (int32_t)(raw[q] & kIdMask);
         }
     if (offsets) offsets[(int64_t)kx * ky] = at;
     return SJ_OK;
@@ -614,7 +615,8 @@ sj_status sj_part_download(const sj_part* P, int64_t* offsets, int32_t* ids, voi
 
 void sj_part_free(sj_part* P) {
     if (!P) return;
-    void* bufs[] = {P->h1, P->e1, P->e1i, P->cp, P->chunk_cell, P->h2, P->ent, P->off, P->scan_tmp, P->st};
+    void* bufs[] = {P->h1, P->e1, P->e1i, P->cp, P->chunk_cell, P->h2, P->entb, P->enti, P->off,
+                    P->scan_tmp, P->st};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete P;

@@ -49,15 +49,6 @@ constexpr uint32_t kIdMask = 0x3FFFFFFFu;
 constexpr uint32_t kBx = 0x40000000u;
 constexpr uint32_t kBy = 0x80000000u;
 
-// A partition entry: the rectangle (x_l, y_l, x_u, y_u) and its id word,
-// padded to one 32-byte sector so that a scattered entry write is a single
-// full-sector HBM write (a 16-byte and a separate 4-byte store would each
-// cost a 32-byte request).  m.y..m.w are zero.
-struct __attribute__((aligned(32))) Entry {
-    float4 b;
-    uint4 m;
-};
-
 // Device-side status word bits.
 constexpr uint32_t kStatBadRect = 1u;
 constexpr uint32_t kStatCapacity = 2u;  // an internal buffer was too small (sizes reported)
@@ -121,8 +112,9 @@ struct Part {
     int64_t cap_chunks = 0;
     uint32_t* h2 = nullptr;   // [B*B*cap_chunks + 1] level-2 histograms -> offsets
     int64_t cap_h2 = 0;
-    Entry* ent = nullptr;     // [cap_m]   tile entries (id word: position | start bits)
-    int64_t cap_m = 0;
+    float4* entb = nullptr;   // [cap_m]   tile entries: boxes ...
+    uint32_t* enti = nullptr; // [cap_m]   ... and id words (position | start bits)
+    int64_t cap_m = 0, cap_mi = 0;
     uint32_t* off = nullptr;  // [G*G*B*B + 1] segment start per blocked tile
     int64_t cap_off = 0;
     uint32_t* scan_tmp = nullptr;
