@@ -603,11 +603,21 @@ __global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t* __restr
     }
 }
 
-// ---- exclusive scan (reduce, top-level scan, down-sweep), in place allowed ----
-constexpr int kScanItems = 16;
-constexpr int kScanChunk = kBlock * kScanItems;
+// ---- exclusive scan, in place allowed ----
+// k_scan_reduce  the sum of every tile of kScanChunk counters -> bs[tile];
+// k_scan_top     (more than kScanDirect tiles only) exclusive scan of bs in
+//                place, by one workgroup;
+// k_scan_final   the tile's prefix -- the sum of bs over the tiles before it
+//                (at most kScanDirect cached words), or bs[tile] after
+//                k_scan_top -- plus the scan within the tile.
+// Items of a tile: round k covers [k*1024, (k+1)*1024); thread t holds 4
+// consecutive counters of each round, loaded and stored as uint4.
+constexpr int kScanRounds = 8;
+constexpr int kScanChunk = kBlock * 4 * kScanRounds;
+constexpr int64_t kScanDirect = 2048;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
         const uint32_t t = __shfl_up(v, d, kWave);
         if (lane >= d) v += t;
@@ -641,6 +651,24 @@ __device__ __forceinline__ int64_t scan_len(int64_t cmax, const uint32_t* dyn, i
     return c < cmax ? c : cmax;
 }
 
+// The tile's counters, thread t's four of every round.
+__device__ __forceinline__ void load_tile(const uint32_t* cnt, int64_t base, int64_t C,
+                                          uint4 (&v)[kScanRounds]) {
+    const bool full = base + kScanChunk <= C;
+#pragma unroll
+    for (int k = 0; k < kScanRounds; ++k) {
+        const int64_t i = base + (int64_t)k * (kBlock * 4) + threadIdx.x * 4;
+        if (full) {
+            v[k] = *(const uint4*)(cnt + i);
+        } else {
+            v[k].x = i < C ? cnt[i] : 0u;
+            v[k].y = i + 1 < C ? cnt[i + 1] : 0u;
+            v[k].z = i + 2 < C ? cnt[i + 2] : 0u;
+            v[k].w = i + 3 < C ? cnt[i + 3] : 0u;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt,
                                                        int64_t cmax, const uint32_t* dyn,
                                                        int64_t mult, uint32_t* __restrict__ bs,
@@ -649,14 +677,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
     if (aborted(st)) return;
     const int64_t C = scan_len(cmax, dyn, mult);
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    if (base >= C) return;
+    uint4 v[kScanRounds];
+    load_tile(cnt, base, C, v);
     uint32_t s = 0;
-    if (base < C) {
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            const int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-            if (i < C) s += cnt[i];
-        }
-    }
+    for (int k = 0; k < kScanRounds; ++k) s += v[k].x + v[k].y + v[k].z + v[k].w;
     for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
     __syncthreads();
@@ -669,8 +695,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
 
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bs, int64_t cmax,
                                                   const uint32_t* dyn, int64_t mult,
-                                                  uint32_t* __restrict__ off,
-                                                  unsigned long long* total_out,
+                                                  uint32_t* off,
+                                                  unsigned long long* __restrict__ total_out,
                                                   DevStatus* __restrict__ st) {
     __shared__ uint32_t lds[1024 / kWave + 1];
     if (aborted(st)) return;
@@ -696,30 +722,93 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bs, in
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* cnt, int64_t cmax,
-                                                     const uint32_t* dyn, int64_t mult,
-                                                     const uint32_t* __restrict__ bs, uint32_t* off,
-                                                     const DevStatus* __restrict__ st) {
-    __shared__ uint32_t lds[kBlock / kWave + 1];
+template <bool DIRECT>
+__global__ __launch_bounds__(kBlock) void k_scan_final(const uint32_t* cnt, int64_t cmax,
+                                                      const uint32_t* dyn, int64_t mult,
+                                                      const uint32_t* __restrict__ bs,
+                                                      uint32_t* off,
+                                                      unsigned long long* __restrict__ total_out,
+                                                      DevStatus* __restrict__ st) {
+    constexpr int kNW = kBlock / kWave;
+    __shared__ uint32_t s_wsum[kScanRounds][kNW];
+    __shared__ unsigned long long s_part[kNW];
     if (aborted(st)) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int64_t C = scan_len(cmax, dyn, mult);
-    if ((int64_t)blockIdx.x * kScanChunk >= C) return;
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        v[k] = i < C ? cnt[i] : 0u;
-        s += v[k];
+    const int64_t tile = blockIdx.x;
+    const int64_t ntiles = (C + kScanChunk - 1) / kScanChunk;
+    if (C == 0) {
+        if (tile == 0 && tid == 0) {
+            off[0] = 0u;
+            *total_out = 0ull;
+        }
+        return;
     }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(s, lds, tot) + bs[blockIdx.x];
+    if (tile >= ntiles) return;
+    const int64_t base = tile * kScanChunk;
+    uint4 v[kScanRounds];
+    load_tile(cnt, base, C, v);
+    // the tile's prefix (64-bit in the direct form, so the total is exact)
+    unsigned long long x = 0;
+    if (DIRECT) {
+        for (int64_t j = tid; j < tile; j += kBlock) x += bs[j];
+    } else if (tid == 0) {
+        x = bs[tile];
+    }
+    uint32_t sum[kScanRounds], inc[kScanRounds];
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int64_t i = base + k;
-        if (i < C) off[i] = ex;
-        ex += v[k];
+    for (int k = 0; k < kScanRounds; ++k) {
+        sum[k] = v[k].x + v[k].y + v[k].z + v[k].w;
+        inc[k] = wave_incl_scan(sum[k], lane);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < kScanRounds; ++k) s_wsum[k][w] = inc[k];
+    }
+    if (lane == 0) s_part[w] = x;
+    __syncthreads();
+    unsigned long long prefix = 0;
+#pragma unroll
+    for (int q = 0; q < kNW; ++q) prefix += s_part[q];
+    const bool full = base + kScanChunk <= C;
+    uint32_t before = 0;  // counters of the earlier rounds of this tile
+#pragma unroll
+    for (int k = 0; k < kScanRounds; ++k) {
+        uint32_t wpre = 0, rtot = 0;
+#pragma unroll
+        for (int q = 0; q < kNW; ++q) {
+            const uint32_t y = s_wsum[k][q];
+            wpre += q < w ? y : 0u;
+            rtot += y;
+        }
+        const unsigned long long b = prefix + before + wpre + inc[k] - sum[k];
+        uint4 o;
+        o.x = (uint32_t)b;
+        o.y = (uint32_t)(b + v[k].x);
+        o.z = (uint32_t)(b + v[k].x + v[k].y);
+        o.w = (uint32_t)(b + v[k].x + v[k].y + v[k].z);
+        const int64_t i = base + (int64_t)k * (kBlock * 4) + tid * 4;
+        if (full) {
+            *(uint4*)(off + i) = o;
+        } else {
+            if (i < C) off[i] = o.x;
+            if (i + 1 < C) off[i + 1] = o.y;
+            if (i + 2 < C) off[i + 2] = o.z;
+            if (i + 3 < C) off[i + 3] = o.w;
+        }
+        before += rtot;
+    }
+    if (DIRECT && tile == ntiles - 1 && tid == 0) {  // (else k_scan_top wrote the total)
+        const unsigned long long total = prefix + before;
+        if (total >= 0x7FFFFFFFull) {
+            atomicOr(&st->flags, kStatCapacity | kStatTooLarge);
+            off[C] = 0x7FFFFFFFu;
+        } else {
+            off[C] = (uint32_t)total;
+        }
+        *total_out = total;
     }
 }
 
@@ -735,15 +824,22 @@ int grid_for(int64_t n, int block, int max_blocks) {
     return (int)b;
 }
 
-// in-place capable exclusive scan of cmax (or *dyn * mult) counters
+// in-place capable exclusive scan of cmax (or *dyn * mult) counters; bs holds
+// scan_block_sums_needed(cmax) words
 void scan(uint32_t* data, int64_t cmax, const uint32_t* dyn, int64_t mult, uint32_t* bs,
           unsigned long long* total, DevStatus* st, hipStream_t s) {
-    const int64_t nb = (cmax + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(kBlock), 0, s,
-                       data, cmax, dyn, mult, bs, st);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bs, cmax, dyn, mult, data, total, st);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(kBlock), 0, s,
-                       data, cmax, dyn, mult, bs, data, st);
+    const int64_t nb = std::max<int64_t>((cmax + kScanChunk - 1) / kScanChunk, 1);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, data, cmax, dyn, mult,
+                       bs, st);
+    if (nb <= kScanDirect) {
+        hipLaunchKernelGGL(k_scan_final<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, data, cmax,
+                           dyn, mult, bs, data, total, st);
+    } else {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bs, cmax, dyn, mult, data, total,
+                           st);
+        hipLaunchKernelGGL(k_scan_final<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, data, cmax,
+                           dyn, mult, bs, data, total, st);
+    }
 }
 
 }  // namespace

@@ -116,6 +116,7 @@ struct SortState {
     uint32_t* bs = nullptr;
     int64_t cap_bs = 0;
     DevStatus* st = nullptr;  // always clear: the scan's abort word
+    hipEvent_t done = nullptr;  // end of the last sort's work: the next one waits for it
 };
 
 std::mutex g_smu;
@@ -170,6 +171,13 @@ extern "C" sj_status sj_sort_pairs(sj_pair* pairs, int64_t n, int64_t n_r, int64
         if (ensure(S.st, one, 1) != hipSuccess) return SJ_ERR_OOM;
         if (hipMemset(S.st, 0, sizeof(DevStatus)) != hipSuccess) return SJ_ERR_DEVICE;
     }
+    if (!S.done && hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess) {
+        S.done = nullptr;
+        return SJ_ERR_DEVICE;
+    }
+    // the library buffers are shared by every sort on this device: a sort
+    // enqueued on another stream runs after the previous one
+    if (hipStreamWaitEvent(s, S.done, 0) != hipSuccess) return SJ_ERR_DEVICE;
     // digit positions of the key (r << 32) | s that can be non-zero
     int shifts[8];
     int np = 0;
@@ -190,5 +198,6 @@ extern "C" sj_status sj_sort_pairs(sj_pair* pairs, int64_t n, int64_t n_r, int64
     }
     // the sorted keys are in src; back to pairs in the caller's buffer
     hipLaunchKernelGGL(k_rs_swap, dim3(grid_of(n)), dim3(256), 0, s, src, buf, n);
-    return hipGetLastError() == hipSuccess ? SJ_OK : SJ_ERR_DEVICE;
+    if (hipGetLastError() != hipSuccess || hipEventRecord(S.done, s) != hipSuccess) return SJ_ERR_DEVICE;
+    return SJ_OK;
 }
