@@ -38,6 +38,23 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kL1NT = 512;  // level-1 / level-2 workgroup size
 
+// Workgroups are dispatched to the eight XCDs round-robin (workgroup b runs on
+// XCD b % 8), and every XCD has its own L2.  The chunk histograms keep chunk
+// q and chunk q + 1 of a cell in adjacent words, so handing chunk q to
+// workgroup q would make eight L2s each fetch, or write back, the same
+// sectors for one word apiece.  xcd_slot gives the workgroups of one XCD
+// consecutive chunks instead: the first chunk of workgroup b in a grid of n
+// workgroups (n a multiple of 8; otherwise b).  Persistent loops go on with
+// q += n, so every chunk is still taken exactly once.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_slot(uint32_t b, uint32_t n) {
+    if (n % kXcds) return b;
+    return (b % kXcds) * (n / kXcds) + b / kXcds;
+}
+
+int64_t xcd_grid(int64_t nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
+
 __device__ __forceinline__ bool rect_ok(float4 a) {
     return isfinite(a.x) && isfinite(a.y) && isfinite(a.z) && isfinite(a.w) && a.x <= a.z &&
            a.y <= a.w;
@@ -83,10 +100,13 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
                                                     uint32_t* __restrict__ h1,
                                                     DevStatus* __restrict__ st) {
     extern __shared__ uint32_t hist[];  // [G1]
+    const int64_t nb = (n + ch1 - 1) / ch1;  // chunks (the grid is rounded up to whole XCD rows)
+    const int64_t q = xcd_slot(blockIdx.x, gridDim.x);
+    if (q >= nb) return;
     const int G1 = bl.cells();
     for (int i = threadIdx.x; i < G1; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * ch1;
+    const int64_t lo = q * ch1;
     const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
     bool bad = false;
     // the next rectangle is loaded while this one is counted
@@ -107,8 +127,7 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
     }
     if (bad) atomicOr(&st->flags, kStatBadRect);
     __syncthreads();
-    const int64_t nb = gridDim.x;
-    for (int i = threadIdx.x; i < G1; i += blockDim.x) h1[(int64_t)i * nb + blockIdx.x] = hist[i];
+    for (int i = threadIdx.x; i < G1; i += blockDim.x) h1[(int64_t)i * nb + q] = hist[i];
 }
 
 __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__ rects, int64_t n,
@@ -119,11 +138,13 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
                                                       DevStatus* __restrict__ st) {
     extern __shared__ uint32_t cur[];  // [G1]
     if (aborted(st)) return;
+    const int64_t nb = (n + ch1 - 1) / ch1;  // chunks (the grid is rounded up to whole XCD rows)
+    const int64_t q = xcd_slot(blockIdx.x, gridDim.x);
+    if (q >= nb) return;
     const int G1 = bl.cells();
-    const int64_t nb = gridDim.x;
-    for (int i = threadIdx.x; i < G1; i += blockDim.x) cur[i] = o1[(int64_t)i * nb + blockIdx.x];
+    for (int i = threadIdx.x; i < G1; i += blockDim.x) cur[i] = o1[(int64_t)i * nb + q];
     __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * ch1;
+    const int64_t lo = q * ch1;
     const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
     uint32_t err = 0;
     int64_t i = lo + threadIdx.x;
@@ -181,7 +202,7 @@ __global__ __launch_bounds__(1024) void k_l1_scatter_staged(
     const int64_t last = (int64_t)G1 * nb1;
     const uint32_t m1_total = (uint32_t)st->m1_total;
     uint32_t err = 0;
-    for (int64_t q = blockIdx.x; q < nb1; q += gridDim.x) {
+    for (int64_t q = xcd_slot(blockIdx.x, gridDim.x); q < nb1; q += gridDim.x) {
         const int64_t lo = q * ch1;
         const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
         // entries of this chunk per coarse cell (one cell per thread)
@@ -369,7 +390,7 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e
     if (aborted(st)) return;
     const int B2 = bl.tiles_per_cell();
     const uint32_t nchunks = st->n_chunks;
-    for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+    for (uint32_t q = xcd_slot(blockIdx.x, gridDim.x); q < nchunks; q += gridDim.x) {
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
         for (int i = threadIdx.x; i < B2; i += blockDim.x) hist[i] = 0u;
         __syncthreads();
@@ -404,7 +425,7 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__
     const int B2 = bl.tiles_per_cell();
     const uint32_t nchunks = st->n_chunks;
     uint32_t err = 0;
-    for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+    for (uint32_t q = xcd_slot(blockIdx.x, gridDim.x); q < nchunks; q += gridDim.x) {
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
         for (int t = threadIdx.x; t < B2; t += blockDim.x)
             cur[t] = o2[k.h2base + (uint32_t)t * k.nch + k.c];
@@ -479,7 +500,7 @@ __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
     // the scan leaves the total in the status word, not after the last count
     const uint32_t last = (uint32_t)B2 * nchunks, m_total = (uint32_t)st->m_total;
     uint32_t err = 0;
-    for (uint32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+    for (uint32_t q = xcd_slot(blockIdx.x, gridDim.x); q < nchunks; q += gridDim.x) {
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
         // per-tile counts of this chunk from the scanned level-2 histogram
         uint32_t gb[kStagePer], cnt[kStagePer], sum = 0;
@@ -909,7 +930,8 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
     {
         ProfRange pr("k_l1_count", s);
         if (n > 0) {
-            hipLaunchKernelGGL(k_l1_count, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
+            hipLaunchKernelGGL(k_l1_count, dim3((unsigned)xcd_grid(nb1)), dim3(kL1NT), G1 * 4, s,
+                               rects, n,
                                P.gd, bl, ch1, P.h1, P.st);
         } else {
             hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(G1, kBlock, 65536)), dim3(kBlock), 0, s,
@@ -926,7 +948,8 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
             hipLaunchKernelGGL(k_l1_scatter_staged, dim3(num_cus), dim3(1024), 0, s, rects, n, P.gd,
                                bl, ch1, nb1, P.h1, P.e1, P.e1i, P.cap_m1, P.st);
         else
-            hipLaunchKernelGGL(k_l1_scatter, dim3((unsigned)nb1), dim3(kL1NT), G1 * 4, s, rects, n,
+            hipLaunchKernelGGL(k_l1_scatter, dim3((unsigned)xcd_grid(nb1)), dim3(kL1NT), G1 * 4, s,
+                               rects, n,
                                P.gd, bl, ch1, P.h1, P.e1, P.e1i, P.cap_m1, P.st);
     }
     {
