@@ -508,6 +508,7 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
     }
     __shared__ uint32_t s_tot[2];
     __shared__ uint32_t s_wsum[2][NT / kWave + 1];
+    __shared__ uint32_t s_wq[Q][NT / kWave];  // range-length sums per round and wave
     // 1. tile table with local prefixes (chunks of NT tiles; unrolled, so
     //    the chunk index is a constant for tile_of)
     uint32_t carry_r = 0, carry_s = 0;
@@ -751,11 +752,12 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
     uint32_t* cnt = L.key;
     uint16_t* js = L.tk;
     auto X = [&](int q) { return L.bx[q].x; };
+    //     Thread tid takes the pivots p = q * NT + tid, so that the lanes of
+    //     a wave read consecutive boxes (no LDS bank conflicts).
     uint32_t v[Q];
-    uint32_t sum = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int p = tid * Q + q;
+        const int p = q * NT + tid;
         v[q] = 0;
         if (p < NE) {
             const int k = L.tk[p];
@@ -768,39 +770,54 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
             v[q] = (uint32_t)(j1 - j0);
             js[p] = (uint16_t)j0;
         }
-        sum += v[q];
     }
-    // 4b. exclusive prefix of the range lengths (candidate index space)
+    // 4b. exclusive prefix of the range lengths in pivot order (candidate
+    //     index space): round q of NT pivots after the rounds before it
     {
         const int lane = lane_id(), w = tid / kWave;
-        uint32_t inc = sum;
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t t = __shfl_up(inc, d, kWave);
-            if (lane >= d) inc += t;
-        }
-        if (lane == kWave - 1) s_wsum[1][w] = inc;
-        __syncthreads();
-        uint32_t ex = inc - sum, total = 0;
-        for (int q = 0; q < NT / kWave; ++q) {
-            if (q < w) ex += s_wsum[1][q];
-            total += s_wsum[1][q];
-        }
+        uint32_t inc[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int p = tid * Q + q;
-            if (p < NE) cnt[p] = ex;
-            ex += v[q];
+            inc[q] = v[q];
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t t = __shfl_up(inc[q], d, kWave);
+                if (lane >= d) inc[q] += t;
+            }
         }
-        if (tid == 0) cnt[NE] = total;
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) s_wq[q][w] = inc[q];
+        }
+        __syncthreads();
+        uint32_t before = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            uint32_t wpre = 0, rtot = 0;
+#pragma unroll
+            for (int x = 0; x < NT / kWave; ++x) {
+                const uint32_t y = s_wq[q][x];
+                wpre += x < w ? y : 0u;
+                rtot += y;
+            }
+            const int p = q * NT + tid;
+            if (p < NE) cnt[p] = before + wpre + inc[q] - v[q];
+            before += rtot;
+        }
+        if (tid == 0) cnt[NE] = before;
     }
     __syncthreads();
-    // 4c. every lane takes chunks of kChunkC consecutive candidates, so long
-    //     scans are shared by many lanes; each candidate gets the closed
-    //     y-test and the reference-point test of Eq. (1)
+    // 4c. every lane takes chunks of kUnitChunk consecutive candidates, so
+    //     long scans are shared by many lanes; each candidate gets the closed
+    //     y-test and the reference-point test of Eq. (1).  A batch of small
+    //     tiles has few candidates per pivot: shorter chunks leave fewer lanes
+    //     idle in the last round (measured: 4 beats 2 and 8 there; one medium
+    //     tile keeps 8)
+    constexpr int kUnitChunk = TC == 2 ? kChunkC : kChunkC / 2;
     const uint32_t T = cnt[NE];
     // the trip count is uniform over the workgroup (the sink needs all lanes)
-    for (uint32_t it = 0; it * (uint32_t)(NT * kChunkC) < T; ++it) {
-        const uint32_t c0 = it * (uint32_t)(NT * kChunkC) + (uint32_t)tid * kChunkC;
+    for (uint32_t it = 0; it * (uint32_t)(NT * kUnitChunk) < T; ++it) {
+        const uint32_t c0 = it * (uint32_t)(NT * kUnitChunk) + (uint32_t)tid * kUnitChunk;
         const uint32_t cs = c0 < T ? c0 : T - 1u;
         int lo = 0, hi = NE;  // pivot of candidate cs: last p with cnt[p] <= cs
         while (hi - lo > 1) {
@@ -813,7 +830,7 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
         float4 pb4 = L.bx[p];
         uint32_t pid = L.id[p];
 #pragma unroll
-        for (int i = 0; i < kChunkC; ++i) {
+        for (int i = 0; i < kUnitChunk; ++i) {
             const uint32_t cc = c0 + (uint32_t)i;
             const bool valid = cc < T;
             if (valid && cc >= pend) {
