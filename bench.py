@@ -302,15 +302,13 @@ def bench_distance(args, pk, sj, torch):
     K, tau, n = state["g"].k, state["g"].split_tau, state["n"]
     nc = info["candidates"]
     w = dict(nR=nP, nS=nQ, m1R=info["level1_entries_p"], m1S=info["level1_entries_q"],
-             mR=info["entries_p"], mS=info["entries_q"], C=K * K, P=nc, stats=st)
+             mR=info["entries_p"], mS=info["entries_q"], C=K * K, P=n, stats=st)
     kernels = {}
     for name, (tot, calls) in kern.items():
         avg = tot / max(calls, 1)
         if name == "k_point_squares":
             b = 24 * (nP + nQ) / 2           # two launches: 8 B in, 16 B out per point
-        elif name == "k_refine":
-            b = 24 * nc + 8 * n              # candidate + two point gathers, result write
-        else:
+        else:  # the join writes the result pairs (the distance test is in its sweep)
             b = kernel_bytes(name, w)
         kernels[name] = {"avg_ms": round(avg, 5), "calls": calls,
                          "alg_bytes": None if b is None else int(b),

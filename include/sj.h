@@ -421,8 +421,10 @@ sj_status sj_generate(float* rects, int64_t n, const float* mu, const float* sig
 
 /*
  * Epsilon-distance join of two point sets (Sec. 1: a distance join between
- * point sets reduces to the intersection join of squares of side eps
- * centred on the points, followed by a distance check).
+ * point sets reduces to the intersection join of squares of side eps around
+ * the points, followed by a distance check).  Here each square is anchored
+ * at its point (the point is its lower-left corner), and the join checks
+ * the distance of every pair the filter passes as it finds it.
  *
  * Result: every (i, j) with dx*dx + dy*dy <= eps*eps, where dx = P[i].x -
  * Q[j].x and dy = P[i].y - Q[j].y, evaluated in float64 from the float32
@@ -441,10 +443,11 @@ sj_status sj_generate(float* rects, int64_t n, const float* mu, const float* sig
  *   n_pairs    (host) the number of result pairs.  If out is not NULL and
  *              the count exceeds capacity the call returns SJ_ERR_CAPACITY
  *              and the first capacity slots hold an unspecified subset.
- * The squares (widened by a relative 2^-44 so that rounding cannot lose a
- * pair), their partitions and the candidate pairs live in library-owned
- * device buffers that are reused and grown across calls.  Synchronises the
- * stream.  Size limits as for rectangles.
+ *              SJ_SORTED_OUTPUT in g->flags: sorted by (i, j) as sj_join.
+ * The squares (the side widened by a relative 2^-44 so that rounding cannot
+ * lose a pair) and their partitions live in library-owned device buffers
+ * that are reused and grown across calls.  Synchronises the stream.  Size
+ * limits as for rectangles.
  */
 sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
                            sj_grid* g, sj_pair* out, int64_t capacity, int64_t* n_pairs,
@@ -454,7 +457,7 @@ sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t n
  * Autotune the join schedule of an epsilon-distance join (as sj_tune does for
  * two partitions): builds the squares, the grid (when g->k is 0; written
  * back) and the partitions as sj_distance_join does, then times every
- * candidate schedule on them with the full candidate output and caches the
+ * candidate schedule on them with the full pair output and caches the
  * fastest for that grid and size class, so that later sj_distance_join calls
  * on the same inputs use it.  best (host, may be NULL) receives it.
  * Arguments as for sj_distance_join; reps >= 1.  Synchronises the stream.
@@ -463,8 +466,9 @@ sj_status sj_distance_tune(const float* P, int64_t nP, const float* Q, int64_t n
                            sj_grid* g, int32_t reps, sj_tuning* best, void* stream);
 
 /* Work of the last sj_distance_join on the calling thread's current device
- * (all zero before the first): candidate pairs of the filter (before the
- * distance check) and the tile entries of the two partitions of squares
+ * (all zero before the first): the pairs the filter passed to the distance
+ * check (squares that meet, each pair once) and the tile entries of the two
+ * partitions of squares
  * (final and first-level, as sj_part_info and sj_part_stats report them). */
 typedef struct {
     int64_t candidates;

@@ -1,8 +1,7 @@
 // Epsilon-distance join of two point sets on top of the MBR join: the
 // filter-and-refine reduction of Sec. 1.  Every point becomes a square of
-// side eps centred on it, the squares of P and Q are partitioned and joined
-// like any rectangles, and each candidate pair is then refined by its
-// distance.
+// side eps, the squares of P and Q are partitioned and joined like any
+// rectangles, and each pair the filter passes is refined by its distance.
 //
 // Result: every (i, j) with D(p_i, q_j) <= E, where, in float64 from the
 // float32 inputs, dx = p.x - q.x, dy = p.y - q.y, D = dx*dx + dy*dy and
@@ -10,15 +9,21 @@
 // is a pure function of the inputs: it depends on no grid, schedule or
 // launch shape.
 //
-// Filter soundness.  The squares are widened before they are rounded
-// outward to float32: half-side eps/2 plus m = (|c| + eps/2) * 2^-44 per
-// coordinate c.  D <= E implies |c_p - c_q| <= eps * (1 + 2^-50) on each
-// axis (every float64 rounding above is a relative error of at most 2^-53),
-// while two widened squares overlap on an axis whenever their centres are
-// within eps + (m_p + m_q)(1 - 2^-7) >= eps * (1 + 2^-45) on it (the
-// roundings of the bounds cost less than m / 128), so every accepted pair is
-// a candidate.  The filter also keeps pairs farther than eps (the squares'
-// corners, the margin); the refinement drops them.
+// Squares.  The square of a point c is anchored at it: [c, u(c)] on each
+// axis, with u(c) = c + eps + m, m = (|c| + eps) * 2^-44, summed in float64
+// and rounded up to float32.  Two squares meet on an axis iff their lower
+// ends are at most the side apart, as for squares centred on the points, so
+// the filter is the same; and the lower corner of every entry is its input
+// point exactly, so the join tests D <= E on the two boxes it has in hand
+// (no candidate list, no gathers of the points).
+//
+// Filter soundness.  D <= E implies |c_p - c_q| <= eps * (1 + 2^-50) on each
+// axis (every float64 rounding above is a relative error of at most 2^-53).
+// The two float64 additions of u(c) lose at most 2^-52 (|c| + eps) < m, so
+// u(c) >= c + eps * (1 + 2^-45): the squares of every accepted pair overlap,
+// and the pair is examined in the tile of its reference point.  The filter
+// also passes pairs farther than eps (the squares' corners, the margin);
+// the distance test drops them.
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -54,108 +59,34 @@ __device__ __forceinline__ float up_f(double v) {
     return (double)f < v ? step_up(f) : f;
 }
 
-__device__ __forceinline__ void widen(float c, double h, float& lo, float& hi) {
+// Upper end of the anchored square of c (see above).
+__device__ __forceinline__ float upper_end(float c, double eps) {
     const double cd = (double)c;
-    const double m = __dmul_rn(__dadd_rn(fabs(cd), h), 0x1p-44);
-    lo = down_f(__dsub_rn(__dsub_rn(cd, h), m));
-    hi = up_f(__dadd_rn(__dadd_rn(cd, h), m));
+    const double m = __dmul_rn(__dadd_rn(fabs(cd), eps), 0x1p-44);
+    return up_f(__dadd_rn(__dadd_rn(cd, eps), m));
 }
 
-// One thread per point: the widened, outward-rounded square of side eps.  A
+// One thread per point: its anchored, outward-rounded square of side eps.  A
 // non-finite coordinate gives a non-finite bound, which the partition
 // rejects with SJ_ERR_RECT.
 __global__ __launch_bounds__(256) void k_point_squares(const float2* __restrict__ pts, int64_t n,
                                                        float eps, float4* __restrict__ box) {
-    const double h = 0.5 * (double)eps;
+    const double e = (double)eps;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float2 p = pts[i];
-        float4 b;
-        widen(p.x, h, b.x, b.z);
-        widen(p.y, h, b.y, b.w);
-        box[i] = b;
-    }
-}
-
-// Refinement: keep the candidates (r, s) with D <= E.  The two point reads
-// per candidate are random gathers, so each thread takes kRefineU candidates
-// (strided by the block size, so the candidate reads coalesce) and issues all
-// of their gathers before the first test, to keep many in flight.  A
-// wavefront's kept pairs are placed with one atomic and a lane prefix sum of
-// the per-lane counts; positions at or beyond `capacity` are counted, not
-// written.
-constexpr int kRefineU = 8;
-constexpr int kRefineBlock = 256;
-
-__global__ __launch_bounds__(kRefineBlock) void k_refine(const sj_pair* __restrict__ cand,
-                                                         int64_t nc,
-                                                         const float2* __restrict__ P,
-                                                         const float2* __restrict__ Q, float eps,
-                                                         sj_pair* __restrict__ out,
-                                                         int64_t capacity,
-                                                         unsigned long long* __restrict__ count) {
-    const double e2 = __dmul_rn((double)eps, (double)eps);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t span = (int64_t)kRefineBlock * kRefineU;
-    for (int64_t base = (int64_t)blockIdx.x * span; base < nc; base += (int64_t)gridDim.x * span) {
-        // slots past the end read candidate (0, 0) (both sets are non-empty
-        // when there is a candidate) and are masked out of the result
-        sj_pair c[kRefineU];
-        float2 p[kRefineU], q[kRefineU];
-        uint32_t valid = 0;
-#pragma unroll
-        for (int u = 0; u < kRefineU; ++u) {
-            const int64_t i = base + (int64_t)u * kRefineBlock + threadIdx.x;
-            const bool in = i < nc;
-            c[u] = cand[in ? i : 0];
-            valid |= (uint32_t)in << u;
-        }
-#pragma unroll
-        for (int u = 0; u < kRefineU; ++u) {
-            p[u] = P[c[u].r];
-            q[u] = Q[c[u].s];
-        }
-        uint32_t keep = 0;
-#pragma unroll
-        for (int u = 0; u < kRefineU; ++u) {
-            const double dx = __dsub_rn((double)p[u].x, (double)q[u].x);
-            const double dy = __dsub_rn((double)p[u].y, (double)q[u].y);
-            if (__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) <= e2) keep |= 1u << u;
-        }
-        keep &= valid;
-        const int cnt = __popc(keep);
-        int incl = cnt;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int t = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += t;
-        }
-        const int total = __shfl(incl, kWave - 1, kWave);
-        if (total == 0) continue;
-        unsigned long long wbase = 0;
-        if (lane == kWave - 1) wbase = atomicAdd(count, (unsigned long long)total);
-        wbase = __shfl(wbase, kWave - 1, kWave);
-        unsigned long long at = wbase + (unsigned long long)(incl - cnt);
-#pragma unroll
-        for (int u = 0; u < kRefineU; ++u) {
-            if (keep >> u & 1u) {
-                if (at < (unsigned long long)capacity) out[at] = c[u];
-                ++at;
-            }
-        }
+        box[i] = make_float4(p.x, p.y, upper_end(p.x, e), upper_end(p.y, e));
     }
 }
 
 // Library-owned state per device: the squares of both inputs, their
-// partitions and the candidate buffer, reused (and grown) across calls.
+// partitions and the tuner's pair buffer, reused (and grown) across calls.
 struct DistState {
     float4* sqP = nullptr;
     float4* sqQ = nullptr;
     int64_t capP = 0, capQ = 0;
-    sj_pair* cand = nullptr;
-    int64_t cap_cand = 0;
-    unsigned long long* count = nullptr;
-    unsigned long long* host = nullptr;
+    sj_pair* tune_out = nullptr;
+    int64_t cap_tune = 0;
     sj_part* PP = nullptr;
     sj_part* PQ = nullptr;
     int64_t last_candidates = 0;
@@ -193,16 +124,6 @@ namespace {
 // partitions, in the device state d.  The caller holds g_dmu.
 sj_status prepare(DistState& d, const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
                   sj_grid* g, hipStream_t s) {
-    if (!d.count) {
-        if (hipMalloc((void**)&d.count, sizeof(unsigned long long)) != hipSuccess) return SJ_ERR_OOM;
-        if (hipHostMalloc((void**)&d.host, sizeof(unsigned long long), hipHostMallocDefault) !=
-            hipSuccess) {
-            d.host = nullptr;
-            (void)hipFree(d.count);
-            d.count = nullptr;
-            return SJ_ERR_OOM;
-        }
-    }
     if (grow_to(d.sqP, d.capP, std::max<int64_t>(nP, 1)) != hipSuccess ||
         grow_to(d.sqQ, d.capQ, std::max<int64_t>(nQ, 1)) != hipSuccess)
         return SJ_ERR_OOM;
@@ -236,6 +157,9 @@ sj_status check_args(const float* P, int64_t nP, const float* Q, int64_t nQ, flo
     return SJ_OK;
 }
 
+// E = eps * eps in float64 (one rounding)
+double eps_sq(float eps) { return (double)eps * (double)eps; }
+
 }  // namespace
 
 sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
@@ -251,33 +175,12 @@ sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t n
     DistState& d = g_ds[dev];
     st = prepare(d, P, nP, Q, nQ, eps, g, s);
     if (st != SJ_OK) return st;
-    int64_t nc = 0;
-    st = sj_join(d.PP, d.PQ, d.cand, d.cap_cand, &nc, stream);
-    if (st == SJ_ERR_CAPACITY) {
-        if (grow_to(d.cand, d.cap_cand, nc) != hipSuccess) return SJ_ERR_OOM;
-        st = sj_join(d.PP, d.PQ, d.cand, d.cap_cand, &nc, stream);
-    }
-    if (st != SJ_OK) return st;
-    d.last_candidates = nc;
-    {
-        ProfRange pr("k_refine", s);
-        if (hipMemsetAsync(d.count, 0, sizeof(unsigned long long), s) != hipSuccess)
-            return SJ_ERR_DEVICE;
-        const int64_t span = (int64_t)kRefineBlock * kRefineU;
-        const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nc + span - 1) / span, 8192));
-        if (nc > 0)
-            hipLaunchKernelGGL(k_refine, dim3(nb), dim3(kRefineBlock), 0, s, d.cand, nc,
-                               (const float2*)P, (const float2*)Q, eps, out, capacity, d.count);
-        if (hipGetLastError() != hipSuccess) return SJ_ERR_DEVICE;
-    }
-    if (hipMemcpyAsync(d.host, d.count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return SJ_ERR_DEVICE;
-    *n_pairs = (int64_t)*d.host;
-    if (out && *n_pairs > capacity) return SJ_ERR_CAPACITY;
-    if (out && (g->flags & SJ_SORTED_OUTPUT)) return sj_sort_pairs(out, *n_pairs, nP, nQ, stream);
-    return SJ_OK;
+    // the join tests the distance of every filter pair and writes the result
+    // (sorted by (i, j) when the grid asks for it)
+    int64_t cand = 0;
+    st = api_distance_pairs(d.PP, d.PQ, eps_sq(eps), out, capacity, n_pairs, &cand, s);
+    if (st == SJ_OK || st == SJ_ERR_CAPACITY) d.last_candidates = cand;
+    return st;
 }
 
 sj_status sj_distance_tune(const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
@@ -292,13 +195,13 @@ sj_status sj_distance_tune(const float* P, int64_t nP, const float* Q, int64_t n
     DistState& d = g_ds[dev];
     st = prepare(d, P, nP, Q, nQ, eps, g, s);
     if (st != SJ_OK) return st;
-    // the candidate buffer holds every candidate, so each schedule is timed
-    // with its full output
-    int64_t nc = 0;
-    st = sj_join_count(d.PP, d.PQ, &nc, stream);
+    // every schedule is timed with its full output, in a library buffer
+    const double e2 = eps_sq(eps);
+    int64_t np = 0, cand = 0;
+    st = api_distance_pairs(d.PP, d.PQ, e2, nullptr, 0, &np, &cand, s);
     if (st != SJ_OK) return st;
-    if (grow_to(d.cand, d.cap_cand, std::max<int64_t>(nc, 1)) != hipSuccess) return SJ_ERR_OOM;
-    return sj_tune(d.PP, d.PQ, d.cand, d.cap_cand, reps, best, stream);
+    if (grow_to(d.tune_out, d.cap_tune, std::max<int64_t>(np, 1)) != hipSuccess) return SJ_ERR_OOM;
+    return api_distance_tune(d.PP, d.PQ, e2, d.tune_out, d.cap_tune, reps, best, s);
 }
 
 sj_status sj_distance_last_info(sj_distance_info* info) {

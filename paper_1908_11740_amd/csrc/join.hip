@@ -116,6 +116,8 @@ struct Args {
     int gbda;                     // dense tiles: the 9 class-class mini-joins, no duplicate test
     uint32_t* dgrp;               // [cap_dense * 10] class group starts of each dense tile (R, S)
     uint32_t* dmj;                // [cap_dense * 10] units before each mini-join of a dense tile
+    int dist;                     // distance join (boxes: squares anchored at their points)
+    double e2;                    // ... keep a pair only if dx*dx + dy*dy <= e2
 };
 
 // GBDA classes of an entry in its tile, from the start bits of Eq. (1):
@@ -176,6 +178,7 @@ struct Sink {
     uint32_t region, chunk, cfill;  // current scratch chunk (kSingle)
     bool have, ok;
     unsigned long long total;       // hits seen by this wave (kSingle)
+    uint32_t cand;                  // this lane's filter pairs (distance join; not kWrite)
 
     __device__ void init(uint32_t wave_gid) {
         n = 0;
@@ -187,6 +190,7 @@ struct Sink {
         have = false;
         ok = true;
         total = 0;
+        cand = 0;
     }
 
     __device__ void begin(const Args& a, int64_t slot) {
@@ -293,6 +297,11 @@ struct Sink {
 
     // kernel end, every lane: the last staged pairs and the wave's totals
     __device__ void finish(const Args& a, uint32_t wave_gid) {
+        if (MODE != kWrite && a.dist) {
+            unsigned long long v = cand;
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+            if (lane_id() == 0 && v) atomicAdd(&a.st->n_cand, v);
+        }
         if (MODE != kSingle) return;
         if (n) flush(a);
         if (lane_id() == 0) {
@@ -305,6 +314,17 @@ struct Sink {
 // Reference-point test of Eq. (1) on the start bits of the two entries.
 __device__ __forceinline__ bool ref_point_here(uint32_t ida, uint32_t idb) {
     return ((ida | idb) & (kBx | kBy)) == (kBx | kBy);
+}
+
+// Distance join (Sec. 1): the squares are anchored at their points, so the
+// lower corners (x_l, y_l) are the input points themselves.  The refinement
+// of a filter pair, in float64 with every operation rounded once (no fused
+// multiply-add); symmetric in x and y and in the two points, so it holds for
+// boxes taken with x and y exchanged.
+__device__ __forceinline__ bool within_eps(const float4& p, const float4& q, double e2) {
+    const double dx = __dsub_rn((double)p.x, (double)q.x);
+    const double dy = __dsub_rn((double)p.y, (double)q.y);
+    return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) <= e2;
 }
 
 // First index in [lo, hi) whose x_l is > v (upper) or >= v (lower).
@@ -338,7 +358,7 @@ __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_e
                              Sink<MODE, BLOCK>& sk) {
     bool scanning = false, exhausted = false, isR = false;
     int j = 0, jend = 0;
-    float pxu = 0.f, pyl = 0.f, pyu = 0.f;
+    float pxl = 0.f, pxu = 0.f, pyl = 0.f, pyu = 0.f;
     uint32_t pid = 0;
     const int lane = lane_id();
     while (true) {
@@ -353,7 +373,7 @@ __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_e
             if (need) {
                 const int p = p_begin + (int)(base + lanes_below(m));
                 if (p < p_end) {
-                    acc.setup(p, isR, j, jend, pxu, pyl, pyu, pid);
+                    acc.setup(p, isR, j, jend, pxl, pxu, pyl, pyu, pid);
                     scanning = j < jend;
                 } else {
                     exhausted = true;
@@ -384,7 +404,10 @@ __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_e
 #pragma unroll
             for (int k = 0; k < kCand; ++k) {
                 go = go && (j + k < jend) && (c[k].x <= pxu);
-                hit[k] = go && (pyl <= c[k].w) && (c[k].y <= pyu) && (!REF || ref_point_here(pid, qid[k]));
+                const bool f = go && (pyl <= c[k].w) && (c[k].y <= pyu) &&
+                               (!REF || ref_point_here(pid, qid[k]));
+                hit[k] = f && (!a.dist || within_eps(make_float4(pxl, pyl, pxu, pyu), c[k], a.e2));
+                if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
                 used += go ? 1 : 0;
                 const uint32_t other = qid[k] & kIdMask;
                 er[k] = isR ? me : other;
@@ -847,7 +870,9 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
                 const int j = (int)js[p] + (int)(cc - cnt[p]);
                 const float4 q4 = L.bx[j];
                 const uint32_t qid = L.id[j];
-                hit[0] = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
+                const bool f = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
+                hit[0] = f && (!a.dist || within_eps(pb4, q4, a.e2));
+                if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
                 const bool isR = p < NR;
                 er[0] = (isR ? pid : qid) & kIdMask;
                 es[0] = (isR ? qid : pid) & kIdMask;
@@ -1160,7 +1185,9 @@ __device__ void sweep_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const W
                 const int j = (int)T.tk[p] + (int)(cc - cnt[p]);
                 const float4 q4 = W.bx[j];
                 const uint32_t qid = W.id[j];
-                hit[0] = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
+                const bool f = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
+                hit[0] = f && (!a.dist || within_eps(pb4, q4, a.e2));
+                if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
                 const bool isR = p < NR;
                 er[0] = (isR ? pid : qid) & kIdMask;
                 es[0] = (isR ? qid : pid) & kIdMask;
@@ -1899,10 +1926,11 @@ struct GlobAcc {
     int base, nr, ns;  // R entries at [base, base+nr), S at [base+nr, base+nr+ns)
     __device__ float4 box(int j) const { return bxs[j]; }
     __device__ uint32_t id(int j) const { return idf[j]; }
-    __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxu, float& pyl, float& pyu,
-                          uint32_t& pid) const {
+    __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxl, float& pxu, float& pyl,
+                          float& pyu, uint32_t& pid) const {
         const int e = base + p;  // pivots: R entries then S entries
         const float4 b = bxs[e];
+        pxl = b.x;
         pxu = b.z;
         pyl = b.y;
         pyu = b.w;
@@ -1925,11 +1953,12 @@ struct GbdaAcc {
     int rb, nr, sb, ns;
     __device__ float4 box(int j) const { return bxs[j]; }
     __device__ uint32_t id(int j) const { return idf[j]; }
-    __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxu, float& pyl, float& pyu,
-                          uint32_t& pid) const {
+    __device__ bool setup(int p, bool& isR, int& j, int& jend, float& pxl, float& pxu, float& pyl,
+                          float& pyu, uint32_t& pid) const {
         isR = p < nr;
         const int e = isR ? rb + p : sb + (p - nr);
         const float4 b = bxs[e];
+        pxl = b.x;
         pxu = b.z;
         pyl = b.y;
         pyu = b.w;
@@ -2027,6 +2056,7 @@ __global__ void k_reset(uint32_t* ctr, DevStatus* st, uint32_t* sc_ctr,
         st->flags = 0u;
         st->n_dense = 0u;
         st->n_units = 0u;
+        st->n_cand = 0ull;
     }
 }
 
@@ -2205,6 +2235,8 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     a.writeback = (!single && !p.count_only) ? 1 : 0;
     a.axis_model = (p.axis_model && !p.plain) ? 1 : 0;
     a.gbda = (p.gbda && !p.plain) ? 1 : 0;
+    a.dist = p.dist ? 1 : 0;
+    a.e2 = p.e2;
     a.dgrp = w.dgrp;
     a.dmj = w.dmj;
     a.medt = w.medt;

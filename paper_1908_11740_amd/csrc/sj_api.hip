@@ -157,8 +157,9 @@ int log2_bucket(int64_t m) {
     return b;
 }
 
-TuneKey tune_key(int dev, const sj_grid& g, int64_t mR, int64_t mS, bool count_only) {
-    return TuneKey{dev, g.k, log2_bucket(mR), log2_bucket(mS), count_only ? 1 : 0};
+// mode: 1 = count only, 2 = distance join (tuned apart from rectangle joins)
+TuneKey tune_key(int dev, const sj_grid& g, int64_t mR, int64_t mS, int mode) {
+    return TuneKey{dev, g.k, log2_bucket(mR), log2_bucket(mS), mode};
 }
 
 // Schedule parameters of a join.
@@ -194,9 +195,10 @@ void apply_tuning(JoinParams& p, const sj_grid& g, const sj_tuning& t) {
     if (g.split_tau == 0 && t.split_tau > 0) p.split_tau = t.split_tau;
 }
 
-JoinParams tuned_params(int dev, const sj_grid& g, int64_t mR, int64_t mS, bool count_only) {
+JoinParams tuned_params(int dev, const sj_grid& g, int64_t mR, int64_t mS, bool count_only,
+                        bool dist = false) {
     JoinParams p = join_params(g, count_only);
-    auto it = g_tune.find(tune_key(dev, g, mR, mS, count_only));
+    auto it = g_tune.find(tune_key(dev, g, mR, mS, (count_only ? 1 : 0) | (dist ? 2 : 0)));
     if (it != g_tune.end()) apply_tuning(p, g, it->second);
     return p;
 }
@@ -305,8 +307,11 @@ hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
     return hipSuccess;
 }
 
+// e2 non-null: distance join of two partitions of anchored squares (pairs
+// with dx*dx + dy*dy <= *e2); *cand then receives the filter's pair count.
 sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
-                  int64_t* n_pairs, bool count_only, hipStream_t s) {
+                  int64_t* n_pairs, bool count_only, hipStream_t s, const double* e2 = nullptr,
+                  int64_t* cand = nullptr) {
     if (!R || !S || !n_pairs || capacity < 0) return SJ_ERR_ARG;
     if (!count_only && capacity > 0 && !out) return SJ_ERR_ARG;
     if (!same_grid(R->grid, S->grid)) return SJ_ERR_GRID_MISMATCH;
@@ -319,7 +324,11 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
     sj_status st = device_state(R->device, &ds);
     if (st != SJ_OK) return st;
     JoinWork& w = ds->w;
-    JoinParams p = tuned_params(R->device, R->grid, R->m, S->m, count_only);
+    JoinParams p = tuned_params(R->device, R->grid, R->m, S->m, count_only, e2 != nullptr);
+    if (e2) {
+        p.dist = true;
+        p.e2 = *e2;
+    }
     st = join_prepare(w, p, (int64_t)R->bl.cells() * R->bl.tiles_per_cell(), R->m, S->m, capacity);
     if (st != SJ_OK) return st;
     hipError_t e = hipSuccess;
@@ -356,12 +365,82 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
         return SJ_ERR_DEVICE;
     }
     *n_pairs = (int64_t)hs.n_pairs;
+    if (cand) *cand = (int64_t)hs.n_cand;
     if (!count_only && (int64_t)hs.n_pairs > capacity) return SJ_ERR_CAPACITY;
     if (!count_only && (R->grid.flags & SJ_SORTED_OUTPUT))
         return sj_sort_pairs(out, *n_pairs, R->n, S->n, s);
     return SJ_OK;
 }
 
+
+// The schedule search of sj_tune; e2 non-null: of the distance join.
+sj_status tune_impl(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
+                    int32_t reps, sj_tuning* best, void* stream, const double* e2) {
+    if (!R || !S || capacity < 0 || reps < 1 || (capacity > 0 && !out)) return SJ_ERR_ARG;
+    if (!same_grid(R->grid, S->grid)) return SJ_ERR_GRID_MISMATCH;
+    if (R->grid.flags & SJ_PLAIN) return SJ_ERR_ARG;
+    const bool count_only = (out == nullptr);
+    const int mode = (count_only ? 1 : 0) | (e2 ? 2 : 0);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SJ_ERR_DEVICE;
+    const int blocks[] = {64, 128, 256, 512};
+    const int taus[] = {128, 256, 1024};
+    sj_tuning win{};
+    win.ms = -1.0;
+    sj_status rs = SJ_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tune.erase(tune_key(R->device, R->grid, R->m, S->m, mode));
+    }
+    for (int blk : blocks) {
+        const int E = lds_unit_entries(blk);
+        for (int sc : {E / 4, E / 2}) {
+            for (int mc : {1024, 2048}) {
+                for (int tau : taus) {
+                    if (R->grid.split_tau != 0 && tau != taus[0]) continue;  // fixed by the grid
+                    sj_tuning t{blk, sc, mc, R->grid.split_tau != 0 ? 0 : tau, 0.0};
+                    {
+                        std::lock_guard<std::mutex> lk(g_mu);
+                        g_tune[tune_key(R->device, R->grid, R->m, S->m, mode)] = t;
+                    }
+                    int64_t np = 0;
+                    float ms = 0.f, tot = 0.f;
+                    sj_status st = do_join(R, S, out, capacity, &np, count_only, s, e2);  // warm-up
+                    for (int r = 0; r < reps && (st == SJ_OK || st == SJ_ERR_CAPACITY); ++r) {
+                        if (hipEventRecord(e0, s) != hipSuccess) st = SJ_ERR_DEVICE;
+                        if (st != SJ_ERR_DEVICE)
+                            st = do_join(R, S, out, capacity, &np, count_only, s, e2);
+                        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                            st = SJ_ERR_DEVICE;
+                        tot += ms;
+                    }
+                    if (st != SJ_OK && st != SJ_ERR_CAPACITY) {
+                        rs = st;
+                        break;
+                    }
+                    t.ms = tot / reps;
+                    if (win.ms < 0 || t.ms < win.ms) win = t;
+                }
+                if (rs != SJ_OK) break;
+            }
+            if (rs != SJ_OK) break;
+        }
+        if (rs != SJ_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_mu);
+    const TuneKey key = tune_key(R->device, R->grid, R->m, S->m, mode);
+    if (rs != SJ_OK) {
+        g_tune.erase(key);
+        return rs;
+    }
+    g_tune[key] = win;
+    if (best) *best = win;
+    return SJ_OK;
+}
 }  // namespace
 
 // Entry points for the batch driver (batch.hip).
@@ -385,6 +464,14 @@ sj_status api_join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, in
 }
 hipError_t api_part_prepare(Part& P, int64_t n, int64_t need_m1, int64_t need_m) {
     return part_prepare(P, n, need_m1, need_m);
+}
+sj_status api_distance_pairs(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
+                             int64_t capacity, int64_t* n_pairs, int64_t* cand, hipStream_t s) {
+    return do_join(R, S, out, capacity, n_pairs, out == nullptr, s, &e2, cand);
+}
+sj_status api_distance_tune(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
+                            int64_t capacity, int32_t reps, sj_tuning* best, hipStream_t s) {
+    return tune_impl(R, S, out, capacity, reps, best, s, &e2);
 }
 
 }  // namespace sj
@@ -478,69 +565,7 @@ sj_status sj_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
 
 sj_status sj_tune(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
                   int32_t reps, sj_tuning* best, void* stream) {
-    if (!R || !S || capacity < 0 || reps < 1 || (capacity > 0 && !out)) return SJ_ERR_ARG;
-    if (!same_grid(R->grid, S->grid)) return SJ_ERR_GRID_MISMATCH;
-    if (R->grid.flags & SJ_PLAIN) return SJ_ERR_ARG;
-    const bool count_only = (out == nullptr);
-    hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SJ_ERR_DEVICE;
-    const int blocks[] = {64, 128, 256, 512};
-    const int taus[] = {128, 256, 1024};
-    sj_tuning win{};
-    win.ms = -1.0;
-    sj_status rs = SJ_OK;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_tune.erase(tune_key(R->device, R->grid, R->m, S->m, count_only));
-    }
-    for (int blk : blocks) {
-        const int E = lds_unit_entries(blk);
-        for (int sc : {E / 4, E / 2}) {
-            for (int mc : {1024, 2048}) {
-                for (int tau : taus) {
-                    if (R->grid.split_tau != 0 && tau != taus[0]) continue;  // fixed by the grid
-                    sj_tuning t{blk, sc, mc, R->grid.split_tau != 0 ? 0 : tau, 0.0};
-                    {
-                        std::lock_guard<std::mutex> lk(g_mu);
-                        g_tune[tune_key(R->device, R->grid, R->m, S->m, count_only)] = t;
-                    }
-                    int64_t np = 0;
-                    float ms = 0.f, tot = 0.f;
-                    sj_status st = do_join(R, S, out, capacity, &np, count_only, s);  // warm-up
-                    for (int r = 0; r < reps && (st == SJ_OK || st == SJ_ERR_CAPACITY); ++r) {
-                        if (hipEventRecord(e0, s) != hipSuccess) st = SJ_ERR_DEVICE;
-                        if (st != SJ_ERR_DEVICE)
-                            st = do_join(R, S, out, capacity, &np, count_only, s);
-                        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                            st = SJ_ERR_DEVICE;
-                        tot += ms;
-                    }
-                    if (st != SJ_OK && st != SJ_ERR_CAPACITY) {
-                        rs = st;
-                        break;
-                    }
-                    t.ms = tot / reps;
-                    if (win.ms < 0 || t.ms < win.ms) win = t;
-                }
-                if (rs != SJ_OK) break;
-            }
-            if (rs != SJ_OK) break;
-        }
-        if (rs != SJ_OK) break;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    std::lock_guard<std::mutex> lk(g_mu);
-    const TuneKey key = tune_key(R->device, R->grid, R->m, S->m, count_only);
-    if (rs != SJ_OK) {
-        g_tune.erase(key);
-        return rs;
-    }
-    g_tune[key] = win;
-    if (best) *best = win;
-    return SJ_OK;
+    return tune_impl(R, S, out, capacity, reps, best, stream, nullptr);
 }
 
 sj_status sj_tune_set(const sj_part* R, const sj_part* S, int32_t count_only,

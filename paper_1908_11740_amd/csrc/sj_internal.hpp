@@ -65,6 +65,7 @@ struct DevStatus {
     uint32_t n_dense;             // dense tiles found by the join classification
     uint32_t n_units;             // LDS units built by the classification
     uint32_t n_chunks;            // level-2 chunks of the partition
+    unsigned long long n_cand;    // distance join: pairs passed by the filter
 };
 
 // Two-level blocking of the K x K grid: G x G coarse cells of B x B tiles.
@@ -145,6 +146,8 @@ struct JoinParams {
     bool single;     // one sweep into scratch chunks + compaction (else count, scan, write)
     bool axis_model; // medium and dense tiles choose their sweeping axis (Eq. (2))
     bool gbda;       // dense tiles: the 9 GBDA class mini-joins, no duplicate test
+    bool dist;       // distance join: boxes are squares anchored at their points, and
+    double e2;       // a pair is kept only if dx*dx + dy*dy <= e2 (float64, no FMA)
 };
 
 struct JoinWork {
@@ -210,6 +213,13 @@ JoinParams api_join_params(const sj_grid& g, bool count_only);
 sj_status api_join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_t mS,
                            int64_t capacity);
 hipError_t api_part_prepare(Part& P, int64_t n, int64_t need_m1, int64_t need_m);
+// distance join of two partitions of anchored squares (distance.hip): pairs
+// with dx*dx + dy*dy <= e2 straight into out (out NULL: count only); cand
+// receives the pairs the filter passed to the distance test
+sj_status api_distance_pairs(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
+                             int64_t capacity, int64_t* n_pairs, int64_t* cand, hipStream_t s);
+sj_status api_distance_tune(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
+                            int64_t capacity, int32_t reps, sj_tuning* best, hipStream_t s);
 bool prof_pause(bool pause);  // prof.hip: suspend event brackets (graph capture)
 
 }  // namespace sj
