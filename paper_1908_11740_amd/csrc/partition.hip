@@ -28,6 +28,8 @@
 // Every kernel checks the status word first and does nothing if an earlier
 // stage reported a bad rectangle or a full buffer; the host then grows the
 // buffers (sizes are reported in the status) and runs the partition again.
+#include <cstdlib>
+
 #include "sj_internal.hpp"
 #include "sj_prof.hpp"
 
@@ -850,9 +852,14 @@ int grid_for(int64_t n, int block, int max_blocks) {
 void scan(uint32_t* data, int64_t cmax, const uint32_t* dyn, int64_t mult, uint32_t* bs,
           unsigned long long* total, DevStatus* st, hipStream_t s) {
     const int64_t nb = std::max<int64_t>((cmax + kScanChunk - 1) / kScanChunk, 1);
+    // test hook: a lower limit of the direct form sends small scans through
+    // the top-level scan, which otherwise only inputs of tens of millions of
+    // counters reach
+    int64_t direct = kScanDirect;
+    if (const char* dbg = std::getenv("SJ_DEBUG_SCAN_DIRECT")) direct = std::max(0, std::atoi(dbg));
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, data, cmax, dyn, mult,
                        bs, st);
-    if (nb <= kScanDirect) {
+    if (nb <= direct) {
         hipLaunchKernelGGL(k_scan_final<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, data, cmax,
                            dyn, mult, bs, data, total, st);
     } else {

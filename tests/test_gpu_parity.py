@@ -215,6 +215,19 @@ def test_scratch_overflow_falls_back_to_two_passes(uniform1m, monkeypatch):
     assert st == sj.SJ_ERR_CAPACITY and n == len(ref)
 
 
+def test_scans_through_the_top_level_scan(uniform1m, monkeypatch):
+    """Above 2048 tiles of 8192 counters the exclusive scans add a top-level
+    scan of the tile sums; a test hook lowers that limit to 0, so that the
+    partition histograms, the pair-count and chunk scans and the pair sort of
+    the uniform 1M join all run through it, with the same pairs."""
+    R, S, ref = uniform1m
+    monkeypatch.setenv("SJ_DEBUG_SCAN_DIRECT", "0")
+    for K, flags in ((1024, 0), (256, sj.SJ_TWO_PASS), (4096, sj.SJ_SORTED_OUTPUT)):
+        say("top-level scan path, uniform 1M K", K, "flags", flags)
+        assert np.array_equal(gpu_join(R, S, K, flags=flags), ref), (K, flags)
+    assert gpu_join(R, S, 512, count=True) == len(ref)
+
+
 def test_handle_reuse_across_grids():
     R, S, _ = datagen.small_case()
     ref = oracle.bruteforce(R, S)
