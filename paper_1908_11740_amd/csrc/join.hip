@@ -62,6 +62,9 @@ enum Ctr : int {
     kAxisY = 9,         // ... and those of them swept along y
     kNumCtr = 10
 };
+// k_classify adds to each of these pairs of counters with one 64-bit atomic
+static_assert(kUnitsWritten == kTilesWritten + 1 && kTilesWritten % 2 == 0, "tile/unit pair");
+static_assert(kMedEntries == kSmallEntries + 1 && kSmallEntries % 2 == 0, "statistics pair");
 
 constexpr int kWaveBuf = 256;        // staged pairs per wave (>= 64 lanes x kCand)
 constexpr int kUnitWaveBuf = 128;    // LDS units emit one candidate per lane and call
@@ -1247,7 +1250,7 @@ __global__ __launch_bounds__(kWNT, 4) void k_wave_units(Args a) {
 // dependent loads of the offset arrays.
 // ---------------------------------------------------------------------------
 constexpr int kClassNT = 256;
-constexpr int kClassPer = 8;
+constexpr int kClassPer = 16;
 constexpr int kClassChunk = kClassNT * kClassPer;
 
 __device__ __forceinline__ void append_dense(const Args& a, uint32_t t, uint32_t nr, uint32_t ns) {
@@ -1340,8 +1343,10 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
         s_ws[3][1] = am;
         uint32_t msum = 0;
         for (int q = 0; q < kClassNT / kWave; ++q) msum += s_msz[q];
-        if (as) atomicAdd(&a.ctr[kSmallEntries], as);
-        if (msum) atomicAdd(&a.ctr[kMedEntries], msum);
+        // both statistics in one 64-bit add (every workgroup adds to the same
+        // words, so the atomics serialise; the low word never carries)
+        const unsigned long long both = (unsigned long long)as | ((unsigned long long)msum << 32);
+        if (both) atomicAdd((unsigned long long*)&a.ctr[kSmallEntries], both);
     }
     __syncthreads();
     const uint32_t total_small = s_ws[3][0], total_med = s_ws[3][1];
@@ -1359,8 +1364,13 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
     __syncthreads();
     const uint32_t nunits = total_small ? s_uidx[total_small - 1] + 1 : 0u;
     if (tid == 0) {
-        s_base[0] = total_small ? atomicAdd(&a.ctr[kTilesWritten], total_small) : 0u;
-        s_base[1] = nunits ? atomicAdd(&a.ctr[kUnitsWritten], nunits) : 0u;
+        // small tiles and units reserved with one 64-bit add, as above
+        const unsigned long long add =
+            (unsigned long long)total_small | ((unsigned long long)nunits << 32);
+        const unsigned long long tu =
+            add ? atomicAdd((unsigned long long*)&a.ctr[kTilesWritten], add) : 0ull;
+        s_base[0] = (uint32_t)tu;
+        s_base[1] = (uint32_t)(tu >> 32);
         s_base[2] = total_med ? atomicAdd(&a.ctr[kMedCount], total_med) : 0u;
     }
     __syncthreads();
