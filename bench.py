@@ -246,8 +246,8 @@ def bench_batch(args, pk, sj, torch):
 
 def bench_distance(args, pk, sj, torch):
     """Epsilon-distance join (Sec. 1): a step is one sj_distance_join over the
-    resident point sets -- squares, grid choice, partition of both sides, the
-    intersection join into the candidate buffer and the distance check."""
+    resident point sets -- squares, grid choice, partition of both sides, and
+    the intersection join with the distance check in its sweep."""
     from paper_1908_11740_amd import datagen
     log("generating", args.workload)
     P, Q, eps = datagen.skewed_points_10m()
