@@ -21,7 +21,8 @@ from paper_1908_11740_amd import sj  # noqa: E402
 from gpu_util import sort_pairs, to_dev  # noqa: E402
 
 SCHED = {"tuned": dict(), "plain": dict(flags=sj.SJ_PLAIN), "twopass": dict(flags=sj.SJ_TWO_PASS),
-         "tau1": dict(split_tau=1), "stripes": dict(flags=sj.SJ_STRIPES)}
+         "tau1": dict(split_tau=1), "stripes": dict(flags=sj.SJ_STRIPES),
+         "gbda": dict(split_tau=1, flags=sj.SJ_GBDA), "sweepx": dict(flags=sj.SJ_SWEEP_X)}
 
 
 def say(*a):
@@ -90,6 +91,32 @@ def test_medium_vs_filter_and_refine():
         got, _ = gpu_distance(P, Q, eps, k=k, **SCHED[sched])
         assert np.array_equal(got, ref), (k, sched)
     assert len(ref) > 1_000_000
+
+
+@pytest.mark.parametrize("k", [0, 5, 97])
+def test_sorted_output_is_the_oracle_list(small, k):
+    """With SJ_SORTED_OUTPUT the pairs come out in the oracle's (i, j) order,
+    byte for byte, on any grid."""
+    P, Q, eps, ref = small
+    pairs, _ = sj.distance_join(to_dev(P), to_dev(Q), eps, k=k, flags=sj.SJ_SORTED_OUTPUT)
+    torch.cuda.synchronize()
+    got = pairs.cpu().numpy()
+    assert got.shape == ref.shape and np.array_equal(got, ref)
+
+
+def test_filter_pairs_counted_in_every_mode(small):
+    """The filter's pair count does not depend on the schedule: single pass,
+    two passes (counted once, in the counting pass) and count only agree."""
+    P, Q, eps, ref = small
+    Pd, Qd = to_dev(P), to_dev(Q)
+    counts = []
+    for flags in (0, sj.SJ_TWO_PASS):
+        gpu_distance(P, Q, eps, k=33, flags=flags)
+        counts.append(sj.distance_last_info()["candidates"])
+    s, n = sj.distance_join_into(Pd, Qd, eps, None, sj.make_grid(33))
+    assert s == sj.SJ_OK and n == len(ref)
+    counts.append(sj.distance_last_info()["candidates"])
+    assert counts[0] == counts[1] == counts[2] >= len(ref)
 
 
 def test_zero_eps_and_duplicates():
