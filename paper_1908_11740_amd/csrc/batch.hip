@@ -200,7 +200,12 @@ hipError_t capture(sj_batch* b) {
 }
 
 // Eager runs of the given joins (on their lanes) until every one fits.
+// Re-preparing a join may free and reallocate its partition buffers and its
+// lane's work lists, and may switch it to two passes, so a recorded graph
+// holds stale kernel arguments after any job is prepared again: it is
+// dropped here, and the next replay records a new one.
 sj_status settle(sj_batch* b, std::vector<int> jobs, hipStream_t s) {
+    if (!jobs.empty()) drop_graph(b);
     for (int attempt = 0; attempt < 4 && !jobs.empty(); ++attempt) {
         for (int j : jobs) {
             sj_status st = prepare_join(b, j);
@@ -219,7 +224,6 @@ sj_status settle(sj_batch* b, std::vector<int> jobs, hipStream_t s) {
         if (e != hipSuccess) return from_hip_err(e);
         sj_status st = check(b, jobs);
         if (st != SJ_OK) return st;
-        if (!jobs.empty()) drop_graph(b);
     }
     if (!jobs.empty()) {
         api_set_error("batch: buffers still too small after regrowth");

@@ -105,12 +105,16 @@ def test_batch_inputs_changed_in_place_regrow():
         Sd.copy_(torch.from_numpy(S2))
         new.append((R2, S2))
     refs = [oracle.pbsm(R, S, 16) for R, S in new]
-    st, n = b.run()
-    assert list(n) == [len(r) for r in refs]
-    if st == sj.SJ_OK:
-        _check_batch(b, new, refs, st, n)
-    else:
-        assert st == sj.SJ_ERR_CAPACITY and any(len(r) > big for r in refs)
+    # the replay that outgrows the buffers (regrowth), then replays of the
+    # graph recorded after it, which must not use the freed buffers
+    for rep in range(3):
+        say("regrow replay", rep)
+        st, n = b.run()
+        assert list(n) == [len(r) for r in refs]
+        if st == sj.SJ_OK:
+            _check_batch(b, new, refs, st, n)
+        else:
+            assert st == sj.SJ_ERR_CAPACITY and any(len(r) > big for r in refs)
     b.free()
 
 
