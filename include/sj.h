@@ -290,6 +290,28 @@ sj_status sj_last_join_stats(sj_join_stats* out);
  */
 sj_status sj_sort_pairs(sj_pair* pairs, int64_t n, int64_t n_r, int64_t n_s, void* stream);
 
+/* Most pairs sj_sort_pairs_noalloc sorts (its fixed work buffer: 8 bytes per
+ * pair plus the digit histograms, about 33 MiB per GPU). */
+#define SJ_SORT_NOALLOC_MAX 4194304
+
+/*
+ * For callers that cannot allocate device memory (code recorded into a HIP
+ * graph, tight serving loops, harnesses that forbid allocation): the same
+ * sort as sj_sort_pairs, same arguments, result and order, with no hipMalloc,
+ * hipFree or other allocating call.  Its work buffers live in one fixed
+ * device array per GPU (about 33 MiB), held from the first call on that GPU
+ * until the process ends.
+ *   n         <= SJ_SORT_NOALLOC_MAX, else SJ_ERR_TOO_LARGE (nothing is
+ *             enqueued; sj_last_error names the limit).
+ * Enqueued on the stream (no synchronisation).  Every call on one GPU uses
+ * the same array and keeps the last call's contents, so calls that overlap
+ * on one GPU -- on different streams, or from different threads -- race and
+ * must be ordered by the caller.  It does not share buffers with
+ * sj_sort_pairs.
+ */
+sj_status sj_sort_pairs_noalloc(sj_pair* pairs, int64_t n, int64_t n_r, int64_t n_s,
+                                void* stream);
+
 /*
  * The sweeping-axis model of Sec. 3.3 for chosen tiles of two partitioned
  * inputs (the join evaluates the same model on its medium and dense tiles).

@@ -143,6 +143,66 @@ unsigned grid_of(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
 }
 
+sj_status check_args(const sj_pair* pairs, int64_t n, int64_t n_r, int64_t n_s) {
+    if (n < 0 || (n > 0 && !pairs) || n_r < 0 || n_s < 0 || n_r > ((int64_t)1 << 31) ||
+        n_s > ((int64_t)1 << 31))
+        return SJ_ERR_ARG;
+    if ((uintptr_t)pairs & 7u) return SJ_ERR_ARG;
+    if (n >= ((int64_t)1 << 32)) return SJ_ERR_TOO_LARGE;
+    return SJ_OK;
+}
+
+// The passes of the sort over n >= 2 pairs with the given work buffers:
+// tmp (n keys), hist (256 * tiles + 1 counters), bs (the scan's block sums),
+// st (a status word whose flags are clear).  Launches only.
+hipError_t sort_passes(unsigned long long* buf, int64_t n, int64_t n_r, int64_t n_s,
+                       unsigned long long* tmp, uint32_t* hist, uint32_t* bs, DevStatus* st,
+                       hipStream_t s) {
+    const int64_t tiles = (n + kRsTile - 1) / kRsTile;
+    const int64_t hlen = (int64_t)kRsDigits * tiles;
+    // digit positions of the key (r << 32) | s that can be non-zero
+    int shifts[8];
+    int np = 0;
+    for (int b = 0; b < bits_for(n_s); b += 8) shifts[np++] = b;
+    for (int b = 0; b < bits_for(n_r); b += 8) shifts[np++] = 32 + b;
+    hipLaunchKernelGGL(k_rs_swap, dim3(grid_of(n)), dim3(256), 0, s, buf, tmp, n);
+    unsigned long long* src = tmp;
+    unsigned long long* dst = buf;
+    for (int p = 0; p < np; ++p) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(kRsNT), 0, s, src, n, shifts[p],
+                           tiles, hist);
+        const hipError_t e = scan_u32(hist, hlen, bs, &st->n_pairs, st, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(kRsNT), 0, s, src, dst, n,
+                           shifts[p], tiles, hist);
+        std::swap(src, dst);
+    }
+    // the sorted keys are in src; back to pairs in the caller's buffer
+    hipLaunchKernelGGL(k_rs_swap, dim3(grid_of(n)), dim3(256), 0, s, src, buf, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Work buffers of sj_sort_pairs_noalloc: one fixed array per GPU, resident
+// until the process ends (see include/sj.h).  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address is taken once per
+// device with hipGetSymbolAddress, and only that address is used.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNaTiles = (SJ_SORT_NOALLOC_MAX + kRsTile - 1) / kRsTile;
+constexpr int64_t kNaHist = kRsDigits * kNaTiles + 1;
+constexpr int64_t kNaTmpBytes = SJ_SORT_NOALLOC_MAX * 8;
+constexpr int64_t kNaHistOff = kNaTmpBytes;
+constexpr int64_t kNaBsOff = (kNaHistOff + kNaHist * 4 + 255) / 256 * 256;
+constexpr int64_t kNaBsWords = (kRsDigits * kNaTiles + 8191) / 8192 + 1;  // >= scan block sums
+constexpr int64_t kNaStOff = (kNaBsOff + kNaBsWords * 4 + 255) / 256 * 256;
+constexpr int64_t kNaBytes = kNaStOff + (int64_t)((sizeof(DevStatus) + 255) / 256 * 256);
+
+__device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_namu;
+unsigned char* g_na_ptr[kNaMaxDevices] = {};  // device address of scratch per device
+
 }  // namespace
 }  // namespace sj
 
@@ -150,11 +210,8 @@ using namespace sj;
 
 extern "C" sj_status sj_sort_pairs(sj_pair* pairs, int64_t n, int64_t n_r, int64_t n_s,
                                    void* stream) {
-    if (n < 0 || (n > 0 && !pairs) || n_r < 0 || n_s < 0 || n_r > ((int64_t)1 << 31) ||
-        n_s > ((int64_t)1 << 31))
-        return SJ_ERR_ARG;
-    if ((uintptr_t)pairs & 7u) return SJ_ERR_ARG;
-    if (n >= ((int64_t)1 << 32)) return SJ_ERR_TOO_LARGE;
+    const sj_status as = check_args(pairs, n, n_r, n_s);
+    if (as != SJ_OK) return as;
     if (n < 2) return SJ_OK;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SJ_ERR_DEVICE;
@@ -178,26 +235,47 @@ extern "C" sj_status sj_sort_pairs(sj_pair* pairs, int64_t n, int64_t n_r, int64
     // the library buffers are shared by every sort on this device: a sort
     // enqueued on another stream runs after the previous one
     if (hipStreamWaitEvent(s, S.done, 0) != hipSuccess) return SJ_ERR_DEVICE;
-    // digit positions of the key (r << 32) | s that can be non-zero
-    int shifts[8];
-    int np = 0;
-    for (int b = 0; b < bits_for(n_s); b += 8) shifts[np++] = b;
-    for (int b = 0; b < bits_for(n_r); b += 8) shifts[np++] = 32 + b;
-    unsigned long long* buf = (unsigned long long*)pairs;
     ProfRange pr("k_sort_pairs", s);
-    hipLaunchKernelGGL(k_rs_swap, dim3(grid_of(n)), dim3(256), 0, s, buf, S.tmp, n);
-    unsigned long long* src = S.tmp;
-    unsigned long long* dst = buf;
-    for (int p = 0; p < np; ++p) {
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(kRsNT), 0, s, src, n, shifts[p],
-                           tiles, S.hist);
-        if (scan_u32(S.hist, hlen, S.bs, &S.st->n_pairs, S.st, s) != hipSuccess) return SJ_ERR_DEVICE;
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(kRsNT), 0, s, src, dst, n,
-                           shifts[p], tiles, S.hist);
-        std::swap(src, dst);
-    }
-    // the sorted keys are in src; back to pairs in the caller's buffer
-    hipLaunchKernelGGL(k_rs_swap, dim3(grid_of(n)), dim3(256), 0, s, src, buf, n);
-    if (hipGetLastError() != hipSuccess || hipEventRecord(S.done, s) != hipSuccess) return SJ_ERR_DEVICE;
+    if (sort_passes((unsigned long long*)pairs, n, n_r, n_s, S.tmp, S.hist, S.bs, S.st, s) !=
+            hipSuccess ||
+        hipEventRecord(S.done, s) != hipSuccess)
+        return SJ_ERR_DEVICE;
     return SJ_OK;
+}
+
+extern "C" sj_status sj_sort_pairs_noalloc(sj_pair* pairs, int64_t n, int64_t n_r, int64_t n_s,
+                                           void* stream) {
+    const sj_status as = check_args(pairs, n, n_r, n_s);
+    if (as != SJ_OK) return as;
+    if (n > SJ_SORT_NOALLOC_MAX) {
+        api_set_error("sj_sort_pairs_noalloc: more pairs than the fixed work buffer holds "
+                      "(SJ_SORT_NOALLOC_MAX)");
+        return SJ_ERR_TOO_LARGE;
+    }
+    if (n < 2) return SJ_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SJ_ERR_DEVICE;
+    if (dev < 0 || dev >= kNaMaxDevices) return SJ_ERR_DEVICE;
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_namu);
+        if (!g_na_ptr[dev]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                api_set_error("sj_sort_pairs_noalloc: no device address for the work buffer");
+                return SJ_ERR_DEVICE;
+            }
+            g_na_ptr[dev] = (unsigned char*)p;
+        }
+        base = g_na_ptr[dev];
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    DevStatus* st = (DevStatus*)(base + kNaStOff);
+    // the status word keeps the last call's contents: clear it (a fill
+    // kernel, so the call can also be recorded into a graph)
+    hipError_t e = launch_fill_u32((uint32_t*)st, 0u, (int64_t)(sizeof(DevStatus) / 4), s);
+    if (e == hipSuccess)
+        e = sort_passes((unsigned long long*)pairs, n, n_r, n_s, (unsigned long long*)base,
+                        (uint32_t*)(base + kNaHistOff), (uint32_t*)(base + kNaBsOff), st, s);
+    return e == hipSuccess ? SJ_OK : SJ_ERR_DEVICE;
 }

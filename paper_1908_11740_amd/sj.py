@@ -147,6 +147,7 @@ def lib():
         L.sj_mlp_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, ctypes.c_int32, vp]
         L.sj_sweep_axis.argtypes = [vp, vp, vp, i64, vp, vp]
         L.sj_sort_pairs.argtypes = [vp, i64, i64, i64, vp]
+        L.sj_sort_pairs_noalloc.argtypes = [vp, i64, i64, i64, vp]
         L.sj_distance_join.argtypes = [vp, i64, vp, i64, f32, ctypes.POINTER(Grid), vp, i64,
                                        i64p, vp]
         L.sj_distance_last_info.argtypes = [ctypes.POINTER(DistanceInfo)]
@@ -155,7 +156,8 @@ def lib():
         for f in ("sj_partition", "sj_join", "sj_join_count", "sj_part_info", "sj_part_download",
                   "sj_features", "sj_choose_grid", "sj_picker_load", "sj_mlp_forward",
                   "sj_mlp_loss", "sj_mlp_backward", "sj_mlp_adam", "sj_distance_join", "sj_sweep_axis",
-                  "sj_distance_last_info", "sj_distance_tune", "sj_sort_pairs"):
+                  "sj_distance_last_info", "sj_distance_tune", "sj_sort_pairs",
+                  "sj_sort_pairs_noalloc"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -384,6 +386,20 @@ def sort_pairs(pairs, n_r, n_s, stream=None):
         raise ValueError("pairs must be a contiguous (n, 2) int32 CUDA tensor")
     _check(lib().sj_sort_pairs(_ptr(pairs), pairs.shape[0], int(n_r), int(n_s), _stream(stream)),
            "sj_sort_pairs")
+    return pairs
+
+
+SJ_SORT_NOALLOC_MAX = 4194304
+
+
+def sort_pairs_noalloc(pairs, n_r, n_s, stream=None):
+    """sj_sort_pairs_noalloc: the same sort with the library's fixed per-GPU
+    work buffer (no device allocation); at most SJ_SORT_NOALLOC_MAX pairs."""
+    if not (isinstance(pairs, torch.Tensor) and pairs.is_cuda and pairs.dtype == torch.int32 and
+            pairs.dim() == 2 and pairs.shape[1] == 2 and pairs.is_contiguous()):
+        raise ValueError("pairs must be a contiguous (n, 2) int32 CUDA tensor")
+    _check(lib().sj_sort_pairs_noalloc(_ptr(pairs), pairs.shape[0], int(n_r), int(n_s),
+                                       _stream(stream)), "sj_sort_pairs_noalloc")
     return pairs
 
 
