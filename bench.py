@@ -103,7 +103,7 @@ def kernel_bytes(name, w):
         "k_compact": 16 * w["P"],
     }
     if st["single_pass"]:
-        table["k_lds_units_single"] = 20 * st["small_entries"] + 8 * st["pairs_small"]
+        table["k_span_units_single"] = 20 * st["small_entries"] + 8 * st["pairs_small"]
         table["k_lds_medium_single"] = 20 * st["medium_entries"] + 8 * st["pairs_medium"]
         table["k_dense_sweep_single"] = 20 * st["dense_entries"] + 8 * st["pairs_dense"]
     return table.get(name)

@@ -47,7 +47,7 @@ void free_part(Part& P) {  // st belongs to the batch's status array
 }
 
 void free_work(JoinWork& w) {
-    void* bufs[] = {w.tinfo, w.units, w.med, w.medt, w.dense, w.dense_unit_prefix, w.dgrp, w.dmj,
+    void* bufs[] = {w.uspan, w.units, w.med, w.medt, w.dense, w.dense_unit_prefix, w.dgrp, w.dmj,
                     w.ucnt, w.scan_tmp,
                     w.dbox, w.didf, w.dtmp, w.sc_buf, w.sc_fills, w.sc_ctr, w.sc_total, w.ctr};
     for (void* b : bufs)

@@ -87,12 +87,13 @@ struct Args {
     int med_cap;      // medium tiles: small_cap < nr + ns <= med_cap
     int split_tau;    // pivots per dense unit
     int plain;
-    uint4* tinfo;     // small tiles: (R start, nr, S start, ns), grouped by unit
-    uint2* units;     // small units: (first tinfo index, tile count)
+    int unit_tiles;   // tiles per small unit (at most)
+    uint4* uspan;     // small units: (R start, NR, S start, NS) of the unit's entry spans
+    uint2* units;     // small units: (first blocked tile, tile count)
     uint4* med;       // medium tiles: (R start, nr, S start, ns)
     uint4* dense;     // dense tiles: (tile, base in dense buffer, nr, ns)
     uint32_t* dprefix;  // dense units before each dense tile
-    int64_t cap_tiles, cap_units, cap_med, cap_dense, cap_dent, cap_dunits;
+    int64_t cap_units, cap_med, cap_dense, cap_dent, cap_dunits;
     float4* dbox;
     uint32_t* didf;
     unsigned long long* dtmp;
@@ -886,33 +887,55 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
 }
 
 // ---------------------------------------------------------------------------
-// Wave units: small tiles are batched into units of at most kWE entries and
-// every wavefront processes its own units in a private LDS region, with
-// wave-level fences only.  Without workgroup barriers the waves of a CU
-// overlap one another's memory waits.  Same steps as run_lds_unit: stage the
-// unit's tile slabs, sort each tile segment by x_l (counting pass, written
-// back sorted), then the load-balanced candidate ranges of the sweep.
+// Span units: the small tiles.  k_classify cuts the blocked tile order into
+// runs of consecutive tiles of at most small_cap entries each (a tile with
+// one empty list rides along: its entries are loaded but never swept), so a
+// unit's R entries and its S entries are each one contiguous span of the
+// tile slabs.  A unit record is (R start, NR, S start, NS) and (first tile,
+// tile count); the gather needs no tile table, so the kernel issues the next
+// unit's gather (and its table of tile offsets) as soon as the current
+// unit's entries sit sorted in LDS, and the loads travel while the current
+// unit is swept.  The tile of an entry is found by a binary search in the
+// offset table (a position keeps its tile through the sort, which stays
+// inside tile segments), the candidate prefix of the sweep is taken per
+// wavefront over the wave's own pivots, and a unit costs three workgroup
+// barriers: table and keys staged, boxes sorted, LDS free again.
 // ---------------------------------------------------------------------------
-constexpr int kWNT = 256;               // threads per workgroup (4 independent waves)
-constexpr int kWQ = 4;                  // entries per lane
-constexpr int kWE = kWave * kWQ;        // entries per wave unit
-constexpr int kWTC = kWE / 2 + 1;       // tiles per wave unit (each has >= 2 entries)
-constexpr int kWBuf = 96;               // staged pairs per wave (>= 64 + one flush margin)
-
-struct WaveTable {                      // one unit's local tile table and entry -> tile map
-    uint16_t rl[kWTC + 1], sl[kWTC + 1];  // local start (prefix) of each tile's R / S segment
-    uint16_t tk[kWE];                     // local tile of each entry, then scan starts
+struct SpanLayout {
+    unsigned long long* wbuf;  // [NT / 64 * kUnitWaveBuf] pair staging per wave
+    uint32_t* acc;             // [0] sink accumulator
+    uint16_t* rl;              // [NT] local start of each tile's R segment (count + 1 used)
+    uint16_t* sl;              // [NT] ... of its S segment
+    float4* bx;                // [E] sorted boxes (R part, then S part)
+    uint32_t* id;              // [E] sorted id words
+    uint32_t* key;             // [E + 8] sort keys; then per wave the candidate prefix
+    uint16_t* js;              // [E] per wave: first candidate of each pivot's scan
 };
 
-// 10,048 bytes: four waves of a workgroup and four workgroups fit one CU
-struct WaveLds {
-    float4 bx[kWE];                     // sorted boxes (R part, then S part)
-    uint32_t id[kWE];                   // sorted id words
-    uint32_t key[kWE + 8];              // sort keys, then candidate-range prefix
-    uint32_t rg[kWTC + 1], sg[kWTC + 1];  // global segment starts (staging only)
-    WaveTable tab[2];                   // the unit being swept and the next one
-    unsigned long long wbuf[kWBuf];     // pair staging
-};
+__host__ __device__ constexpr size_t span_lds_bytes(int nt, int e) {
+    return (size_t)(nt / kWave) * kUnitWaveBuf * 8 + 16 + (size_t)nt * 4 +  // staging, acc, tables
+           (size_t)e * 16 + (size_t)e * 4 + (size_t)(e + 8) * 4 + (size_t)e * 2;
+}
+
+__device__ inline SpanLayout carve_span(unsigned char* p, int nt, int e) {
+    SpanLayout L;
+    L.wbuf = (unsigned long long*)p;
+    p += (size_t)(nt / kWave) * kUnitWaveBuf * 8;
+    L.acc = (uint32_t*)p;
+    p += 16;
+    L.rl = (uint16_t*)p;
+    p += (size_t)nt * 2;
+    L.sl = (uint16_t*)p;
+    p += (size_t)nt * 2;  // nt is a multiple of 64: the boxes stay 16-byte aligned
+    L.bx = (float4*)p;
+    p += (size_t)e * 16;
+    L.id = (uint32_t*)p;
+    p += (size_t)e * 4;
+    L.key = (uint32_t*)p;
+    p += (size_t)(e + 8) * 4;
+    L.js = (uint16_t*)p;
+    return L;
+}
 
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
@@ -924,330 +947,302 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, int lane) {
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v, int lane) {
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, kWave);
-        if (lane >= d) v = t > v ? t : v;
+// Last k in [0, c) with T[k] <= v: the segment holding local position v
+// (T non-decreasing, T[0] = 0 <= v < T[c]; empty segments are skipped).
+__device__ __forceinline__ int segment_of(const uint16_t* T, int c, int v) {
+    int lo = 0, hi = c;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)T[mid] <= v) lo = mid;
+        else hi = mid;
     }
-    return v;
+    return lo;
 }
 
-// A unit staged for the sweep: its table in LDS (WaveLds::tab[buffer]) and
-// its entries in flight into registers.  The kernel stages unit u + 1 (and
-// loads the table of u + 2) before it sweeps unit u, so both dependent
-// global round trips of a unit overlap the previous unit's work.
-static_assert(sizeof(WaveLds) * 4 <= 40960, "four wave-unit workgroups per CU");
+typedef float vf4 __attribute__((ext_vector_type(4)));  // a box held in registers
 
-struct WaveStage {
-    int c, NR, NS;
-    float4 pb[kWQ];
-    uint32_t pi[kWQ], pg[kWQ];
-};
-
-// table registers: lane l holds tiles 2l and 2l+1 of the unit
-struct WaveTabRegs {
-    uint4 t0, t1;
-    int c;
-};
-
-__device__ __forceinline__ WaveTabRegs load_wave_table(const Args& a, uint2 ud) {
-    const int lane = lane_id();
-    WaveTabRegs r;
-    r.c = (int)ud.y;
-    r.t0 = make_uint4(0, 0, 0, 0);
-    r.t1 = make_uint4(0, 0, 0, 0);
-    if (2 * lane < r.c) r.t0 = a.tinfo[ud.x + 2 * lane];
-    if (2 * lane + 1 < r.c) r.t1 = a.tinfo[ud.x + 2 * lane + 1];
-    return r;
+// Issue the loads of a staged span unit: thread tid's words of the tile
+// offset tables (raw: made local to the spans only when the unit is staged,
+// so that no instruction here waits for a load) and its entries
+// e = tid + q * NT.
+template <int NT, int Q>
+__device__ __forceinline__ void span_issue(const Args& a, int tid, const uint4& sp, const uint2& ut,
+                                           uint32_t& tr, uint32_t& ts, vf4 (&pb)[Q],
+                                           uint32_t (&pi)[Q]) {
+    if (tid <= (int)ut.y) {
+        tr = a.offR[ut.x + tid];
+        ts = a.offS[ut.x + tid];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t e = (uint32_t)(tid + q * NT);
+        if (e < sp.y) {
+            pb[q] = ((const vf4*)a.entR)[sp.x + e];
+            pi[q] = a.idR[sp.x + e];
+        } else if (e < sp.y + sp.w) {
+            pb[q] = ((const vf4*)a.entS)[sp.z + (e - sp.y)];
+            pi[q] = a.idS[sp.z + (e - sp.y)];
+        }
+    }
 }
 
-// Write the table of a unit to LDS, map entries to tiles and issue the
-// gather of the unit's entries.  Returns false (status flagged) if the unit
-// breaks the classification's invariants.
-__device__ bool stage_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const WaveTabRegs& tr,
-                                WaveStage& st) {
-    const int lane = lane_id();
-    const int c = tr.c;
-    st.c = c;
-    st.NR = st.NS = 0;
-    if (c > kWTC) {  // cannot happen for units built by k_classify
-        if (lane == 0) atomicOr(&a.st->flags, kStatInternal);
-        return false;
-    }
-    const uint32_t ir = wave_incl_sum(tr.t0.y + tr.t1.y, lane);
-    const uint32_t is = wave_incl_sum(tr.t0.w + tr.t1.w, lane);
-    const int NR = __shfl((int)ir, kWave - 1, kWave), NS = __shfl((int)is, kWave - 1, kWave);
-    const int NE = NR + NS;
-    if (NE > kWE) {
-        if (lane == 0) atomicOr(&a.st->flags, kStatInternal);
-        return false;
-    }
-    st.NR = NR;
-    st.NS = NS;
-    {
-        const uint32_t r0 = ir - tr.t0.y - tr.t1.y, s0 = is - tr.t0.w - tr.t1.w;
-        if (2 * lane < c) {
-            W.rg[2 * lane] = tr.t0.x;
-            W.sg[2 * lane] = tr.t0.z;
-            T.rl[2 * lane] = (uint16_t)r0;
-            T.sl[2 * lane] = (uint16_t)s0;
-        }
-        if (2 * lane + 1 < c) {
-            W.rg[2 * lane + 1] = tr.t1.x;
-            W.sg[2 * lane + 1] = tr.t1.z;
-            T.rl[2 * lane + 1] = (uint16_t)(r0 + tr.t0.y);
-            T.sl[2 * lane + 1] = (uint16_t)(s0 + tr.t0.w);
-        }
-        if (lane == 0) {
-            T.rl[c] = (uint16_t)NR;
-            T.sl[c] = (uint16_t)NS;
-        }
-    }
-    // local tile of every entry: head marks (R: k, S: c + k) + max-scan
-#pragma unroll
-    for (int q = 0; q < kWQ; ++q) T.tk[lane * kWQ + q] = 0;
-    wave_fence();
-    for (int k = lane; k < c; k += kWave) {
-        if (T.rl[k + 1] > T.rl[k]) T.tk[T.rl[k]] = (uint16_t)k;
-        if (T.sl[k + 1] > T.sl[k]) T.tk[NR + T.sl[k]] = (uint16_t)(c + k);
-    }
-    wave_fence();
-    {
-        uint32_t v[kWQ];
-        uint32_t run = 0;
-#pragma unroll
-        for (int q = 0; q < kWQ; ++q) {
-            const uint32_t x = T.tk[lane * kWQ + q];
-            run = x > run ? x : run;
-            v[q] = run;
-        }
-        const uint32_t inc = wave_incl_max(run, lane);
-        uint32_t ex = __shfl_up(inc, 1, kWave);
-        if (lane == 0) ex = 0;
-        wave_fence();
-#pragma unroll
-        for (int q = 0; q < kWQ; ++q) {
-            const int i = lane * kWQ + q;
-            const uint32_t t = v[q] > ex ? v[q] : ex;
-            if (i < NE) T.tk[i] = (uint16_t)(i < NR ? t : t - (uint32_t)c);
-        }
-    }
-    wave_fence();
-    // issue the gather (coalesced within each tile segment)
-#pragma unroll
-    for (int q = 0; q < kWQ; ++q) {
-        const int e = lane + q * kWave;
-        st.pg[q] = 0;
-        if (e < NE) {
-            const bool isR = e < NR;
-            const int k = T.tk[e];
-            const uint32_t g = isR ? W.rg[k] + (uint32_t)e - T.rl[k] : W.sg[k] + (uint32_t)(e - NR) - T.sl[k];
-            st.pb[q] = (isR ? a.entR : a.entS)[g];
-            st.pi[q] = (isR ? a.idR : a.idS)[g];
-            st.pg[q] = g;
-        }
-    }
-    return true;
+// waves per SIMD that the LDS slab allows: the register budget the compiler
+// is held to, so that registers do not lower the occupancy further
+__host__ __device__ constexpr int span_waves(int nt, int q) {
+    const int per_cu = (int)(163840 / span_lds_bytes(nt, nt * q));
+    const int w = per_cu * (nt / kWave) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-// Sort the staged unit's tile segments by x_l (counting pass: written back
-// sorted) and sweep them: the load-balanced candidate ranges of run_lds_unit
-// with one wavefront and wave-level fences only.
-template <int MODE>
-__device__ void sweep_wave_unit(const Args& a, WaveLds& W, WaveTable& T, const WaveStage& st,
-                                uint32_t u, Sink<MODE, false>& sk) {
-    const int lane = lane_id();
-    const int NR = st.NR, NE = st.NR + st.NS;
-#pragma unroll
-    for (int q = 0; q < kWQ; ++q) {
-        const int e = lane + q * kWave;
-        if (e < NE) {
-            if (MODE == kWrite) {  // the counting pass left every slab sorted
-                W.bx[e] = make_float4(st.pb[q].x, st.pb[q].y, st.pb[q].z, st.pb[q].w);
-                W.id[e] = st.pi[q];
-            } else {
-                W.key[e] = order_key(st.pb[q].x);
-            }
+template <int NT, int Q, int MODE>
+__global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
+    constexpr int E = NT * Q;
+    constexpr int PW = Q * kWave;  // pivots of one wavefront
+    constexpr int kCh = kChunkC / 2;  // consecutive candidates per lane and round
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const SpanLayout L = carve_span(smem, NT, E);
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const uint32_t nu = min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
+    const uint32_t G = gridDim.x;
+    Sink<MODE, true> sk;
+    sk.buf = L.wbuf + w * kUnitWaveBuf;
+    sk.s_acc = L.acc;
+    sk.bufcap = kUnitWaveBuf;
+    sk.init(blockIdx.x * (NT / kWave) + w);
+    // Unit records of this workgroup, kWave at a time: lane l holds the record
+    // of the workgroup's unit i0 + l (unit blockIdx.x + (i0 + l) * G), read
+    // with readlane.  No memory wait falls inside the loop: vector loads
+    // retire in order, so waiting for a record loaded after the next unit's
+    // entries would wait for the entries too.
+    uint4 rsp = make_uint4(0, 0, 0, 0);
+    uint2 rut = make_uint2(0, 0);
+    int i0 = 0;
+    auto load_records = [&](int base) {
+        i0 = base;
+        const uint32_t uu = blockIdx.x + (uint32_t)(base + lane) * G;
+        if (uu < nu) {
+            rsp = a.uspan[uu];
+            rut = a.units[uu];
         }
+    };
+    auto record = [&](int i, uint4& s, uint2& t) {  // i0 <= i < i0 + kWave
+        const int l = i - i0;
+        s = make_uint4(__builtin_amdgcn_readlane(rsp.x, l), __builtin_amdgcn_readlane(rsp.y, l),
+                       __builtin_amdgcn_readlane(rsp.z, l), __builtin_amdgcn_readlane(rsp.w, l));
+        t = make_uint2(__builtin_amdgcn_readlane(rut.x, l), __builtin_amdgcn_readlane(rut.y, l));
+    };
+    // staged unit: record, this thread's table words and entries (in flight)
+    uint4 sp = make_uint4(0, 0, 0, 0);
+    uint2 ut = make_uint2(0, 0);
+    uint32_t tr = 0, ts = 0;
+    vf4 pb[Q];
+    uint32_t pi[Q];
+    uint32_t u = blockIdx.x;
+    int i = 0;
+    if (u < nu) {
+        load_records(0);
+        record(0, sp, ut);
+        span_issue<NT, Q>(a, tid, sp, ut, tr, ts, pb, pi);
     }
-    wave_fence();
-    if (MODE != kWrite) {
-        // rank sort inside each tile segment; sorted slab to LDS (and back to
-        // global memory when a writing pass follows)
-        int pos[kWQ];
+    for (; u < nu; u += G, ++i) {
+        const uint4 cur = sp;
+        const int NR = (int)cur.y, NE = (int)(cur.y + cur.w), c = (int)ut.y;
+        if (NE > E || c < 1 || c >= NT) {  // cannot happen for units built by k_classify
+            if (tid == 0) atomicOr(&a.st->flags, kStatInternal);
+            break;
+        }
+        sk.begin(a, u);  // per-unit count / output region; thread 0 clears the accumulator
+        // 1. tile table and sort keys (the writing pass reads slabs left sorted)
+        if (tid <= c) {
+            L.rl[tid] = (uint16_t)(tr - cur.x);
+            L.sl[tid] = (uint16_t)(ts - cur.z);
+        }
 #pragma unroll
-        for (int q = 0; q < kWQ; ++q) {
-            const int e = lane + q * kWave;
-            pos[q] = -1;
+        for (int q = 0; q < Q; ++q) {
+            const int e = tid + q * NT;
             if (e < NE) {
-                const bool isR = e < NR;
-                const int k = T.tk[e];
-                const int lo = isR ? (int)T.rl[k] : NR + (int)T.sl[k];
-                const int hi = isR ? (int)T.rl[k + 1] : NR + (int)T.sl[k + 1];
-                pos[q] = lo + seg_rank(W.key, lo, hi, e);
+                if (MODE == kWrite) {
+                    ((vf4*)L.bx)[e] = pb[q];
+                    L.id[e] = pi[q];
+                } else {
+                    L.key[e] = order_key(pb[q].x);
+                }
             }
         }
+        __syncthreads();
+        // 2. tile of each entry; rank sort inside its segment
+        int tk[Q];
+        {
+            int ev[Q], pe[Q];
+            bool isR[Q], act[Q];
 #pragma unroll
-        for (int q = 0; q < kWQ; ++q) {
-            if (pos[q] >= 0) {
-                W.bx[pos[q]] = make_float4(st.pb[q].x, st.pb[q].y, st.pb[q].z, st.pb[q].w);
-                W.id[pos[q]] = st.pi[q];
+            for (int q = 0; q < Q; ++q) {
+                pe[q] = tid + q * NT;
+                act[q] = pe[q] < NE;
+                isR[q] = pe[q] < NR;
+                ev[q] = isR[q] ? pe[q] : pe[q] - NR;
+                ev[q] = act[q] ? ev[q] : 0;
             }
-        }
-        wave_fence();
-        if (MODE == kCount && a.writeback) {
 #pragma unroll
-            for (int q = 0; q < kWQ; ++q) {
-                const int e = lane + q * kWave;
-                if (e < NE) {
-                    const float4 b = W.bx[e];
-                    const uint32_t idv = W.id[e];
-                    if (e < NR) {
-                        a.entR[st.pg[q]] = b;
-                        a.idR[st.pg[q]] = idv;
-                    } else {
-                        a.entS[st.pg[q]] = b;
-                        a.idS[st.pg[q]] = idv;
+            for (int q = 0; q < Q; ++q)
+                tk[q] = isR[q] ? segment_of(L.rl, c, ev[q]) : segment_of(L.sl, c, ev[q]);
+            if (MODE != kWrite) {
+                int lo[Q], hi[Q], rk[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int k = tk[q];
+                    lo[q] = isR[q] ? (int)L.rl[k] : NR + (int)L.sl[k];
+                    hi[q] = isR[q] ? (int)L.rl[k + 1] : NR + (int)L.sl[k + 1];
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) rk[q] = act[q] ? seg_rank(L.key, lo[q], hi[q], pe[q]) : 0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (act[q]) {
+                        ((vf4*)L.bx)[lo[q] + rk[q]] = pb[q];
+                        L.id[lo[q] + rk[q]] = pi[q];
                     }
                 }
             }
         }
-    }
-    // 4a. exact forward-scan range of every pivot (see run_lds_unit)
-    uint32_t* cnt = W.key;
-    auto X = [&](int q) { return W.bx[q].x; };
-    uint32_t v[kWQ];
-    uint32_t sum = 0;
-    uint16_t jsv[kWQ];
+        // the staged registers are free: start the next unit's loads
+        if (u + G < nu) {
+            if (i + 1 - i0 >= kWave) load_records(i + 1);
+            record(i + 1, sp, ut);
+            span_issue<NT, Q>(a, tid, sp, ut, tr, ts, pb, pi);
+        }
+        __syncthreads();
+        if (MODE == kCount && a.writeback) {  // slabs left sorted for the writing pass
 #pragma unroll
-    for (int q = 0; q < kWQ; ++q) {
-        const int p = lane * kWQ + q;
-        v[q] = 0;
-        jsv[q] = 0;
-        if (p < NE) {
-            const int k = T.tk[p];
-            const float4 b = W.bx[p];
-            const bool isR = p < NR;
-            const int lo = isR ? NR + (int)T.sl[k] : (int)T.rl[k];
-            const int hi = isR ? NR + (int)T.sl[k + 1] : (int)T.rl[k + 1];
-            const int j0 = search_x(X, lo, hi, b.x, isR);
-            const int j1 = search_x(X, j0, hi, b.z, true);
-            v[q] = (uint32_t)(j1 - j0);
-            jsv[q] = (uint16_t)j0;
+            for (int q = 0; q < Q; ++q) {
+                const int e = tid + q * NT;
+                if (e < NR) {
+                    a.entR[cur.x + e] = L.bx[e];
+                    a.idR[cur.x + e] = L.id[e];
+                } else if (e < NE) {
+                    a.entS[cur.z + (e - NR)] = L.bx[e];
+                    a.idS[cur.z + (e - NR)] = L.id[e];
+                }
+            }
         }
-        sum += v[q];
-    }
-    wave_fence();
-    // 4b. exclusive prefix of the range lengths
-    const uint32_t incs = wave_incl_sum(sum, lane);
-    const uint32_t Tc = __shfl(incs, kWave - 1, kWave);
-    {
-        uint32_t ex = incs - sum;
+        // 3. exact forward-scan range of this thread's pivots p = tid + q * NT
+        //    (R pivot: the s with r.x_l < s.x_l <= r.x_u; S pivot: the r with
+        //    s.x_l <= r.x_l <= s.x_u), and the wave's exclusive prefix of the
+        //    range lengths (slot q * 64 + lane)
+        uint32_t* cw = L.key + w * (PW + 1);
+        uint16_t* jw = L.js + w * PW;
+        uint32_t run = 0;
+        {
+            int lo[Q], hi[Q], j0[Q], j1[Q];
+            float xl[Q], xu[Q];
+            bool isR[Q];
 #pragma unroll
-        for (int q = 0; q < kWQ; ++q) {
-            const int p = lane * kWQ + q;
-            if (p < NE) {
-                cnt[p] = ex;
-                T.tk[p] = jsv[q];
+            for (int q = 0; q < Q; ++q) {
+                const int p = tid + q * NT;
+                const int k = tk[q];
+                isR[q] = p < NR;
+                lo[q] = hi[q] = 0;
+                xl[q] = xu[q] = 0.f;
+                if (p < NE) {
+                    const float4 b = L.bx[p];
+                    xl[q] = b.x;
+                    xu[q] = b.z;
+                    lo[q] = isR[q] ? NR + (int)L.sl[k] : (int)L.rl[k];
+                    hi[q] = isR[q] ? NR + (int)L.sl[k + 1] : (int)L.rl[k + 1];
+                }
             }
-            ex += v[q];
-        }
-        if (lane == 0) cnt[NE] = Tc;
-    }
-    wave_fence();
-    // 4c. chunks of kChunkC consecutive candidates per lane
-    sk.begin(a, u);
-    for (uint32_t it = 0; it * (uint32_t)(kWave * kChunkC) < Tc; ++it) {
-        const uint32_t c0 = it * (uint32_t)(kWave * kChunkC) + (uint32_t)lane * kChunkC;
-        const uint32_t cs = c0 < Tc ? c0 : Tc - 1u;
-        int lo = 0, hi = NE;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cnt[mid] <= cs) lo = mid;
-            else hi = mid;
-        }
-        int p = lo;
-        uint32_t pend = cnt[p + 1];
-        float4 pb4 = W.bx[p];
-        uint32_t pid = W.id[p];
+            auto X = [&](int j) { return L.bx[j].x; };
 #pragma unroll
-        for (int i = 0; i < kChunkC; ++i) {
-            const uint32_t cc = c0 + (uint32_t)i;
-            const bool valid = cc < Tc;
-            if (valid && cc >= pend) {
-                do {
-                    ++p;
-                    pend = cnt[p + 1];
-                } while (cc >= pend);
-                pb4 = W.bx[p];
-                pid = W.id[p];
+            for (int q = 0; q < Q; ++q) {
+                j0[q] = search_x(X, lo[q], hi[q], xl[q], isR[q]);
+                j1[q] = search_x(X, j0[q], hi[q], xu[q], true);
             }
-            bool hit[1] = {false};
-            uint32_t er[1] = {0}, es[1] = {0};
-            if (valid) {
-                const int j = (int)T.tk[p] + (int)(cc - cnt[p]);
-                const float4 q4 = W.bx[j];
-                const uint32_t qid = W.id[j];
-                const bool f = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
-                hit[0] = f && (!a.dist || within_eps(pb4, q4, a.e2));
-                if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
-                const bool isR = p < NR;
-                er[0] = (isR ? pid : qid) & kIdMask;
-                es[0] = (isR ? qid : pid) & kIdMask;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const uint32_t v = (uint32_t)(j1[q] - j0[q]);
+                const uint32_t inc = wave_incl_sum(v, lane);
+                cw[q * kWave + lane] = run + inc - v;
+                jw[q * kWave + lane] = (uint16_t)j0[q];
+                run += __shfl(inc, kWave - 1, kWave);
             }
-            sk.template emit<1>(a, hit, er, es);
         }
-    }
-    sk.end(a, u);
-    wave_fence();
-}
-
-template <int MODE>
-__global__ __launch_bounds__(kWNT, 4) void k_wave_units(Args a) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    WaveLds& W = ((WaveLds*)smem)[threadIdx.x / kWave];
-    const uint32_t nu = min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
-    const uint32_t waves = gridDim.x * (kWNT / kWave);
-    const uint32_t wg = blockIdx.x * (kWNT / kWave) + threadIdx.x / kWave;
-    Sink<MODE, false> sk;
-    sk.buf = W.wbuf;
-    sk.s_acc = nullptr;
-    sk.bufcap = kWBuf;
-    sk.init(wg);
-    // three-stage pipeline: table of u + 2w in registers, unit u + w staged
-    // (table in LDS, entries in flight), unit u swept
-    WaveStage cur, nxt;
-    WaveTabRegs tr{};
-    int buf = 0;
-    bool ok = true;
-    if (wg < nu) {
-        const WaveTabRegs t0 = load_wave_table(a, a.units[wg]);
-        ok = stage_wave_unit(a, W, W.tab[0], t0, cur);
-        if (wg + waves < nu) tr = load_wave_table(a, a.units[wg + waves]);
-    }
-    for (uint32_t u = wg; ok && u < nu; u += waves) {
-        const uint32_t un = u + waves;
-        bool have_next = false;
-        if (un < nu) {
-            ok = stage_wave_unit(a, W, W.tab[buf ^ 1], tr, nxt);
-            have_next = true;
-            if (un + waves < nu) tr = load_wave_table(a, a.units[un + waves]);
+        if (lane == 0) cw[PW] = run;
+        wave_fence();
+        // 4. the wave's candidates, kCh consecutive ones per lane and round;
+        //    each gets the closed y-test and the reference-point test of Eq. (1)
+        const uint32_t T = run;
+        for (uint32_t it = 0; it * (uint32_t)(kWave * kCh) < T; ++it) {
+            const uint32_t c0 = it * (uint32_t)(kWave * kCh) + (uint32_t)lane * kCh;
+            const uint32_t cs = c0 < T ? c0 : T - 1u;
+            int lo = 0, hi = PW;  // slot of candidate cs: last slot with cw[slot] <= cs
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (cw[mid] <= cs) lo = mid;
+                else hi = mid;
+            }
+            int sl = lo;
+            uint32_t pend = cw[sl + 1];
+            int p = (sl / kWave) * NT + w * kWave + (sl % kWave);
+            float4 pb4 = L.bx[p];
+            uint32_t pid = L.id[p];
+#pragma unroll
+            for (int i = 0; i < kCh; ++i) {
+                const uint32_t cc = c0 + (uint32_t)i;
+                const bool valid = cc < T;
+                if (valid && cc >= pend) {
+                    do {
+                        ++sl;
+                        pend = cw[sl + 1];
+                    } while (cc >= pend);
+                    p = (sl / kWave) * NT + w * kWave + (sl % kWave);
+                    pb4 = L.bx[p];
+                    pid = L.id[p];
+                }
+                bool hit[1] = {false};
+                uint32_t er[1] = {0}, es[1] = {0};
+                if (valid) {
+                    const int j = (int)jw[sl] + (int)(cc - cw[sl]);
+                    const float4 q4 = L.bx[j];
+                    const uint32_t qid = L.id[j];
+                    const bool f = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
+                    hit[0] = f && (!a.dist || within_eps(pb4, q4, a.e2));
+                    if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
+                    const bool isR = p < NR;
+                    er[0] = (isR ? pid : qid) & kIdMask;
+                    es[0] = (isR ? qid : pid) & kIdMask;
+                }
+                sk.template emit<1>(a, hit, er, es);
+            }
         }
-        sweep_wave_unit<MODE>(a, W, W.tab[buf], cur, u, sk);
-        if (have_next) {
-            cur = nxt;
-            buf ^= 1;
+        // 5. unit end: counts / remaining staged pairs, then LDS is free
+        if (MODE == kWrite && sk.n) sk.flush(a);
+        if (MODE == kCount) {
+            uint32_t v = sk.cnt;
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+            if (lane == 0 && v) atomicAdd(L.acc, v);
         }
+        __syncthreads();
+        if (MODE == kCount && tid == 0) a.ucnt[u] = *L.acc;
     }
-    sk.finish(a, wg);
+    sk.finish(a, blockIdx.x * (NT / kWave) + w);
 }
 
 // ---------------------------------------------------------------------------
-// k_classify: find the tiles with both lists non-empty and sort them into
-// three classes by entry count n = nr + ns (small / medium / dense).  One
-// block covers kClassChunk tiles; small units never cross block chunks.  A
-// tile's segment bounds are written with it, so the join kernels need no
-// dependent loads of the offset arrays.
+// k_classify: sort the tiles into three classes by entry count n = nr + ns
+// and build the work lists of the join.  One workgroup covers kClassChunk
+// consecutive tiles of the blocked order (kClassPer per thread).
+//   small:  both lists non-empty, n <= small_cap.  Cut into span units:
+//           maximal runs of consecutive tiles with n <= small_cap (tiles
+//           with one empty list ride along), also cut where the running
+//           entry count of the run crosses a multiple of unit_cap and every
+//           unit_tiles tiles.  A unit therefore holds at most
+//           unit_cap - 1 + small_cap entries and unit_tiles tiles, and its R
+//           and S entries are contiguous.  Runs without a joinable tile are
+//           dropped.
+//   medium: both lists non-empty, small_cap < n <= med_cap: one record each.
+//   dense:  both lists non-empty, n > med_cap: sorted globally and split.
+// A tile's segment bounds are written with its record, so the join kernels
+// need no dependent loads of the offset arrays.
 // ---------------------------------------------------------------------------
 constexpr int kClassNT = 256;
 constexpr int kClassPer = 16;
@@ -1262,146 +1257,178 @@ __device__ __forceinline__ void append_dense(const Args& a, uint32_t t, uint32_t
         atomicOr(&a.st->flags, kStatCapacity);
 }
 
-__global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
-    __shared__ uint32_t s_uidx[kClassChunk];  // unit index of the k-th small tile
-    __shared__ uint32_t s_ws[4][kClassNT / kWave];
-    __shared__ uint32_t s_msz[kClassNT / kWave];
-    __shared__ uint32_t s_base[3];
+// Block-wide exclusive sums of four per-thread values (kClassNT threads);
+// tot receives the block totals.
+__device__ __forceinline__ void block_excl4(uint32_t (&v)[4], uint32_t (&tot)[4],
+                                            uint32_t (*s_ws)[kClassNT / kWave]) {
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-    const int64_t t0 = (int64_t)blockIdx.x * kClassChunk + (int64_t)tid * kClassPer;
-    uint32_t nsmall = 0, size_small = 0, nmed = 0, size_med = 0;
-    uint4 ti[kClassPer];
-    uint8_t cls[kClassPer];  // 0 none, 1 small, 2 medium, 3 dense
-    uint32_t oR[kClassPer + 1], oS[kClassPer + 1];
+    uint32_t inc[4];
 #pragma unroll
-    for (int q = 0; q <= kClassPer; ++q) {
-        const int64_t t = t0 + q;
-        oR[q] = t <= a.C ? a.offR[t] : 0u;
-        oS[q] = t <= a.C ? a.offS[t] : 0u;
+    for (int i = 0; i < 4; ++i) {
+        inc[i] = v[i];
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc[i], d, kWave);
+            if (lane >= d) inc[i] += t;
+        }
+        if (lane == kWave - 1) s_ws[i][w] = inc[i];
     }
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kClassPer; ++q) {
-        const int64_t t = t0 + q;
-        cls[q] = 0;
-        ti[q] = make_uint4(oR[q], 0u, oS[q], 0u);
-        if (t < a.C) {
-            const uint32_t nr = oR[q + 1] - oR[q];
-            const uint32_t ns = oS[q + 1] - oS[q];
-            ti[q].y = nr;
-            ti[q].w = ns;
-            if (nr && ns) {
-                const uint32_t n = nr + ns;
-                if (n <= (uint32_t)a.small_cap) {
-                    cls[q] = 1;
-                    ++nsmall;
-                    size_small += n;
-                } else if (n <= (uint32_t)a.med_cap) {
-                    cls[q] = 2;
-                    ++nmed;
-                    size_med += n;
-                } else {
-                    cls[q] = 3;
-                    append_dense(a, (uint32_t)t, nr, ns);
-                }
+    for (int i = 0; i < 4; ++i) {
+        uint32_t before = 0, all = 0;
+        for (int q = 0; q < kClassNT / kWave; ++q) {
+            const uint32_t y = s_ws[i][q];
+            before += q < w ? y : 0u;
+            all += y;
+        }
+        v[i] = before + inc[i] - v[i];
+        tot[i] = all;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
+    __shared__ uint16_t s_j[kClassChunk + 1];  // joinable small tiles before each tile of the chunk
+    __shared__ uint32_t s_ws[4][kClassNT / kWave];
+    __shared__ uint32_t s_fc[kClassNT / kWave];  // first cut of each wave
+    __shared__ uint32_t s_base[2];
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const int64_t c0 = (int64_t)blockIdx.x * kClassChunk;  // first tile of the chunk
+    const int tl0 = tid * kClassPer;                        // this thread's first local tile
+    const int64_t t0 = c0 + tl0;
+    const uint32_t SC = (uint32_t)a.small_cap, B = (uint32_t)a.unit_cap;
+    const int TC = a.unit_tiles;
+    // offsets of tiles t0 - 1 .. t0 + kClassPer (index i <-> tile t0 - 1 + i)
+    uint32_t oR[kClassPer + 2], oS[kClassPer + 2];
+#pragma unroll
+    for (int i = 0; i < kClassPer + 2; ++i) {
+        const int64_t t = t0 - 1 + i;
+        const bool in = t >= 0 && t <= a.C;
+        oR[i] = in ? a.offR[t] : 0u;
+        oS[i] = in ? a.offS[t] : 0u;
+    }
+    // per tile (bit i <-> index i; index 0 is the tile before this thread's
+    // range): cuts a span run (a tile of more than small_cap entries, or past
+    // the grid), joinable small tile; a run tile weighs its entry count
+    auto n_of = [&](int i) { return (oR[i + 1] - oR[i]) + (oS[i + 1] - oS[i]); };
+    uint32_t brkm = 0, joinm = 0;
+    uint32_t nj = 0, je = 0, nmed = 0, med_e = 0, wsum = 0;
+#pragma unroll
+    for (int i = 0; i <= kClassPer; ++i) {
+        const int64_t t = t0 - 1 + i;
+        const bool exists = t >= 0 && t < a.C;
+        const uint32_t nr = oR[i + 1] - oR[i], ns = oS[i + 1] - oS[i], n = nr + ns;
+        if (!exists || n > SC) brkm |= 1u << i;
+        if (i == 0 || !exists) continue;
+        if (n <= SC) wsum += n;
+        if (nr && ns) {
+            if (n <= SC) {
+                joinm |= 1u << (i - 1);
+                ++nj;
+                je += n;
+            } else if (n <= (uint32_t)a.med_cap) {
+                ++nmed;
+                med_e += n;
+            } else {
+                append_dense(a, (uint32_t)t, nr, ns);
             }
         }
     }
-    // block exclusive scans of nsmall, size_small and nmed
-    uint32_t in = nsmall, isz = size_small, im = nmed;
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t tn = __shfl_up(in, d, kWave), ts = __shfl_up(isz, d, kWave);
-        const uint32_t tm = __shfl_up(im, d, kWave);
-        if (lane >= d) {
-            in += tn;
-            isz += ts;
-            im += tm;
-        }
-    }
-    if (lane == kWave - 1) {
-        s_ws[0][w] = in;
-        s_ws[1][w] = isz;
-        s_ws[2][w] = im;
-    }
+    // block prefixes: run weights, joinable tiles, medium tiles, their entries
+    uint32_t v[4] = {wsum, nj, nmed, med_e}, tot[4];
+    block_excl4(v, tot, s_ws);
+    const uint32_t wpre = v[0], jpre = v[1], mpre = v[2];
+    // unit starts (bit q <-> tile t0 + q); joinable prefix per tile into LDS
+    uint32_t startm = 0;
+    uint32_t first_cut = kClassChunk;
     {
-        uint32_t ms = size_med;
-        for (int d = kWave / 2; d >= 1; d >>= 1) ms += __shfl_xor(ms, d, kWave);
-        if (lane == 0) s_msz[w] = ms;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t an = 0, as = 0, am = 0;
-        for (int q = 0; q < kClassNT / kWave; ++q) {
-            const uint32_t vn = s_ws[0][q], vs = s_ws[1][q], vm = s_ws[2][q];
-            s_ws[0][q] = an;
-            s_ws[1][q] = as;
-            s_ws[2][q] = am;
-            an += vn;
-            as += vs;
-            am += vm;
+        uint32_t pre = wpre, jrun = jpre;
+        uint32_t pre_prev = wpre - ((brkm & 1u) ? 0u : n_of(0));
+#pragma unroll
+        for (int q = 0; q < kClassPer; ++q) {
+            const int tl = tl0 + q;
+            const bool brk = (brkm >> (q + 1)) & 1u, brk_prev = (brkm >> q) & 1u;
+            const bool st = !brk && (tl == 0 || brk_prev || pre / B != pre_prev / B || tl % TC == 0);
+            startm |= st ? 1u << q : 0u;
+            if ((brk || st) && first_cut == (uint32_t)kClassChunk) first_cut = tl;
+            s_j[tl] = (uint16_t)jrun;
+            jrun += (joinm >> q) & 1u;
+            pre_prev = pre;
+            pre += brk ? 0u : n_of(q + 1);
         }
-        s_ws[3][0] = an;
-        s_ws[3][1] = am;
-        uint32_t msum = 0;
-        for (int q = 0; q < kClassNT / kWave; ++q) msum += s_msz[q];
-        // both statistics in one 64-bit add (every workgroup adds to the same
-        // words, so the atomics serialise; the low word never carries)
-        const unsigned long long both = (unsigned long long)as | ((unsigned long long)msum << 32);
+        if (tid == kClassNT - 1) s_j[kClassChunk] = (uint16_t)jrun;
+    }
+    const uint32_t cutm = startm | (brkm >> 1);
+    // first cut after this thread's range: suffix minimum over later threads
+    uint32_t m = first_cut;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_down(m, d, kWave);
+        if (lane + d < kWave) m = t < m ? t : m;
+    }
+    if (lane == 0) s_fc[w] = m;
+    uint32_t after = __shfl_down(m, 1, kWave);
+    if (lane == kWave - 1) after = kClassChunk;
+    __syncthreads();
+    for (int q = w + 1; q < kClassNT / kWave; ++q) after = s_fc[q] < after ? s_fc[q] : after;
+    // a unit [start, next cut) is kept if it holds a joinable tile
+    uint32_t keepm = 0, nu = 0;
+    {
+        uint32_t next = after;
+#pragma unroll
+        for (int q = kClassPer - 1; q >= 0; --q) {
+            if (((startm >> q) & 1u) && s_j[next] != s_j[tl0 + q]) {
+                keepm |= 1u << q;
+                ++nu;
+            }
+            if ((cutm >> q) & 1u) next = (uint32_t)(tl0 + q);
+        }
+    }
+    uint32_t vu[4] = {nu, je, 0, 0}, totu[4];
+    block_excl4(vu, totu, s_ws);
+    const uint32_t total_units = totu[0], total_j = tot[1], total_med = tot[2];
+    if (tid == 0) {
+        // joinable tiles and units reserved with one 64-bit add, the entry
+        // statistics of the small and medium tiles added with another (every
+        // workgroup adds to the same words, so the atomics serialise; the low
+        // words never carry)
+        const unsigned long long add =
+            (unsigned long long)total_j | ((unsigned long long)total_units << 32);
+        const unsigned long long tu =
+            add ? atomicAdd((unsigned long long*)&a.ctr[kTilesWritten], add) : 0ull;
+        s_base[0] = (uint32_t)(tu >> 32);
+        s_base[1] = total_med ? atomicAdd(&a.ctr[kMedCount], total_med) : 0u;
+        const unsigned long long both = (unsigned long long)totu[1] | ((unsigned long long)tot[3] << 32);
         if (both) atomicAdd((unsigned long long*)&a.ctr[kSmallEntries], both);
     }
     __syncthreads();
-    const uint32_t total_small = s_ws[3][0], total_med = s_ws[3][1];
-    uint32_t rank = s_ws[0][w] + in - nsmall;
-    uint32_t spre = s_ws[1][w] + isz - size_small;
-    const uint32_t B = (uint32_t)a.unit_cap;
-#pragma unroll
-    for (int q = 0; q < kClassPer; ++q) {
-        if (cls[q] == 1) {
-            s_uidx[rank] = spre / B;
-            ++rank;
-            spre += ti[q].y + ti[q].w;
-        }
-    }
-    __syncthreads();
-    const uint32_t nunits = total_small ? s_uidx[total_small - 1] + 1 : 0u;
-    if (tid == 0) {
-        // small tiles and units reserved with one 64-bit add, as above
-        const unsigned long long add =
-            (unsigned long long)total_small | ((unsigned long long)nunits << 32);
-        const unsigned long long tu =
-            add ? atomicAdd((unsigned long long*)&a.ctr[kTilesWritten], add) : 0ull;
-        s_base[0] = (uint32_t)tu;
-        s_base[1] = (uint32_t)(tu >> 32);
-        s_base[2] = total_med ? atomicAdd(&a.ctr[kMedCount], total_med) : 0u;
-    }
-    __syncthreads();
-    const uint32_t tb = s_base[0], ub = s_base[1], mb = s_base[2];
-    if ((int64_t)tb + total_small > a.cap_tiles || (int64_t)ub + nunits > a.cap_units ||
-        (int64_t)mb + total_med > a.cap_med) {
+    const uint32_t ub = s_base[0], mb = s_base[1];
+    if ((int64_t)ub + total_units > a.cap_units || (int64_t)mb + total_med > a.cap_med) {
         if (tid == 0) atomicOr(&a.st->flags, kStatCapacity);
         return;
     }
-    rank = s_ws[0][w] + in - nsmall;
-    uint32_t mrank = s_ws[2][w] + im - nmed;
+    {
+        // unit records, last first (the end of a unit is the next cut)
+        uint32_t ui = ub + vu[0] + nu, next = after;
+#pragma unroll
+        for (int q = kClassPer - 1; q >= 0; --q) {
+            if ((keepm >> q) & 1u) {
+                const int64_t t = t0 + q, te = c0 + next;  // te <= C: tiles past the grid cut runs
+                const uint32_t rend = a.offR[te], send = a.offS[te];  // (cached: read by this block)
+                --ui;
+                a.uspan[ui] = make_uint4(oR[q + 1], rend - oR[q + 1], oS[q + 1], send - oS[q + 1]);
+                a.units[ui] = make_uint2((uint32_t)t, (uint32_t)(te - t));
+            }
+            if ((cutm >> q) & 1u) next = (uint32_t)(tl0 + q);
+        }
+    }
+    uint32_t mi = mb + mpre;
 #pragma unroll
     for (int q = 0; q < kClassPer; ++q) {
-        if (cls[q] == 2) {
-            if (a.axis_model) a.medt[mb + mrank] = (uint32_t)(t0 + q);
-            a.med[mb + mrank++] = ti[q];
-        }
-        if (cls[q] == 1) {
-            a.tinfo[tb + rank] = ti[q];
-            const uint32_t u = s_uidx[rank];
-            if (rank == 0 || s_uidx[rank - 1] != u) {
-                // first tile of unit u: count the tiles of the unit
-                uint32_t lo = rank, hi = total_small;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s_uidx[mid] == u) lo = mid;
-                    else hi = mid;
-                }
-                a.units[ub + u] = make_uint2(tb + rank, lo - rank + 1);
-            }
-            ++rank;
+        const int64_t t = t0 + q;
+        const uint32_t nr = oR[q + 2] - oR[q + 1], ns = oS[q + 2] - oS[q + 1];
+        if (t < a.C && nr && ns && nr + ns > SC && nr + ns <= (uint32_t)a.med_cap) {
+            if (a.axis_model) a.medt[mi] = (uint32_t)t;
+            a.med[mi++] = make_uint4(oR[q + 1], nr, oS[q + 1], ns);
         }
     }
 }
@@ -1649,76 +1676,33 @@ __global__ __launch_bounds__(kAxisNT) void k_axis_query(const uint32_t* __restri
 }
 
 // ---------------------------------------------------------------------------
-// k_lds_units: one workgroup per LDS unit.  MEDIUM = false: a batch of small
-// tiles; MEDIUM = true: one medium tile.  The grid is an upper bound on the
-// unit count; surplus workgroups exit at once.
+// k_lds_medium: one workgroup per medium tile (persistent workgroups, tiles
+// assigned round-robin; the record of the next tile is loaded while the
+// current one is sorted and swept).  The grid is an upper bound on the tile
+// count; surplus workgroups exit at once.
 // ---------------------------------------------------------------------------
-template <int NT, int Q, bool MEDIUM, int MODE>
-__global__ __launch_bounds__(NT) void k_lds_units(Args a) {
+template <int NT, int Q, int MODE>
+__global__ __launch_bounds__(NT) void k_lds_medium(Args a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    constexpr int TC = tc_for(NT * Q, !MEDIUM);
-    const uint32_t nu = MEDIUM ? min(a.ctr[kMedCount], (uint32_t)a.cap_med)
-                               : min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
+    constexpr int TC = tc_for(NT * Q, false);
+    const uint32_t nu = min(a.ctr[kMedCount], (uint32_t)a.cap_med);
     const LdsLayout L = carve(smem, NT, NT * Q, TC);
     Sink<MODE, true> sk = make_sink<MODE>(L);
-    // persistent workgroups, units assigned round-robin; the tile table of
-    // the next unit (and the unit record of the one after) is loaded while
-    // the current unit is sorted and swept
-    // table entries prefetched per thread (the rest are read when needed)
-    constexpr int kPf = TC > 2 ? ((TC + NT - 1) / NT < 3 ? (TC + NT - 1) / NT : 3) : 1;
-    const int tid = threadIdx.x;
     const uint32_t G = gridDim.x;
-    uint4 pf0 = make_uint4(0, 0, 0, 0), pf1 = pf0, pf2 = pf0;
-    uint2 ud = make_uint2(0, 0), ud_next = make_uint2(0, 0);
-    if (blockIdx.x < nu) {
-        if (MEDIUM) {
-            pf0 = a.med[blockIdx.x];
-        } else {
-            ud = a.units[blockIdx.x];
-            if (tid < (int)ud.y) pf0 = a.tinfo[ud.x + tid];
-            if (kPf > 1 && tid + NT < (int)ud.y) pf1 = a.tinfo[ud.x + tid + NT];
-            if (kPf > 2 && tid + 2 * NT < (int)ud.y) pf2 = a.tinfo[ud.x + tid + 2 * NT];
-            if (blockIdx.x + G < nu) ud_next = a.units[blockIdx.x + G];
-        }
-    }
+    uint4 pf = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x < nu) pf = a.med[blockIdx.x];
     for (uint32_t u = blockIdx.x; u < nu; u += G) {
-        const int64_t slot = MEDIUM ? a.base_med + u : (int64_t)u;
-        uint4 c0 = pf0;
-        const uint4 c1 = pf1, c2 = pf2;
-        bool swap = false;
-        if (MEDIUM) {  // sweeping axis of the tile in bit 31 of its R count
-            swap = (c0.y & kAxisBit) != 0;
-            c0.y &= ~kAxisBit;
-        }
-        const int c = MEDIUM ? 1 : (int)ud.y;
-        const uint4* tl = a.tinfo + ud.x;
-        // chunk j of the table: thread tid asks for its own tile k = tid + j * NT
-        auto tile_of = [&](int k, int j) -> uint4 {
-            if (MEDIUM) return c0;
-            return j == 0 ? c0 : (j == 1 && kPf > 1 ? c1 : (j == 2 && kPf > 2 ? c2 : tl[k]));
-        };
+        const int64_t slot = a.base_med + u;
+        uint4 c0 = pf;
+        const bool swap = (c0.y & kAxisBit) != 0;  // sweeping axis in bit 31 of the R count
+        c0.y &= ~kAxisBit;
         const uint32_t un = u + G;
         auto prefetch = [&]() {
-            if (un < nu) {
-                if (MEDIUM) {
-                    pf0 = a.med[un];
-                } else {
-                    const uint2 d = ud_next;
-                    if (tid < (int)d.y) pf0 = a.tinfo[d.x + tid];
-                    if (kPf > 1 && tid + NT < (int)d.y) pf1 = a.tinfo[d.x + tid + NT];
-                    if (kPf > 2 && tid + 2 * NT < (int)d.y) pf2 = a.tinfo[d.x + tid + 2 * NT];
-                    if (un + G < nu) ud = a.units[un + G];  // becomes ud_next below
-                }
-            }
+            if (un < nu) pf = a.med[un];
         };
         sk.begin(a, slot);
-        run_lds_unit<NT, Q, TC, MODE>(a, L, c, tile_of, prefetch, sk, swap);
+        run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int, int) { return c0; }, prefetch, sk, swap);
         sk.end(a, slot);
-        if (!MEDIUM) {
-            const uint2 t = ud_next;
-            ud_next = ud;
-            ud = t;
-        }
     }
     sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
 }
@@ -2103,51 +2087,45 @@ hipError_t launch_plain(const Args& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int NT, int Q, bool MEDIUM, int MODE>
-hipError_t launch_units(const Args& a, int64_t bound, int num_cus, hipStream_t s) {
+// grid = min(bound, resident workgroups): persistent workgroups
+template <class K>
+hipError_t launch_persistent(K* kern, int nt, size_t lds, int64_t bound, int num_cus, int& per_cu,
+                             const Args& a, hipStream_t s) {
     if (bound <= 0) return hipSuccess;
-    const size_t lds = lds_bytes(NT, NT * Q, tc_for(NT * Q, !MEDIUM));
-    static int per_cu = 0;  // resident workgroups per CU (computed once per instantiation)
     if (per_cu == 0) {
-        hipError_t e = set_lds(k_lds_units<NT, Q, MEDIUM, MODE>, lds);
+        hipError_t e = set_lds(kern, lds);
         if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lds_units<NT, Q, MEDIUM, MODE>,
-                                                         NT, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
     }
     const int64_t grid = std::min<int64_t>(bound, (int64_t)num_cus * per_cu);
-    hipLaunchKernelGGL((k_lds_units<NT, Q, MEDIUM, MODE>), dim3((unsigned)grid), dim3(NT), lds, s,
-                       a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(nt), lds, s, a);
     return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_waves(const Args& a, int64_t bound, int num_cus, hipStream_t s) {
-    if (bound <= 0) return hipSuccess;
-    const size_t lds = sizeof(WaveLds) * (kWNT / kWave);
+template <int NT, int Q, int MODE>
+hipError_t launch_medium(const Args& a, int64_t bound, int num_cus, hipStream_t s) {
+    static int per_cu = 0;  // resident workgroups per CU (computed once per instantiation)
+    return launch_persistent(k_lds_medium<NT, Q, MODE>, NT, lds_bytes(NT, NT * Q, tc_for(NT * Q, false)),
+                             bound, num_cus, per_cu, a, s);
+}
+
+template <int NT, int Q, int MODE>
+hipError_t launch_span(const Args& a, int64_t bound, int num_cus, hipStream_t s) {
     static int per_cu = 0;
-    if (per_cu == 0) {
-        hipError_t e = set_lds(k_wave_units<MODE>, lds);
-        if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave_units<MODE>, kWNT, lds);
-        if (e != hipSuccess) return e;
-        if (per_cu < 1) per_cu = 1;
-    }
-    const int64_t waves_per_block = kWNT / kWave;
-    const int64_t grid = std::min<int64_t>((bound + waves_per_block - 1) / waves_per_block,
-                                           (int64_t)num_cus * per_cu);
-    hipLaunchKernelGGL(k_wave_units<MODE>, dim3((unsigned)grid), dim3(kWNT), lds, s, a);
-    return hipGetLastError();
+    return launch_persistent(k_span_units<NT, Q, MODE>, NT, span_lds_bytes(NT, NT * Q), bound, num_cus,
+                             per_cu, a, s);
 }
 
+// small-tile units: block threads and entries per unit (see lds_unit_entries)
 template <int MODE>
 hipError_t launch_small(const Args& a, int block, int64_t bound, int num_cus, hipStream_t s) {
     switch (block) {
-        case 64: return launch_waves<MODE>(a, bound, num_cus, s);
-        case 128: return launch_units<128, 8, false, MODE>(a, bound, num_cus, s);
-        case 512: return launch_units<512, 4, false, MODE>(a, bound, num_cus, s);
-        default: return launch_units<256, 4, false, MODE>(a, bound, num_cus, s);
+        case 64: return launch_span<64, 4, MODE>(a, bound, num_cus, s);
+        case 128: return launch_span<128, 8, MODE>(a, bound, num_cus, s);
+        case 512: return launch_span<512, 4, MODE>(a, bound, num_cus, s);
+        default: return launch_span<256, 4, MODE>(a, bound, num_cus, s);
     }
 }
 
@@ -2167,8 +2145,8 @@ hipError_t join_pass(const Args& a0, const JoinParams& p, const JoinWork& w, hip
         e = launch_plain<256, 4, MODE>(a, s);
     } else {
         {
-            ProfRange pr(mode_tag(MODE, "k_lds_units_count", "k_lds_units_write",
-                                  "k_lds_units_single"), s);
+            ProfRange pr(mode_tag(MODE, "k_span_units_count", "k_span_units_write",
+                                  "k_span_units_single"), s);
             e = launch_small<MODE>(a, p.block, std::min<int64_t>(p.units_bound, w.cap_units),
                                    w.num_cus, s);
         }
@@ -2179,8 +2157,8 @@ hipError_t join_pass(const Args& a0, const JoinParams& p, const JoinWork& w, hip
             // medium tiles up to 1024 entries: a half-size slab, twice the
             // workgroups per CU
             const int64_t mb = std::min<int64_t>(p.med_bound, w.cap_med);
-            e = p.med_cap <= 1024 ? launch_units<256, 4, true, MODE>(a, mb, w.num_cus, s)
-                                  : launch_units<kMedNT, kMedE / kMedNT, true, MODE>(a, mb, w.num_cus, s);
+            e = p.med_cap <= 1024 ? launch_medium<256, 4, MODE>(a, mb, w.num_cus, s)
+                                  : launch_medium<kMedNT, kMedE / kMedNT, MODE>(a, mb, w.num_cus, s);
         }
     }
     if (e != hipSuccess) return e;
@@ -2193,9 +2171,11 @@ hipError_t join_pass(const Args& a0, const JoinParams& p, const JoinWork& w, hip
 
 }  // namespace
 
-int lds_unit_entries(int block) { return block == 64 ? kWE : (block == 128 ? 1024 : block * 4); }
+int lds_unit_entries(int block) { return block == 128 ? 1024 : block * 4; }
+int lds_unit_tiles(int block) { return block - 1; }
 int lds_medium_entries() { return kMedE; }
 int64_t classify_blocks(int64_t C) { return (C + kClassChunk - 1) / kClassChunk; }
+int64_t classify_chunk_tiles() { return kClassChunk; }
 
 // Slots of the per-unit count array: small units, medium tiles, dense units
 // (tuned) or one per tile plus dense units (plain).
@@ -2218,12 +2198,12 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     a.med_cap = p.med_cap;
     a.split_tau = p.split_tau;
     a.plain = p.plain ? 1 : 0;
-    a.tinfo = w.tinfo;
+    a.unit_tiles = p.unit_tiles;
+    a.uspan = w.uspan;
     a.units = w.units;
     a.med = w.med;
     a.dense = w.dense;
     a.dprefix = w.dense_unit_prefix;
-    a.cap_tiles = w.cap_tiles;
     a.cap_units = w.cap_units;
     a.cap_med = w.cap_med;
     a.cap_dense = w.cap_dense;

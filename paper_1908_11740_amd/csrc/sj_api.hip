@@ -20,8 +20,10 @@ struct sj_part : public sj::Part {};
 namespace sj {
 
 int lds_unit_entries(int block);
+int lds_unit_tiles(int block);
 int lds_medium_entries();
 int64_t classify_blocks(int64_t C);
+int64_t classify_chunk_tiles();
 
 namespace {
 
@@ -169,11 +171,12 @@ JoinParams join_params(const sj_grid& g, bool count_only) {
     p.C = (int64_t)g.k * g.k;
     p.plain = (g.flags & SJ_PLAIN) != 0;
     p.count_only = count_only;
-    p.block = 64;  // wave units for the small tiles
+    p.block = 256;  // span units of the small tiles
     const int E = lds_unit_entries(p.block);
     const int E_plain = lds_unit_entries(256);  // LDS entries of the plain per-tile kernel
-    p.small_cap = p.plain ? E_plain : E / 2;
+    p.small_cap = p.plain ? E_plain : E / 4;
     p.unit_cap = p.plain ? E_plain : E - p.small_cap;
+    p.unit_tiles = lds_unit_tiles(p.block);
     p.med_cap = p.plain ? E_plain : lds_medium_entries();
     p.split_tau = g.split_tau > 0 ? g.split_tau : 256;
     if (p.plain || g.split_tau == INT32_MAX) p.split_tau = INT32_MAX;
@@ -191,6 +194,7 @@ void apply_tuning(JoinParams& p, const sj_grid& g, const sj_tuning& t) {
     const int E = lds_unit_entries(p.block);
     p.small_cap = std::min(t.small_cap, E / 2 + E / 4);
     p.unit_cap = E - p.small_cap;
+    p.unit_tiles = lds_unit_tiles(p.block);
     p.med_cap = std::max(p.small_cap, std::min(t.med_cap, lds_medium_entries()));
     if (g.split_tau == 0 && t.split_tau > 0) p.split_tau = t.split_tau;
 }
@@ -209,13 +213,19 @@ sj_status join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_
                        int64_t capacity) {
     p.C = C;
     const int64_t active = std::min<int64_t>(p.C, std::min(mR, mS)) + 1;
-    p.units_bound = std::min<int64_t>(active, (mR + mS) / p.unit_cap + classify_blocks(p.C) + 1);
+    // span units per classification chunk: one, plus one per crossing of a
+    // multiple of unit_cap, per unit_tiles tiles and per tile that cuts a run
+    // (more than small_cap entries)
+    const int64_t blocks = classify_blocks(p.C);
+    p.units_bound = std::min<int64_t>(
+        active, (mR + mS) / p.unit_cap + (mR + mS) / (p.small_cap + 1) +
+                    blocks * (classify_chunk_tiles() / p.unit_tiles + 2) + 1);
     p.med_bound = std::min<int64_t>(active, (mR + mS) / (p.small_cap + 1) + 1);
     const int64_t ndense = (mR + mS) / (p.med_cap + 1) + 2;
     hipError_t e = hipSuccess;
     if (!p.plain) {
-        if ((e = grow(w.tinfo, w.cap_tiles, active)) != hipSuccess) return from_hip(e);
         if ((e = grow(w.units, w.cap_units, p.units_bound)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.uspan, w.cap_uspan, w.cap_units)) != hipSuccess) return from_hip(e);
         if ((e = grow(w.med, w.cap_med, p.med_bound)) != hipSuccess) return from_hip(e);
         if ((e = grow(w.medt, w.cap_medt, w.cap_med)) != hipSuccess) return from_hip(e);
     }

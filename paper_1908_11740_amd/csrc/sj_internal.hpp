@@ -135,7 +135,8 @@ struct JoinParams {
     int K;
     int64_t C;
     int split_tau;   // pivots per dense unit
-    int unit_cap;    // LDS unit entry budget
+    int unit_cap;    // span units are cut where their running entry count crosses a multiple of this
+    int unit_tiles;  // ... and hold at most this many tiles
     int small_cap;   // tiles with at most this many entries are batched
     int med_cap;     // tiles above small_cap and up to med_cap: one per workgroup
     int block;       // threads per workgroup for the small-unit kernel
@@ -153,8 +154,9 @@ struct JoinParams {
 struct JoinWork {
     int device = 0;
     // classification outputs
-    uint4* tinfo = nullptr;         // [cap_tiles] small-tile segments, grouped by unit
-    uint2* units = nullptr;         // [cap_units] (first index into tinfo, count)
+    uint4* uspan = nullptr;         // [cap_uspan] small units: (R start, NR, S start, NS)
+    int64_t cap_uspan = 0;
+    uint2* units = nullptr;         // [cap_units] small units: (first blocked tile, tile count)
     uint4* med = nullptr;           // [cap_med] medium-tile segments
     int64_t cap_med = 0;
     uint32_t* medt = nullptr;       // [cap_medt] blocked tile index of each medium tile
@@ -164,7 +166,7 @@ struct JoinWork {
     uint32_t* dgrp = nullptr;       // [cap_dgrp] GBDA class group starts, 10 per dense tile
     uint32_t* dmj = nullptr;        // [cap_dmj] GBDA mini-join unit prefix, 10 per dense tile
     int64_t cap_dgrp = 0, cap_dmj = 0;
-    int64_t cap_tiles = 0, cap_units = 0, cap_dense = 0, cap_prefix = 0, cap_dunits = 0;
+    int64_t cap_units = 0, cap_dense = 0, cap_prefix = 0, cap_dunits = 0;
     uint32_t* ucnt = nullptr;       // per-unit pair counts -> output offsets
     int64_t cap_ucnt = 0;
     uint32_t* scan_tmp = nullptr;   // block sums of the pair-count scan
