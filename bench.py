@@ -10,8 +10,13 @@ line on stdout; progress goes to stderr.
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload skewed10m]
 
 The tuned run uses the learned picker when its weights are present (else the
-rule) with the batched / split schedule; --compare (default) also times the
-baseline: statistics-rule K with the plain one-workgroup-per-tile schedule.
+rule) with the batched / split schedule; --compare (default) also times two
+baselines: the statistics-rule K with the same autotuned schedule family
+(rule_tuned: isolates what the learned grid choice gains) and the
+statistics-rule K with the plain one-workgroup-per-tile schedule.  Schedules
+come from the autotuner cache file (--tune-cache) when it holds the class,
+so that separate runs (this one and its profiling run) use the same kernels;
+--save-tune writes the cache back after tuning.
 """
 import argparse
 import json
@@ -51,6 +56,9 @@ def parse():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--two-pass", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_11740_amd", "tune_cache.txt"),
+                    help="autotuner cache file read before tuning (a class it holds is not re-tuned)")
+    ap.add_argument("--save-tune", action="store_true", help="write the autotuner cache file afterwards")
     ap.add_argument("--stripes", action="store_true",
                     help="one-dimensional partitioning: K vertical stripes swept along y")
     ap.add_argument("--sweep-x", action="store_true",
@@ -378,6 +386,8 @@ def main():
     from paper_1908_11740_amd import sj
 
     torch.cuda.set_device(0)
+    if not args.no_tune and os.path.exists(args.tune_cache):
+        log("autotuner cache:", sj.tune_load(args.tune_cache), "entries from", args.tune_cache)
     if args.workload == "batch256":
         return bench_batch(args, pk, sj, torch)
     if args.workload == "distance10m":
@@ -393,13 +403,14 @@ def main():
     state = {"PR": None, "PS": None, "pairs": 0, "K": 0, "tau": 0, "info": None,
              "out": torch.empty((1 << 20, 2), dtype=torch.int32, device="cuda")}
 
-    def step(plain):
+    def step(mode):
+        plain = mode == "plain"
         stripes = ((sj.SJ_STRIPES if args.stripes else 0) | (sj.SJ_SWEEP_X if args.sweep_x else 0) |
                    (sj.SJ_GBDA if args.gbda else 0) | (sj.SJ_SORTED_OUTPUT if args.sorted else 0))
         if args.k:
             K, tau = args.k, args.split_tau
         else:
-            fl = sj.SJ_RULE_ONLY if (plain or not use_learned) else 0
+            fl = sj.SJ_RULE_ONLY if (mode != "tuned" or not use_learned) else 0
             K, tau, state["info"] = sj.choose_grid(Rd, Sd, split_tau=args.split_tau,
                                                    flags=fl | stripes)
         flags = stripes | (sj.SJ_PLAIN if plain else (sj.SJ_TWO_PASS if args.two_pass else 0))
@@ -415,17 +426,23 @@ def main():
             st, n = sj.join_into(state["PR"], state["PS"], state["out"])
         state["pairs"] = n
 
-    def timed(plain):
+    def timed(mode):
+        plain = mode == "plain"
         for _ in range(max(1, args.warmup)):
-            step(plain)
+            step(mode)
         torch.cuda.synchronize()
         state["tuning"] = None
         if not plain and not args.no_tune:
             # autotuner: schedule for this workload class, cached by the library
-            state["tuning"] = sj.tune(state["PR"], state["PS"],
-                                      None if args.count else state["out"], reps=2)
-            log("autotuned", state["tuning"])
-            step(plain)
+            # (and read from the cache file when it holds the class)
+            cached = sj.tune_lookup(state["PR"], state["PS"], count_only=args.count)
+            if cached is not None:
+                state["tuning"] = dict(cached, source="cache file")
+            else:
+                state["tuning"] = sj.tune(state["PR"], state["PS"],
+                                          None if args.count else state["out"], reps=2)
+            log("autotuned", mode, state["tuning"])
+            step(mode)
             torch.cuda.synchronize()
         # unprofiled: the reported time
         times = []
@@ -435,7 +452,7 @@ def main():
                 flush.fill_(1.0)
                 torch.cuda.synchronize()
             t0 = time.perf_counter()
-            step(plain)
+            step(mode)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         del flush
@@ -443,17 +460,19 @@ def main():
         # the same steps again with per-kernel HIP events on the launch stream
         sj.prof_enable(True)
         for _ in range(args.steps):
-            step(plain)
+            step(mode)
         torch.cuda.synchronize()
         kern = sj.prof_collect()
         sj.prof_enable(False)
         return ms, statistics.median(times) * 1e3, kern
 
     res = {}
-    modes = ["plain"] if args.plain else (["tuned"] + ([] if args.no_compare else ["plain"]))
+    modes = ["plain"] if args.plain else (
+        ["tuned"] + ([] if args.no_compare else (["rule_tuned"] if use_learned and not args.k else []) +
+                     ["plain"]))
     for mode in modes:
         log("timing", mode)
-        ms, med, kern = timed(mode == "plain")
+        ms, med, kern = timed(mode)
         _, mR, _ = state["PR"].info()
         _, mS, _ = state["PS"].info()
         m1R, _ = state["PR"].stats()
@@ -548,6 +567,15 @@ def main():
         "join_stats": r["stats"],
         "cpu_baseline": cpu,
     }
+    if "rule_tuned" in res and main_mode == "tuned":
+        b = res["rule_tuned"]
+        rec["rule_tuned_baseline"] = {"ms_per_step": round(b["ms"], 4), "grid_k": b["K"],
+                                      "split_tau": b["tau"], "n_pairs": int(b["P"]),
+                                      "autotuned": b["tuning"]}
+        rec["speedup_vs_rule_tuned"] = round(b["ms"] / ms, 3)
+    if not args.no_tune and args.save_tune:
+        sj.tune_save(args.tune_cache)
+        log("autotuner cache written to", args.tune_cache)
     if "plain" in res and main_mode == "tuned":
         b = res["plain"]
         rec["plain_rule_baseline"] = {"ms_per_step": round(b["ms"], 4), "grid_k": b["K"],

@@ -191,7 +191,7 @@ const char* sj_last_error(void);
  * Autotuner.  sj_tune times the join of (R, S) -- into `out` (capacity
  * pairs), or count-only if out is NULL -- `reps` times for every candidate
  * schedule: workgroup size of the small-tile kernel (64 = one wavefront per
- * LDS unit, 128, 256, 512), the entry cap of a small tile (E/4 or E/2 of
+ * span unit, 128, 256, 512), the entry cap of a small tile (E/4 or E/2 of
  * the unit's LDS slab E), the entry cap of a medium tile (1024, 2048) and,
  * unless the grid fixes it, the split threshold (128, 256, 1024).  The
  * fastest is cached for (device, K, log2 |entries| of R and S, mode) and
@@ -214,6 +214,20 @@ void sj_tune_clear(void);
  * block in {64, 128, 256, 512}, caps >= 2; clamped to the kernel's LDS slab. */
 sj_status sj_tune_set(const sj_part* R, const sj_part* S, int32_t count_only,
                       const sj_tuning* t);
+/* Persist the autotuner cache, so that separate processes (a benchmark and
+ * its profiling run) join with the same schedule.  sj_tune_save writes every
+ * cached entry as one text line: the device's architecture name (e.g.
+ * gfx950), K, log2 |entries| of R and of S, the mode (bit 0 count only,
+ * bit 1 distance join) and the schedule.  sj_tune_load adds the entries of
+ * a file whose architecture name matches the current device (others are
+ * skipped) to the cache, replacing entries of the same class; *n_loaded (may
+ * be NULL) receives their count.  Errors: SJ_ERR_ARG for a NULL path, a
+ * file that cannot be opened or a malformed line (nothing is added then). */
+sj_status sj_tune_save(const char* path);
+/* The cached schedule for the class of (R, S) in *t (host): SJ_OK if the
+ * cache holds one, SJ_ERR_ARG if not (or for NULL arguments). */
+sj_status sj_tune_lookup(const sj_part* R, const sj_part* S, int32_t count_only, sj_tuning* t);
+sj_status sj_tune_load(const char* path, int32_t* n_loaded);
 
 /*
  * Many independent joins in one replayable launch.  Joins, like tiles, are

@@ -137,6 +137,14 @@ sj_status current_device(int* dev) {
     return SJ_OK;
 }
 
+// Architecture name of a device without feature suffixes ("gfx950").
+void arch_name(const hipDeviceProp_t& prop, char* out, size_t cap) {
+    size_t i = 0;
+    for (; i + 1 < cap && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+        out[i] = prop.gcnArchName[i];
+    out[i] = '\0';
+}
+
 hipError_t read_status(const DevStatus* dst, DevStatus* host, hipStream_t s) {
     hipError_t e = hipMemcpyAsync(host, dst, sizeof(DevStatus), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
@@ -591,6 +599,75 @@ sj_status sj_tune_set(const sj_part* R, const sj_part* S, int32_t count_only,
 void sj_tune_clear(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_tune.clear();
+}
+
+sj_status sj_tune_lookup(const sj_part* R, const sj_part* S, int32_t count_only, sj_tuning* t) {
+    if (!R || !S || !t) return SJ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune.find(tune_key(R->device, R->grid, R->m, S->m, count_only != 0));
+    if (it == g_tune.end()) return SJ_ERR_ARG;
+    *t = it->second;
+    return SJ_OK;
+}
+
+sj_status sj_tune_save(const char* path) {
+    if (!path) return SJ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return SJ_ERR_ARG;
+    std::fprintf(f, "# arch k log2_mR log2_mS mode block small_cap med_cap split_tau ms\n");
+    for (const auto& kv : g_tune) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, kv.first.dev) != hipSuccess) continue;
+        char arch[64];
+        arch_name(prop, arch, sizeof(arch));
+        const sj_tuning& t = kv.second;
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.6f\n", arch, kv.first.k, kv.first.lr,
+                     kv.first.ls, kv.first.count_only, t.block, t.small_cap, t.med_cap,
+                     t.split_tau, t.ms);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? SJ_OK : SJ_ERR_ARG;
+}
+
+sj_status sj_tune_load(const char* path, int32_t* n_loaded) {
+    if (n_loaded) *n_loaded = 0;
+    if (!path) return SJ_ERR_ARG;
+    int dev = 0;
+    if (current_device(&dev) != SJ_OK) return SJ_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return SJ_ERR_DEVICE;
+    char mine[64];
+    arch_name(prop, mine, sizeof(mine));
+    FILE* f = std::fopen(path, "r");
+    if (!f) return SJ_ERR_ARG;
+    std::vector<std::pair<TuneKey, sj_tuning>> got;
+    char line[512];
+    bool bad = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char arch[64];
+        TuneKey key{dev, 0, 0, 0, 0};
+        sj_tuning t{};
+        if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %lf", arch, &key.k, &key.lr, &key.ls,
+                        &key.count_only, &t.block, &t.small_cap, &t.med_cap, &t.split_tau,
+                        &t.ms) != 10 ||
+            (t.block != 64 && t.block != 128 && t.block != 256 && t.block != 512) ||
+            t.small_cap < 2 || t.med_cap < 2 || t.split_tau < 0 || key.k < 1 || key.k > SJ_K_MAX) {
+            bad = true;
+            break;
+        }
+        if (std::strcmp(arch, mine) == 0) got.emplace_back(key, t);
+    }
+    std::fclose(f);
+    if (bad) {
+        snprintf(g_err, sizeof(g_err), "sj_tune_load: malformed line in %s", path);
+        return SJ_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : got) g_tune[kv.first] = kv.second;
+    if (n_loaded) *n_loaded = (int32_t)got.size();
+    return SJ_OK;
 }
 
 sj_status sj_join_count(const sj_part* R, const sj_part* S, int64_t* n_pairs, void* stream) {

@@ -116,6 +116,12 @@ def lib():
         L.sj_tune_set.restype = ctypes.c_int
         L.sj_tune_clear.argtypes = []
         L.sj_tune_clear.restype = None
+        L.sj_tune_lookup.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(Tuning)]
+        L.sj_tune_lookup.restype = ctypes.c_int
+        L.sj_tune_save.argtypes = [ctypes.c_char_p]
+        L.sj_tune_save.restype = ctypes.c_int
+        L.sj_tune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
+        L.sj_tune_load.restype = ctypes.c_int
         L.sj_batch_create.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(vp), vp]
         L.sj_batch_run.argtypes = [vp, vp, vp]
@@ -304,6 +310,28 @@ def tune_set(R, S, block, small_cap, med_cap, split_tau=0, count_only=False):
     t = Tuning(block, small_cap, med_cap, split_tau, 0.0)
     _check(lib().sj_tune_set(R.handle, S.handle, 1 if count_only else 0, ctypes.byref(t)),
            "sj_tune_set")
+
+
+def tune_lookup(R, S, count_only=False):
+    """The cached schedule for the class of (R, S) (dict), or None."""
+    t = Tuning()
+    if lib().sj_tune_lookup(R.handle, S.handle, 1 if count_only else 0, ctypes.byref(t)) != SJ_OK:
+        return None
+    return {"block": t.block, "small_cap": t.small_cap, "med_cap": t.med_cap,
+            "split_tau": t.split_tau, "ms": t.ms}
+
+
+def tune_save(path):
+    """sj_tune_save: write the autotuner cache to a text file."""
+    _check(lib().sj_tune_save(os.fsencode(path)), "sj_tune_save")
+
+
+def tune_load(path):
+    """sj_tune_load: add the entries of a cache file for this device's
+    architecture; returns how many were loaded."""
+    n = ctypes.c_int32(0)
+    _check(lib().sj_tune_load(os.fsencode(path), ctypes.byref(n)), "sj_tune_load")
+    return int(n.value)
 
 
 def tune_clear():

@@ -74,3 +74,39 @@ def test_every_candidate_schedule_is_exact():
     st_ = sj.last_join_stats()
     assert st_["n_pairs"] == len(ref)
     sj.tune_clear()
+
+
+def test_tune_cache_save_and_load(tmp_path):
+    """The cache written by sj_tune_save comes back with sj_tune_load on this
+    device's architecture and drives the join (same schedule, exact pairs);
+    entries of another architecture and malformed files are handled."""
+    R, S, K = datagen.small_case()
+    ref = oracle.pbsm(R, S, 64)
+    PR, PS = sj.partition(to_dev(R), K), sj.partition(to_dev(S), K)
+    out = torch.empty((len(ref) + 10, 2), dtype=torch.int32, device="cuda")
+    sj.tune_clear()
+    sj.tune_set(PR, PS, 128, 256, 1024, 128)
+    path = tmp_path / "tune.txt"
+    sj.tune_save(path)
+    lines = [l for l in path.read_text().splitlines() if not l.startswith("#")]
+    assert len(lines) == 1
+    arch, k, lr, ls, mode, blk, sc, mc, tau, ms = lines[0].split()
+    assert arch.startswith("gfx") and int(k) == K and int(mode) == 0
+    assert (int(blk), int(sc), int(mc), int(tau)) == (128, 256, 1024, 128)
+    sj.tune_clear()
+    # another architecture's line is skipped, ours is loaded
+    path.write_text(path.read_text() + lines[0].replace(arch, "gfx000", 1) + "\n")
+    assert sj.tune_lookup(PR, PS) is None
+    assert sj.tune_load(path) == 1
+    assert sj.tune_lookup(PR, PS)["small_cap"] == 256
+    assert sj.tune_lookup(PR, PS, count_only=True) is None
+    st, n = sj.join_into(PR, PS, out)
+    assert st == sj.SJ_OK and np.array_equal(sort_pairs(out[:n].cpu().numpy()), ref)
+    assert sj.last_join_stats()["small_cap"] == 256
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 12 x\n")
+    with pytest.raises(sj.SjError):
+        sj.tune_load(bad)
+    with pytest.raises(sj.SjError):
+        sj.tune_load(tmp_path / "missing.txt")
+    sj.tune_clear()
