@@ -35,8 +35,6 @@ def _load():
         i64 = ctypes.c_int64
         lib.oracle_bruteforce.argtypes = [f32p, i64, f32p, i64, i32pp]
         lib.oracle_bruteforce.restype = i64
-        lib.oracle_bruteforce_count.argtypes = [f32p, i64, f32p, i64]
-        lib.oracle_bruteforce_count.restype = i64
         lib.oracle_sweep.argtypes = [f32p, i64, f32p, i64, i32pp]
         lib.oracle_sweep.restype = i64
         lib.oracle_pbsm.argtypes = [f32p, i64, f32p, i64, ctypes.c_int, f32p, ctypes.c_int,
@@ -91,11 +89,6 @@ def bruteforce(R, S):
     out = ctypes.POINTER(ctypes.c_int32)()
     n = _load().oracle_bruteforce(_fp(R), len(R), _fp(S), len(S), ctypes.byref(out))
     return _take(n, out)
-
-
-def bruteforce_count(R, S):
-    R, S = _rects(R), _rects(S)
-    return int(_load().oracle_bruteforce_count(_fp(R), len(R), _fp(S), len(S)))
 
 
 def sweep(R, S):

@@ -89,14 +89,6 @@ int64_t oracle_bruteforce(const float *R, int64_t nR, const float *S, int64_t nS
     return p.n;
 }
 
-/* Brute-force count only: for inputs whose pair list would not fit. */
-int64_t oracle_bruteforce_count(const float *R, int64_t nR, const float *S, int64_t nS) {
-    int64_t c = 0;
-    for (int64_t i = 0; i < nR; i++)
-        for (int64_t j = 0; j < nS; j++) c += intersects(R + 4 * i, S + 4 * j);
-    return c;
-}
-
 /* ------------------------------------------------------------------ */
 /* Algorithm 1: forward-scan plane sweep over two lists of entries.      */
 /* ------------------------------------------------------------------ */
@@ -143,26 +135,43 @@ static int y_intersects(const entry *r, const entry *s) {
     return r->yl <= s->yu && s->yl <= r->yu;
 }
 
-/* Algorithm 1 over Rl[0..nr) and Sl[0..ns), both already sorted by x_l. */
+/* First index in A[lo..hi) whose x_l is > v (strict = 1) or >= v (strict =
+ * 0); hi if none.  A is sorted by x_l. */
+static int64_t first_beyond(const entry *A, int64_t lo, int64_t hi, float v, int strict) {
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        int before = strict ? (A[mid].xl <= v) : (A[mid].xl < v);
+        if (before) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* Algorithm 1 (Sec. 2.1) over two lists sorted by x_l.  The sweep visits
+ * the elements of both lists in x_l order (on equal x_l an element of S
+ * before one of R) and, at each element, scans the elements of the other
+ * list that come later in that order, as long as their x_l does not exceed
+ * its x_u.  So the candidates of an r are the s with r.x_l < s.x_l <= r.x_u,
+ * those of an s the r with s.x_l <= r.x_l <= s.x_u, and every pair whose
+ * x-intervals meet is a candidate exactly once.  Each candidate gets the
+ * closed y-test and, in a tile, the reference-point test of Eq. (1). */
 static int sweep_sorted(const entry *Rl, int64_t nr, const entry *Sl, int64_t ns,
                         const tile_ctx *ctx, plist *out) {
-    int64_t i = 0, j = 0;
-    while (i < nr && j < ns) {
-        if (Rl[i].xl < Sl[j].xl) {
-            /* r is the pivot: scan S forward from s while s'.x_l <= r.x_u */
-            const entry *r = &Rl[i];
-            for (int64_t k = j; k < ns && r->xu >= Sl[k].xl; k++)
-                if (y_intersects(r, &Sl[k]) && reference_point_in_tile(r, &Sl[k], ctx))
-                    if (plist_push(out, r->id, Sl[k].id)) return -1;
-            i++;
-        } else {
-            /* s is the pivot: scan R forward from r while r'.x_l <= s.x_u */
-            const entry *s = &Sl[j];
-            for (int64_t k = i; k < nr && s->xu >= Rl[k].xl; k++)
-                if (y_intersects(&Rl[k], s) && reference_point_in_tile(&Rl[k], s, ctx))
-                    if (plist_push(out, Rl[k].id, s->id)) return -1;
-            j++;
-        }
+    for (int64_t i = 0; i < nr; i++) {
+        const entry *r = &Rl[i];
+        int64_t from = first_beyond(Sl, 0, ns, r->xl, 1);
+        int64_t to = first_beyond(Sl, from, ns, r->xu, 1);
+        for (int64_t k = from; k < to; k++)
+            if (y_intersects(r, &Sl[k]) && reference_point_in_tile(r, &Sl[k], ctx))
+                if (plist_push(out, r->id, Sl[k].id)) return -1;
+    }
+    for (int64_t j = 0; j < ns; j++) {
+        const entry *s = &Sl[j];
+        int64_t from = first_beyond(Rl, 0, nr, s->xl, 0);
+        int64_t to = first_beyond(Rl, from, nr, s->xu, 1);
+        for (int64_t k = from; k < to; k++)
+            if (y_intersects(&Rl[k], s) && reference_point_in_tile(&Rl[k], s, ctx))
+                if (plist_push(out, Rl[k].id, s->id)) return -1;
     }
     return 0;
 }

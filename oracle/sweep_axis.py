@@ -22,9 +22,13 @@ Readings where the paper leaves details open (the same in the GPU library):
 * k: 1000 for tiles large against the rectangles, else the number of times
   the tile's extent exceeds the mean extent of the rectangles.  Here the
   mean extent (w + h) / 2 is taken over the tile's sampled rectangles (R and
-  S), in cell units, each of w, h clipped to 2 cells and summed in fixed
-  point (2^-30 of a cell, integers, so the sum does not depend on order);
+  S), in cell units (a tile is one cell), summed exactly as integers in
+  units of 2^-30 of a cell (each w and h truncated to that unit), so the sum
+  does not depend on the order of the tile's list;
   k = clamp(floor(2 n 2^30 / sum), 1, 1000), and 1000 when the sum is 0.
+  An extent is capped at 2^32 cells before the sum: one such extent makes
+  the sum at least 2^62 > 2 n 2^30 for any n < 2^31, so k = 1 with or
+  without the cap, and the cap keeps the GPU's fixed-width sums finite.
 * Divisions: the division of a coordinate v in tile column t is
   clamp(floor(fl(fl(u - t) * k)), 0, k - 1) with u = fl(fl(v - x0) * sx),
   the float32 cell coordinate of the grid's cell function (sx = float32(K) /
@@ -47,10 +51,14 @@ def grid_scales(K, domain=None):
     return x0, y0, f32(f32(K) / w), f32(f32(K) / h)
 
 
+CAP = 2.0 ** 32  # cells; does not change k (see above)
+
+
 def _fixed(ext):
-    """Extent (float32, cell units) clipped to 2 cells, in units of 2^-30."""
-    e = np.minimum(np.asarray(ext, dtype=np.float64), 2.0)
-    return np.floor(e * FIX).astype(np.int64)
+    """Extents (float32, cell units) in units of 2^-30 of a cell, as Python
+    integers (exact sums of any size)."""
+    e = np.minimum(np.asarray(ext, dtype=np.float64), CAP)
+    return [int(v) for v in np.floor(e * FIX)]
 
 
 def buckets(lo, hi, origin, scale, t, k):
@@ -81,7 +89,7 @@ def tile_model(Rt, St, tx, ty, K, domain=None):
     A = np.concatenate([Rt, St])
     wc = f32(f32(A[:, 2] - A[:, 0]) * sx)
     hc = f32(f32(A[:, 3] - A[:, 1]) * sy)
-    tot = int(_fixed(wc).sum() + _fixed(hc).sum())
+    tot = sum(_fixed(wc)) + sum(_fixed(hc))
     n = len(A)
     k = K_BUCKETS if tot == 0 else int(min(max((2 * n * FIX) // tot, 1), K_BUCKETS))
     I = []

@@ -1438,8 +1438,10 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
 // workgroup of kAxisNT threads.  Sample: the entries whose rectangle index is
 // a multiple of phi = 100.  k divisions per tile extent, k = clamp(floor(
 // tile extent / mean sampled extent), 1, 1000), the mean of (w + h) / 2 in
-// cell units from fixed-point sums (2^-30 of a cell, w and h clipped to 2
-// cells), so it does not depend on the order of the tile's list.  Per axis
+// cell units from exact integer sums in units of 2^-30 of a cell (128-bit),
+// so it does not depend on the order of the tile's list.  An extent is
+// capped at 2^32 cells first: one such extent makes the sum >= 2^62, more
+// than 2 n 2^30 for any sample size n < 2^31, so k = 1 with or without it.  Per axis
 // and side a histogram counts the sampled rectangles meeting each division
 // (difference array in LDS, then a prefix sum); I = sum_i H_R[i] * H_S[i].
 // ---------------------------------------------------------------------------
@@ -1448,10 +1450,13 @@ constexpr uint32_t kAxisPhi = 100;
 constexpr int kAxisKMax = 1000;
 constexpr int kAxisPer = (kAxisKMax + kAxisNT - 1) / kAxisNT;  // divisions per thread
 
+typedef unsigned __int128 u128;
+
 struct AxisLds {
     int hist[4][kAxisKMax + 1];  // difference arrays: R x, R y, S x, S y
     int wsum[kAxisNT / kWave][4];
     unsigned long long red[kAxisNT / kWave][2];
+    u128 ext[kAxisNT / kWave];
     uint32_t cnt[kAxisNT / kWave][2];
 };
 
@@ -1460,10 +1465,17 @@ struct AxisOut {
     unsigned long long ix, iy;
 };
 
-// extent hi - lo in cell units, clipped to 2 cells, in units of 2^-30 cell
+// extent hi - lo in cell units, capped at 2^32 cells, in units of 2^-30 cell
+// (< 2^63: the scaling by 2^30 is exact, the conversion truncates = floor)
 __device__ __forceinline__ unsigned long long fixed_extent(float lo, float hi, float scale) {
-    const float e = fminf(__fmul_rn(__fsub_rn(hi, lo), scale), 2.0f);
-    return (unsigned long long)__fmul_rn(e, 1073741824.0f);  // exact scaling; truncation = floor
+    const float e = fminf(__fmul_rn(__fsub_rn(hi, lo), scale), 4294967296.0f);
+    return (unsigned long long)__fmul_rn(e, 1073741824.0f);
+}
+
+__device__ __forceinline__ u128 shfl_xor_u128(u128 v, int d) {
+    const unsigned long long lo = __shfl_xor((unsigned long long)v, d, kWave);
+    const unsigned long long hi = __shfl_xor((unsigned long long)(v >> 64), d, kWave);
+    return ((u128)hi << 64) | lo;
 }
 
 // division of coordinate v in tile column t
@@ -1490,13 +1502,13 @@ __device__ AxisOut axis_eval(const float4* __restrict__ bR, const uint32_t* __re
     const uint32_t n = nr + ns;
     // A. sample sizes and fixed-point extent sum
     uint32_t cR = 0, cS = 0;
-    unsigned long long ext = 0;
+    u128 ext = 0;
     for (uint32_t i = tid; i < n; i += kAxisNT) {
         const bool isR = i < nr;
         const uint32_t j = isR ? i : i - nr;
         if (((isR ? iR : iS)[j] & kIdMask) % kAxisPhi == 0u) {
             const float4 b = (isR ? bR : bS)[j];
-            ext += fixed_extent(b.x, b.z, g.sx) + fixed_extent(b.y, b.w, g.sy);
+            ext += (u128)fixed_extent(b.x, b.z, g.sx) + (u128)fixed_extent(b.y, b.w, g.sy);
             if (isR) ++cR;
             else ++cS;
         }
@@ -1504,28 +1516,28 @@ __device__ AxisOut axis_eval(const float4* __restrict__ bR, const uint32_t* __re
     for (int d = kWave / 2; d >= 1; d >>= 1) {
         cR += __shfl_xor(cR, d, kWave);
         cS += __shfl_xor(cS, d, kWave);
-        ext += __shfl_xor(ext, d, kWave);
+        ext += shfl_xor_u128(ext, d);
     }
     if (lane == 0) {
         L.cnt[w][0] = cR;
         L.cnt[w][1] = cS;
-        L.red[w][0] = ext;
+        L.ext[w] = ext;
     }
     __syncthreads();
     uint32_t nRs = 0, nSs = 0;
-    unsigned long long tot = 0;
+    u128 tot = 0;
     for (int q = 0; q < NW; ++q) {
         nRs += L.cnt[q][0];
         nSs += L.cnt[q][1];
-        tot += L.red[q][0];
+        tot += L.ext[q];
     }
     __syncthreads();
     AxisOut o{0, 0ull, 0ull};
     if (nRs == 0 || nSs == 0) return o;  // the same for every thread
     int k = kAxisKMax;
     if (tot) {
-        const unsigned long long q = ((2ull * (nRs + nSs)) << 30) / tot;
-        k = q < 1ull ? 1 : (q > (unsigned long long)kAxisKMax ? kAxisKMax : (int)q);
+        const u128 q = ((u128)(2ull * (nRs + nSs)) << 30) / tot;
+        k = q < 1 ? 1 : (q > (u128)kAxisKMax ? kAxisKMax : (int)q);
     }
     // B. difference arrays of the four histograms
     for (int i = tid; i < 4 * (kAxisKMax + 1); i += kAxisNT) (&L.hist[0][0])[i] = 0;

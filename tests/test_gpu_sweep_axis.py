@@ -38,6 +38,19 @@ def aniso_small():
     return R, S, oracle.pbsm(R, S, 32)
 
 
+def with_large(n, seed):
+    """A mixture where every 11th rectangle is enlarged to span 2 to 10 tiles
+    of a 16 x 16 grid: the samples' mean extent then depends on the large
+    extents (no clipping in the division count rule)."""
+    A = datagen.mixture(n, datagen.mixture_spec(8, 900 + seed), 0.2, 1e-3, 1.0, seed).copy()
+    rng = np.random.default_rng(seed)
+    big = np.arange(0, n, 11)
+    ext = rng.uniform(0.125, 0.625, size=(len(big), 2)).astype(np.float32)
+    A[big, 2] = A[big, 0] + ext[:, 0]
+    A[big, 3] = A[big, 1] + ext[:, 1]
+    return A
+
+
 CASES = [
     ("aniso K16", lambda: aniso(200_000, 2), 16, None),
     ("aniso K64", lambda: aniso(200_000, 3, 5e-4), 64, None),
@@ -45,6 +58,7 @@ CASES = [
                             datagen.mixture(80_000, datagen.mixture_spec(20, 5), 0.2, 2e-3, 1.0, 7)),
      8, None),
     ("aniso K32 domain", lambda: tuple(2 * A for A in aniso(100_000, 4)), 32, (0.0, 0.0, 2.0, 2.0)),
+    ("large extents K16", lambda: (with_large(60_000, 11), with_large(50_000, 12)), 16, None),
 ]
 
 

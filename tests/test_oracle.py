@@ -186,25 +186,39 @@ def test_uniform_1m_expected_count():
 # --------------------------------------------------------------------------
 def adversarial(n, seed, K):
     """Rectangles snapped to cell boundaries of a K-grid, +-1 ulp, zero extents,
-    coordinates outside [0,1), duplicates."""
+    coordinates outside [0,1), duplicates, and signed zeros: lower corners at
+    -0.0 or +0.0 (kind 5) and upper corners at -0.0 or +0.0 (kind 6), which
+    compare equal but have different bit patterns (the GPU's sort keys
+    canonicalise -0.0 to +0.0)."""
     rng = np.random.default_rng(seed)
-    kind = rng.integers(0, 5, n)
+    kind = rng.integers(0, 7, n)
     x = rng.random((n, 2)).astype(np.float32)
     grid = (rng.integers(-1, K + 2, (n, 2)) / K).astype(np.float32)
     x = np.where(kind[:, None] == 1, grid, x)
     ulp = np.where(rng.random((n, 2)) < 0.5, np.float32(-1), np.float32(1))
     x = np.where(kind[:, None] == 2, np.nextafter(grid, grid + ulp), x)
+    zeros = np.where(rng.random((n, 2)) < 0.5, np.float32(-0.0), np.float32(0.0))
+    x = np.where(kind[:, None] == 5, zeros, x)
     ext = (rng.random((n, 2)) * rng.choice([0.0, 1.0 / K, 2.5 / K, 0.3], n)[:, None]).astype(np.float32)
     ext = np.where(kind[:, None] == 3, np.float32(0), ext)
     ext = np.where(kind[:, None] == 4, (rng.integers(0, 3, (n, 2)) / K).astype(np.float32), ext)
     lo = x
     hi = (lo + ext).astype(np.float32)
-    out = np.concatenate([lo, hi], 1)[:, [0, 1, 2, 3]]
+    # kind 6: the rectangle ends at a signed zero
+    lo = np.where(kind[:, None] == 6, (-ext).astype(np.float32), lo)
+    hi = np.where(kind[:, None] == 6, zeros, hi)
     out = np.stack([lo[:, 0], lo[:, 1], hi[:, 0], hi[:, 1]], 1).astype(np.float32)
     dup = rng.random(n) < 0.05
     if dup.any() and n > 1:
         out[dup] = out[rng.integers(0, n, dup.sum())]
     return out
+
+
+def test_adversarial_inputs_hold_signed_zeros():
+    A = adversarial(2000, 7, 16)
+    z = A == 0
+    assert (z & np.signbit(A)).any() and (z & ~np.signbit(A)).any()
+    assert (A[:, 0] <= A[:, 2]).all() and (A[:, 1] <= A[:, 3]).all()
 
 
 @pytest.mark.parametrize("seed", range(40))

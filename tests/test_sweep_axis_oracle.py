@@ -88,6 +88,20 @@ def test_division_count_rule():
     assert sa.tile_model(B, B, 0, 0, 1)[3] == 0
 
 
+def test_division_count_uses_the_plain_mean_extent():
+    """k = floor(tile extent / mean (w + h) / 2) over the sample, with no
+    clipping of large extents: ten rectangles of 1/64 and one of 4 tiles
+    (K = 1) have mean extent 4.15625 / 11, so k = floor(11 / 4.15625) = 2
+    (clipping the large one at 2 tiles would give 5).  One extent beyond any
+    fixed-point range still gives k = 1."""
+    small = [_rect(0.1 * i, 0.1 * i, 0.1 * i + 1 / 64, 0.1 * i + 1 / 64) for i in range(10)]
+    big = [_rect(0.0, 0.0, 4.0, 4.0)]
+    A = np.array(small + big, np.float32)
+    assert sa.tile_model(A[:5], A[5:], 0, 0, 1)[0] == 2
+    H = np.array([_rect(-1e30, 0.0, 1e30, 0.5), _rect(0.2, 0.2, 0.2, 0.2)], np.float32)
+    assert sa.tile_model(H[:1], H[1:], 0, 0, 1)[0] == 1
+
+
 def test_divisions_are_relative_to_the_tile():
     # tile column 3 of K = 4 on [0, 8): cell units u = v / 2, divisions of u - 3
     lo, hi = sa.buckets(np.float32([6.0, 7.0]), np.float32([6.9, 7.99]),
