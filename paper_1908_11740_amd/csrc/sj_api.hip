@@ -12,6 +12,7 @@
 #include <new>
 #include <vector>
 
+#include "plan.hpp"
 #include "sj_internal.hpp"
 #include "sj_prof.hpp"
 
@@ -221,13 +222,10 @@ sj_status join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_
                        int64_t capacity) {
     p.C = C;
     const int64_t active = std::min<int64_t>(p.C, std::min(mR, mS)) + 1;
-    // span units per classification chunk: one, plus one per crossing of a
-    // multiple of unit_cap, per unit_tiles tiles and per tile that cuts a run
-    // (more than small_cap entries)
-    const int64_t blocks = classify_blocks(p.C);
     p.units_bound = std::min<int64_t>(
-        active, (mR + mS) / p.unit_cap + (mR + mS) / (p.small_cap + 1) +
-                    blocks * (classify_chunk_tiles() / p.unit_tiles + 2) + 1);
+        active, plan::span_units_bound(p.C, mR + mS,
+                                       plan::SpanRules{p.small_cap, p.unit_cap, p.unit_tiles,
+                                                       classify_chunk_tiles()}));
     p.med_bound = std::min<int64_t>(active, (mR + mS) / (p.small_cap + 1) + 1);
     const int64_t ndense = (mR + mS) / (p.med_cap + 1) + 2;
     hipError_t e = hipSuccess;
@@ -325,6 +323,50 @@ hipError_t part_prepare(Part& Pr, int64_t n, int64_t need_m1, int64_t need_m) {
     return hipSuccess;
 }
 
+// Debug mode (environment SJ_CHECK_WORKLISTS=1): after a join, read the
+// span units and both partitions' tile offsets back and check them on the
+// host (plan::check_units).  Costs a full download per join.
+bool check_worklists_enabled() {
+    const char* v = std::getenv("SJ_CHECK_WORKLISTS");
+    return v && v[0] && v[0] != '0';
+}
+
+sj_status check_worklists(const Part& R, const Part& S, const JoinParams& p, const JoinWork& w) {
+    sj_join_stats js{};
+    if (join_stats(w, false, &js) != hipSuccess) return SJ_ERR_DEVICE;
+    const int64_t n = js.small_units, C = (int64_t)R.bl.cells() * R.bl.tiles_per_cell();
+    if (n > w.cap_units) {
+        snprintf(g_err, sizeof(g_err), "work-list check: %lld span units > capacity %lld",
+                 (long long)n, (long long)w.cap_units);
+        return SJ_ERR_DEVICE;
+    }
+    std::vector<uint32_t> offR((size_t)C + 1), offS((size_t)C + 1);
+    std::vector<uint4> sp((size_t)n);
+    std::vector<uint2> ut((size_t)n);
+    if (hipMemcpy(offR.data(), R.off, (C + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(offS.data(), S.off, (C + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        (n && hipMemcpy(sp.data(), w.uspan, n * sizeof(uint4), hipMemcpyDeviceToHost) != hipSuccess) ||
+        (n && hipMemcpy(ut.data(), w.units, n * sizeof(uint2), hipMemcpyDeviceToHost) != hipSuccess))
+        return SJ_ERR_DEVICE;
+    if (offR[C] != (uint32_t)R.m || offS[C] != (uint32_t)S.m || R.m > R.cap_m || S.m > S.cap_m) {
+        snprintf(g_err, sizeof(g_err), "work-list check: tile offsets end past the entries");
+        return SJ_ERR_DEVICE;
+    }
+    std::vector<plan::Unit> u((size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        u[(size_t)i] = plan::Unit{sp[i].x, sp[i].y, sp[i].z, sp[i].w, ut[i].x, ut[i].y};
+    const plan::SpanRules rules{p.small_cap, p.unit_cap, p.unit_tiles, classify_chunk_tiles()};
+    const int64_t max_e = std::min<int64_t>(plan::span_unit_max_entries(rules), lds_unit_entries(p.block));
+    const char* why = "";
+    const int64_t bad = plan::check_units(offR.data(), offS.data(), C, u.data(), n, max_e,
+                                          p.unit_tiles, p.small_cap, &why);
+    if (bad >= 0) {
+        snprintf(g_err, sizeof(g_err), "work-list check: span unit %lld: %s", (long long)bad, why);
+        return SJ_ERR_DEVICE;
+    }
+    return SJ_OK;
+}
+
 // e2 non-null: distance join of two partitions of anchored squares (pairs
 // with dx*dx + dy*dy <= *e2); *cand then receives the filter's pair count.
 sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
@@ -381,6 +423,10 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
     if (flags & (kStatInternal | kStatCapacity)) {
         snprintf(g_err, sizeof(g_err), "join: internal status flags 0x%x", flags);
         return SJ_ERR_DEVICE;
+    }
+    if (!p.plain && check_worklists_enabled()) {
+        st = check_worklists(*R, *S, p, w);
+        if (st != SJ_OK) return st;
     }
     *n_pairs = (int64_t)hs.n_pairs;
     if (cand) *cand = (int64_t)hs.n_cand;
@@ -619,12 +665,20 @@ sj_status sj_tune_save(const char* path) {
     for (const auto& kv : g_tune) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, kv.first.dev) != hipSuccess) continue;
-        char arch[64];
-        arch_name(prop, arch, sizeof(arch));
-        const sj_tuning& t = kv.second;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.6f\n", arch, kv.first.k, kv.first.lr,
-                     kv.first.ls, kv.first.count_only, t.block, t.small_cap, t.med_cap,
-                     t.split_tau, t.ms);
+        plan::TuneLine t{};
+        arch_name(prop, t.arch, sizeof(t.arch));
+        t.k = kv.first.k;
+        t.lr = kv.first.lr;
+        t.ls = kv.first.ls;
+        t.mode = kv.first.count_only;
+        t.block = kv.second.block;
+        t.small_cap = kv.second.small_cap;
+        t.med_cap = kv.second.med_cap;
+        t.split_tau = kv.second.split_tau;
+        t.ms = kv.second.ms;
+        char line[256];
+        plan::format_tune_line(t, line, sizeof(line));
+        std::fputs(line, f);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? SJ_OK : SJ_ERR_ARG;
@@ -645,19 +699,15 @@ sj_status sj_tune_load(const char* path, int32_t* n_loaded) {
     char line[512];
     bool bad = false;
     while (std::fgets(line, sizeof(line), f)) {
-        if (line[0] == '#' || line[0] == '\n') continue;
-        char arch[64];
-        TuneKey key{dev, 0, 0, 0, 0};
-        sj_tuning t{};
-        if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %lf", arch, &key.k, &key.lr, &key.ls,
-                        &key.count_only, &t.block, &t.small_cap, &t.med_cap, &t.split_tau,
-                        &t.ms) != 10 ||
-            (t.block != 64 && t.block != 128 && t.block != 256 && t.block != 512) ||
-            t.small_cap < 2 || t.med_cap < 2 || t.split_tau < 0 || key.k < 1 || key.k > SJ_K_MAX) {
+        plan::TuneLine t;
+        const int r = plan::parse_tune_line(line, SJ_K_MAX, &t);
+        if (r < 0) {
             bad = true;
             break;
         }
-        if (std::strcmp(arch, mine) == 0) got.emplace_back(key, t);
+        if (r == 0 || std::strcmp(t.arch, mine) != 0) continue;
+        got.emplace_back(TuneKey{dev, t.k, t.lr, t.ls, t.mode},
+                         sj_tuning{t.block, t.small_cap, t.med_cap, t.split_tau, t.ms});
     }
     std::fclose(f);
     if (bad) {

@@ -17,7 +17,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_1908_11740_amd import sj  # noqa: E402
-from gpu_util import gpu_join, to_dev  # noqa: E402
+from gpu_util import gpu_join, sort_pairs, to_dev  # noqa: E402
 
 SCHEDULES = {"tuned": dict(), "plain": dict(flags=sj.SJ_PLAIN),
              "tau1": dict(split_tau=1), "nosplit": dict(split_tau=sj.INT32_MAX),
@@ -240,3 +240,29 @@ def test_handle_reuse_across_grids():
         got = np.asarray(sj.join(PR, PS).cpu().numpy())
         got = got[np.lexsort((got[:, 1], got[:, 0]))]
         assert np.array_equal(got, ref), k
+
+
+@pytest.mark.parametrize("block", [64, 128, 256, 512])
+def test_worklist_check_mode(monkeypatch, block):
+    """With SJ_CHECK_WORKLISTS=1 the library reads every join's span units
+    and tile offsets back and checks them on the host (capacity, spans equal
+    to the offsets, entry and tile limits, a joinable tile per unit, no
+    shared tiles); clustered inputs with empty, one-sided, small and medium
+    tiles pass on every small-tile block shape, and the pairs are exact."""
+    monkeypatch.setenv("SJ_CHECK_WORKLISTS", "1")
+    mix = datagen.mixture_spec(10, 61)
+    R = datagen.mixture(80_000, mix, 0.2, 3e-4, 1.0, 62)
+    S = datagen.mixture(70_000, mix, 0.2, 3e-4, 1.0, 63)
+    ref = oracle.pbsm(R, S, 64)
+    E = {64: 256, 128: 1024, 256: 1024, 512: 2048}[block]
+    for K in (16, 200, 900):
+        say("work-list check", block, K)
+        PR, PS = sj.partition(to_dev(R), K), sj.partition(to_dev(S), K)
+        sj.tune_set(PR, PS, block, E // 4, 1024)
+        out = torch.empty((len(ref) + 16, 2), dtype=torch.int32, device="cuda")
+        st, n = sj.join_into(PR, PS, out)
+        assert st == sj.SJ_OK and n == len(ref)
+        assert np.array_equal(sort_pairs(out[:n].cpu().numpy()), ref), K
+        PR.free()
+        PS.free()
+    sj.tune_clear()
