@@ -233,10 +233,19 @@ sj_status sj_tune_load(const char* path, int32_t* n_loaded);
  * Many independent joins in one replayable launch.  Joins, like tiles, are
  * independent tasks (Sec. 3.4): a batch plans every join once (grid from
  * grids[j], or where its k or split_tau is 0 the picker / rule of
- * sj_choose_grid), sizes its buffers, assigns the joins longest-first to a
- * few concurrent streams and records all partition and join kernels into
- * one hipGraph.  sj_batch_run replays it: one graph launch and one status
- * readback for the whole batch.
+ * sj_choose_grid), sizes its buffers and records one hipGraph: each join's
+ * two partitions and its tile classification (on a few concurrent streams,
+ * joins assigned longest-first), the classification appending the join's
+ * work units -- span units of small tiles, medium tiles, dense tiles split
+ * into pivot ranges -- tagged with the join's index to work lists shared by
+ * the batch; then one sequence of join launches whose persistent workgroups
+ * take the units of all joins from those lists, each pair going straight to
+ * its join's slice of `out` at a position reserved on the join's counter
+ * (pair order within a slice unspecified).  Every join uses the batch's
+ * small-tile workgroup shape and default caps, its grid's split threshold
+ * and flags; SJ_PLAIN and SJ_TWO_PASS do not apply to batches.
+ * sj_batch_run replays it: one graph launch and one status readback for
+ * the whole batch.
  *   R[j], S[j]   device rectangle arrays (as sj_partition) of nR[j], nS[j]
  *                rectangles; borrowed for the batch's lifetime (replays
  *                read them again, so their contents may change between runs).
@@ -245,11 +254,12 @@ sj_status sj_tune_load(const char* path, int32_t* n_loaded);
  *                writes [out_offsets[j], out_offsets[j+1]) (host array of
  *                n_joins + 1).  Borrowed like the inputs.
  *   n_pairs      host, n_joins: |J_j| of every join.
- * Creation runs every join once (capacities are checked on the device and
+ * Creation runs the batch once (capacities are checked on the device and
  * grown as needed) before recording.  A run returns SJ_ERR_CAPACITY if some
- * join's pairs exceed its slice (its n_pairs is still exact).  A join that
- * outgrows its buffers on a later run (new data) is re-run alone with grown
- * buffers and the graph is recorded again.  Synchronises `stream` once.
+ * join's pairs exceed its slice (its n_pairs is still exact).  When a join
+ * outgrows its buffers on a later run (new data), its buffers and the shared
+ * lists grow, the batch runs again and the graph is recorded again.
+ * Synchronises `stream` once.
  */
 typedef struct sj_batch sj_batch;
 

@@ -3,23 +3,34 @@
 // Tiles are independent tasks (Sec. 3.4); so are whole joins.  A batch
 // plans every join once -- grid choice (learned picker or rule), buffer
 // capacities, a longest-processing-time assignment of the joins to a few
-// streams -- and records the partition and join kernels of all joins into
-// one hipGraph whose branches (one per stream) run concurrently, so small
-// joins fill the GPU together instead of paying one launch sequence and
-// one host synchronisation each.  A replay is one graph launch and one
-// status readback for the whole batch.  Capacities are bounds, checked on
-// the device as in the single-join path; a join that outgrew them (new
-// data in the same buffers) is re-run alone with grown buffers and the
+// streams -- and records one hipGraph per batch:
+//   * on the streams, each join's two partitions and its classification,
+//     which appends the join's work records (span units of small tiles,
+//     medium tiles, dense tiles), tagged with the join's index, to one set
+//     of work lists shared by the whole batch;
+//   * then, once, the join launches over the shared lists: persistent
+//     workgroups take the work units of all joins (round-robin over the
+//     lists, which each join's classification filled with its own records),
+//     and every pair goes straight to its join's output region at a
+//     position reserved on the join's fill counter.
+// A replay is one graph launch and one status readback for the whole
+// batch.  Capacities are bounds checked on the device, as in the single-join
+// path; when a join outgrows them (new data in the same buffers) its buffers
+// grow, the shared lists are resized, the batch runs again eagerly and the
 // graph is recorded again.
 #include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
 
+#include "plan.hpp"
 #include "sj_internal.hpp"
 #include "sj_prof.hpp"
 
 namespace sj {
+int64_t classify_chunk_tiles();
+int lds_medium_entries();
+
 namespace {
 
 constexpr int kLanes = 4;  // concurrent graph branches (HIP's hardware queues per process)
@@ -46,19 +57,37 @@ void free_part(Part& P) {  // st belongs to the batch's status array
     P = Part{};
 }
 
-void free_work(JoinWork& w) {
+void free_work(BatchWork& bw) {
+    JoinWork& w = bw.w;
     void* bufs[] = {w.uspan, w.units, w.med, w.medt, w.dense, w.dense_unit_prefix, w.dgrp, w.dmj,
-                    w.ucnt, w.scan_tmp,
-                    w.dbox, w.didf, w.dtmp, w.sc_buf, w.sc_fills, w.sc_ctr, w.sc_total, w.ctr};
+                    w.dbox, w.didf, w.dtmp, w.ctr, w.st, bw.ujob, bw.mjob, bw.djob, bw.jobs,
+                    bw.fill};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
-    w = JoinWork{};
+    bw = BatchWork{};
 }
 
 sj_status from_hip_err(hipError_t e) {
     if (e == hipSuccess) return SJ_OK;
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SJ_ERR_OOM;
     return SJ_ERR_DEVICE;
+}
+
+// The schedule of one join in a batch: the small-tile workgroup shape is the
+// batch's (one launch serves all joins), the caps its defaults, the split
+// threshold and the flags the join's grid's; the plain schedule does not
+// apply (every join is batched).
+JoinParams batch_join_params(const sj_grid& g, bool count_only) {
+    sj_grid q = g;
+    q.flags &= ~(uint32_t)(SJ_PLAIN | SJ_TWO_PASS);
+    JoinParams p = api_join_params(q, count_only);
+    p.block = batch_block();
+    const int E = 4 * p.block;
+    p.small_cap = E / 4;
+    p.unit_cap = E - p.small_cap;
+    p.unit_tiles = p.block - 1;
+    p.med_cap = lds_medium_entries();
+    return p;
 }
 
 }  // namespace
@@ -79,7 +108,9 @@ struct sj_batch {
     sj_pair* out = nullptr;
     sj::DevStatus* dst = nullptr;  // [3n]: R partitions, S partitions, joins
     sj::DevStatus* hst = nullptr;  // pinned mirror
-    sj::JoinWork work[sj::kLanes];
+    sj::BatchWork bw;              // the shared work lists and the job descriptors
+    int64_t units_bound = 0, med_bound = 0;
+    bool any_axis = false;
     hipStream_t ls[sj::kLanes] = {};
     hipEvent_t fork = nullptr, done[sj::kLanes] = {};
     hipGraph_t graph = nullptr;
@@ -93,43 +124,120 @@ int64_t cap_of(const sj_batch* b, int j) {
     return b->out ? b->off[j + 1] - b->off[j] : 0;
 }
 
-sj_status prepare_join(sj_batch* b, int j) {
-    Part& R = b->R[j];
-    Part& S = b->S[j];
+// Size every join's partition buffers from its current needs, the shared
+// work lists from the sum of the joins' bounds, and write the job
+// descriptors.  Buffers may move: a recorded graph is stale afterwards.
+sj_status prepare_all(sj_batch* b) {
     hipError_t e;
-    if ((e = api_part_prepare(R, b->nr[j], b->need_m1R[j], b->need_mR[j])) != hipSuccess ||
-        (e = api_part_prepare(S, b->ns[j], b->need_m1S[j], b->need_mS[j])) != hipSuccess)
+    BatchWork& bw = b->bw;
+    JoinWork& w = bw.w;
+    int64_t units = 1, med = 1, dense = 2, dent = 1, dunits = 1;
+    bool any_gbda = false;
+    b->any_axis = false;
+    std::vector<Job> jobs((size_t)std::max(b->n, 1));
+    for (int j = 0; j < b->n; ++j) {
+        Part& R = b->R[j];
+        Part& S = b->S[j];
+        if ((e = api_part_prepare(R, b->nr[j], b->need_m1R[j], b->need_mR[j])) != hipSuccess ||
+            (e = api_part_prepare(S, b->ns[j], b->need_m1S[j], b->need_mS[j])) != hipSuccess)
+            return from_hip_err(e);
+        JoinParams p = batch_join_params(b->grid[j], b->count_only);
+        p.C = (int64_t)R.bl.cells() * R.bl.tiles_per_cell();
+        const int64_t m = R.cap_m + S.cap_m, active = std::min<int64_t>(p.C, std::min(R.cap_m, S.cap_m)) + 1;
+        p.units_bound = std::min<int64_t>(
+            active, plan::span_units_bound(p.C, m, plan::SpanRules{p.small_cap, p.unit_cap,
+                                                                  p.unit_tiles,
+                                                                  classify_chunk_tiles()}));
+        p.med_bound = std::min<int64_t>(active, m / (p.small_cap + 1) + 1);
+        const int64_t nd = m / (p.med_cap + 1) + 2;
+        units += p.units_bound;
+        med += p.med_bound;
+        dense += nd;
+        dent += m;
+        dunits += (p.gbda ? 4 : 1) * m / std::max(1, p.split_tau) + (p.gbda ? 9 : 1) * nd + 1;
+        any_gbda = any_gbda || p.gbda;
+        b->any_axis = b->any_axis || p.axis_model;
+        b->jp[j] = p;
+        Job& J = jobs[(size_t)j];
+        J = Job{};
+        J.offR = R.off;
+        J.offS = S.off;
+        J.entR = R.entb;
+        J.entS = S.entb;
+        J.idR = R.enti;
+        J.idS = S.enti;
+        J.out = b->out ? (unsigned long long*)(b->out + b->off[j]) : nullptr;
+        J.capacity = cap_of(b, j);
+        J.st = b->dst + 2 * (int64_t)b->n + j;
+        J.stR = R.st;
+        J.stS = S.st;
+        J.e2 = 0.0;
+        J.split_tau = p.split_tau;
+        J.flags = (p.axis_model ? kJobAxis : 0u) | (p.gbda ? kJobGbda : 0u);
+        J.gd = R.gd;
+        J.bl = R.bl;
+    }
+    b->units_bound = units;
+    b->med_bound = med;
+    int64_t c1 = 0, c2 = 0, c3 = 0;
+    if ((e = grow_buf(w.units, w.cap_units, units)) != hipSuccess ||
+        (e = grow_buf(w.uspan, w.cap_uspan, w.cap_units)) != hipSuccess ||
+        (e = grow_buf(bw.ujob, bw.cap_ujob, w.cap_units)) != hipSuccess ||
+        (e = grow_buf(w.med, w.cap_med, med)) != hipSuccess ||
+        (e = grow_buf(w.medt, w.cap_medt, w.cap_med)) != hipSuccess ||
+        (e = grow_buf(bw.mjob, bw.cap_mjob, w.cap_med)) != hipSuccess ||
+        (e = grow_buf(w.dense, w.cap_dense, dense)) != hipSuccess ||
+        (e = grow_buf(bw.djob, bw.cap_djob, w.cap_dense)) != hipSuccess ||
+        (e = grow_buf(w.dense_unit_prefix, w.cap_prefix, w.cap_dense + 1)) != hipSuccess)
         return from_hip_err(e);
-    JoinParams p = api_join_params(b->grid[j], b->count_only);
-    const int64_t C = (int64_t)R.bl.cells() * R.bl.tiles_per_cell();
-    sj_status st = api_join_prepare(b->work[b->lane[j]], p, C, R.cap_m, S.cap_m, cap_of(b, j));
-    if (st != SJ_OK) return st;
-    b->jp[j] = p;
+    w.cap_dunits = std::max(w.cap_dunits, dunits);
+    if (any_gbda && ((e = grow_buf(w.dgrp, w.cap_dgrp, 10 * w.cap_dense)) != hipSuccess ||
+                     (e = grow_buf(w.dmj, w.cap_dmj, 10 * w.cap_dense)) != hipSuccess))
+        return from_hip_err(e);
+    if (dent > w.cap_dent || !w.dbox) {
+        if (w.dbox) (void)hipFree(w.dbox);
+        if (w.didf) (void)hipFree(w.didf);
+        if (w.dtmp) (void)hipFree(w.dtmp);
+        w.dbox = nullptr;
+        w.didf = nullptr;
+        w.dtmp = nullptr;
+        w.cap_dent = 0;
+        if ((e = grow_buf(w.dbox, c1, dent)) != hipSuccess ||
+            (e = grow_buf(w.didf, c2, c1)) != hipSuccess ||
+            (e = grow_buf(w.dtmp, c3, 2 * c1)) != hipSuccess)
+            return from_hip_err(e);
+        w.cap_dent = c1;
+    }
+    if ((e = grow_buf(bw.jobs, bw.cap_jobs, (int64_t)jobs.size())) != hipSuccess ||
+        (e = grow_buf(bw.fill, bw.cap_fill, (int64_t)jobs.size())) != hipSuccess)
+        return from_hip_err(e);
+    for (int j = 0; j < b->n; ++j) jobs[(size_t)j].fill = bw.fill + j;
+    if (b->n > 0 &&
+        (e = hipMemcpy(bw.jobs, jobs.data(), sizeof(Job) * (size_t)b->n, hipMemcpyHostToDevice)) !=
+            hipSuccess)
+        return from_hip_err(e);
     return SJ_OK;
 }
 
-hipError_t enqueue_join(sj_batch* b, int j, hipStream_t s) {
-    hipError_t e;
-    if ((e = run_partition(b->R[j], b->rin[j], b->nr[j], b->num_cus, s)) != hipSuccess) return e;
-    if ((e = run_partition(b->S[j], b->sin[j], b->ns[j], b->num_cus, s)) != hipSuccess) return e;
-    JoinWork w = b->work[b->lane[j]];
-    w.st = b->dst + 2 * (int64_t)b->n + j;
-    return run_join(b->R[j], b->S[j], b->jp[j], w, b->out ? b->out + b->off[j] : nullptr,
-                    cap_of(b, j), s);
-}
-
-// All joins, one stream per lane, forked from and joined back into s.
+// The whole batch on stream s: clear the shared counters, then per lane each
+// join's partitions and classification, then the shared join launches.
 hipError_t enqueue_all(sj_batch* b, hipStream_t s) {
     hipError_t e;
+    if ((e = batch_reset(b->bw, b->n, s)) != hipSuccess) return e;
     if ((e = hipEventRecord(b->fork, s)) != hipSuccess) return e;
     for (int l = 0; l < kLanes; ++l) {
         if ((e = hipStreamWaitEvent(b->ls[l], b->fork, 0)) != hipSuccess) return e;
-        for (int j : b->lane_jobs[l])
-            if ((e = enqueue_join(b, j, b->ls[l])) != hipSuccess) return e;
+        for (int j : b->lane_jobs[l]) {
+            if ((e = run_partition(b->R[j], b->rin[j], b->nr[j], b->num_cus, b->ls[l])) != hipSuccess ||
+                (e = run_partition(b->S[j], b->sin[j], b->ns[j], b->num_cus, b->ls[l])) != hipSuccess ||
+                (e = batch_classify(b->bw, b->R[j], b->S[j], b->jp[j], (uint32_t)j, b->ls[l])) !=
+                    hipSuccess)
+                return e;
+        }
         if ((e = hipEventRecord(b->done[l], b->ls[l])) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(s, b->done[l], 0)) != hipSuccess) return e;
     }
-    return hipSuccess;
+    return batch_join(b->bw, b->n, b->any_axis, b->units_bound, b->med_bound, s);
 }
 
 hipError_t read_all(sj_batch* b, hipStream_t s) {
@@ -139,10 +247,10 @@ hipError_t read_all(sj_batch* b, hipStream_t s) {
     return hipStreamSynchronize(s);
 }
 
-// After a run: grow what overflowed.  Returns SJ_OK when every join fitted,
-// SJ_ERR_CAPACITY (internal) when some were regrown and must run again.
-sj_status check(sj_batch* b, std::vector<int>& redo) {
-    redo.clear();
+// After a run: raise the needs of what overflowed.  *again: something must
+// grow and the batch run again.
+sj_status check(sj_batch* b, bool* again) {
+    *again = false;
     const int n = b->n;
     for (int j = 0; j < n; ++j) {
         const DevStatus& r = b->hst[j];
@@ -151,24 +259,23 @@ sj_status check(sj_batch* b, std::vector<int>& redo) {
         const uint32_t f = r.flags | s.flags | q.flags;
         if (f & kStatBadRect) return SJ_ERR_RECT;
         if (f & kStatTooLarge) return SJ_ERR_TOO_LARGE;
-        if (f & kStatInternal) return SJ_ERR_DEVICE;
-        bool again = false;
+        if (f & kStatInternal) {
+            api_set_error("batch: internal status flag");
+            return SJ_ERR_DEVICE;
+        }
         if (r.flags & kStatCapacity) {
             b->need_m1R[j] = std::max<int64_t>(b->need_m1R[j], (int64_t)r.m1_total + 1);
             if (r.m_total) b->need_mR[j] = std::max<int64_t>(b->need_mR[j], (int64_t)r.m_total + 1);
-            again = true;
+            *again = true;
         }
         if (s.flags & kStatCapacity) {
             b->need_m1S[j] = std::max<int64_t>(b->need_m1S[j], (int64_t)s.m1_total + 1);
             if (s.m_total) b->need_mS[j] = std::max<int64_t>(b->need_mS[j], (int64_t)s.m_total + 1);
-            again = true;
+            *again = true;
         }
-        if (!again && (q.flags & kStatCapacity)) again = true;  // join bounds: exact m next time
-        if (!again && (q.flags & kStatScratch) && (int64_t)q.n_pairs <= cap_of(b, j)) {
-            b->grid[j].flags |= SJ_TWO_PASS;
-            again = true;
-        }
-        if (again) redo.push_back(j);
+        // the shared lists are sized from bounds of the partitions' capacities,
+        // so they overflow only after a partition did (re-sized above)
+        if (q.flags & kStatCapacity) *again = true;
     }
     return SJ_OK;
 }
@@ -199,37 +306,25 @@ hipError_t capture(sj_batch* b) {
     return e;
 }
 
-// Eager runs of the given joins (on their lanes) until every one fits.
-// Re-preparing a join may free and reallocate its partition buffers and its
-// lane's work lists, and may switch it to two passes, so a recorded graph
-// holds stale kernel arguments after any job is prepared again: it is
-// dropped here, and the next replay records a new one.
-sj_status settle(sj_batch* b, std::vector<int> jobs, hipStream_t s) {
-    if (!jobs.empty()) drop_graph(b);
-    for (int attempt = 0; attempt < 4 && !jobs.empty(); ++attempt) {
-        for (int j : jobs) {
-            sj_status st = prepare_join(b, j);
-            if (st != SJ_OK) return st;
-        }
-        hipError_t e = hipEventRecord(b->fork, s);
-        for (int j : jobs) {
-            if (e == hipSuccess) e = hipStreamWaitEvent(b->ls[b->lane[j]], b->fork, 0);
-            if (e == hipSuccess) e = enqueue_join(b, j, b->ls[b->lane[j]]);
-        }
-        for (int l = 0; l < kLanes && e == hipSuccess; ++l) {
-            e = hipEventRecord(b->done[l], b->ls[l]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(s, b->done[l], 0);
-        }
+// Size everything and run the batch eagerly until every join fits.  Sizing
+// may free and reallocate buffers, so a recorded graph holds stale kernel
+// arguments afterwards: it is dropped, and the next replay records a new one.
+sj_status settle(sj_batch* b, hipStream_t s) {
+    drop_graph(b);
+    if (b->n == 0) return prepare_all(b);
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        sj_status st = prepare_all(b);
+        if (st != SJ_OK) return st;
+        hipError_t e = enqueue_all(b, s);
         if (e == hipSuccess) e = read_all(b, s);
         if (e != hipSuccess) return from_hip_err(e);
-        sj_status st = check(b, jobs);
+        bool again = false;
+        st = check(b, &again);
         if (st != SJ_OK) return st;
+        if (!again) return SJ_OK;
     }
-    if (!jobs.empty()) {
-        api_set_error("batch: buffers still too small after regrowth");
-        return SJ_ERR_DEVICE;
-    }
-    return SJ_OK;
+    api_set_error("batch: buffers still too small after regrowth");
+    return SJ_ERR_DEVICE;
 }
 
 void destroy(sj_batch* b) {
@@ -237,7 +332,7 @@ void destroy(sj_batch* b) {
     drop_graph(b);
     for (auto& P : b->R) free_part(P);
     for (auto& P : b->S) free_part(P);
-    for (auto& w : b->work) free_work(w);
+    free_work(b->bw);
     for (int l = 0; l < kLanes; ++l) {
         if (b->ls[l]) (void)hipStreamDestroy(b->ls[l]);
         if (b->done[l]) (void)hipEventDestroy(b->done[l]);
@@ -309,11 +404,15 @@ sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t*
         if (hipStreamCreateWithFlags(&b->ls[l], hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&b->done[l], hipEventDisableTiming) != hipSuccess)
             return fail(SJ_ERR_DEVICE);
-        JoinWork& w = b->work[l];
+    }
+    {
+        JoinWork& w = b->bw.w;
         w.device = b->device;
         w.num_cus = b->num_cus;
         int64_t cap = 0;
         if (grow_buf(w.ctr, cap, 16, true) != hipSuccess) return fail(SJ_ERR_OOM);
+        cap = 0;
+        if (grow_buf(w.st, cap, 1, true) != hipSuccess) return fail(SJ_ERR_OOM);
     }
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
         return fail(SJ_ERR_DEVICE);
@@ -367,7 +466,7 @@ sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t*
         load[l] += work[j];
     }
     // 3. size everything, run once eagerly (capacities checked), record the graph
-    sj_status st = settle(b, order, s);
+    sj_status st = settle(b, s);
     if (st != SJ_OK) return fail(st);
     if (capture(b) != hipSuccess) {
         api_set_error("batch: graph capture failed");
@@ -384,11 +483,11 @@ sj_status sj_batch_run(sj_batch* b, int64_t* n_pairs, void* stream) {
     if (!b->exec && capture(b) != hipSuccess) return SJ_ERR_DEVICE;
     if (hipGraphLaunch(b->exec, s) != hipSuccess || read_all(b, s) != hipSuccess)
         return SJ_ERR_DEVICE;
-    std::vector<int> redo;
-    sj_status st = check(b, redo);
+    bool again = false;
+    sj_status st = check(b, &again);
     if (st != SJ_OK) return st;
-    if (!redo.empty()) {
-        st = settle(b, redo, s);
+    if (again) {
+        st = settle(b, s);
         if (st != SJ_OK) return st;
     }
     bool over = false;

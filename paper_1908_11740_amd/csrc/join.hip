@@ -69,6 +69,7 @@ static_assert(kMedEntries == kSmallEntries + 1 && kSmallEntries % 2 == 0, "stati
 constexpr int kWaveBuf = 256;        // staged pairs per wave (>= 64 lanes x kCand)
 constexpr int kUnitWaveBuf = 128;    // LDS units emit one candidate per lane and call
 constexpr int kMedNT = 512;          // workgroup of the medium-tile kernel
+constexpr int kBatchBlock = 256;     // small-tile workgroup of a batch of joins
 constexpr int kMedE = 2048;          // LDS entries of a medium tile
 constexpr int kDenseSortMax = 8192;  // entries sorted in LDS by the dense sort
 constexpr int kDenseSortNT = 1024;
@@ -122,7 +123,45 @@ struct Args {
     uint32_t* dmj;                // [cap_dense * 10] units before each mini-join of a dense tile
     int dist;                     // distance join (boxes: squares anchored at their points)
     double e2;                    // ... keep a pair only if dx*dx + dy*dy <= e2
+    // batch of joins: the lists hold the records of many joins, each tagged
+    // with its join's index into jobs (slabs, output region, flags); the
+    // fields above that describe one join are then those of jid (k_classify)
+    int batch;
+    uint32_t jid;
+    const Job* jobs;
+    uint32_t* ujob;               // join of each span unit
+    uint32_t* mjob;               // ... medium tile
+    uint32_t* djob;               // ... dense tile
 };
+
+// One join's tile offsets and slabs: from the arguments (single join) or
+// from the descriptor of a record's join (batch).
+struct Src {
+    const uint32_t* offR;
+    const uint32_t* offS;
+    float4* entR;
+    float4* entS;
+    uint32_t* idR;
+    uint32_t* idS;
+};
+
+__device__ __forceinline__ Src src_of(const Args& a) {
+    return Src{a.offR, a.offS, a.entR, a.entS, a.idR, a.idS};
+}
+__device__ __forceinline__ Src src_of(const Job& j) {
+    return Src{j.offR, j.offS, j.entR, j.entS, j.idR, j.idS};
+}
+
+// Per-join schedule fields of a record: its job's (batch) or the arguments'.
+struct JobFlags {
+    int dist, gbda, plain, split_tau;
+    double e2;
+};
+__device__ __forceinline__ JobFlags flags_of(const Args& a, uint32_t job) {
+    if (!a.batch) return JobFlags{a.dist, a.gbda, a.plain, a.split_tau, a.e2};
+    const Job& j = a.jobs[job];
+    return JobFlags{(j.flags & kJobDist) ? 1 : 0, (j.flags & kJobGbda) ? 1 : 0, 0, j.split_tau, j.e2};
+}
 
 // GBDA classes of an entry in its tile, from the start bits of Eq. (1):
 // A = both projections begin in the tile, B = only x, C = only y, D = neither.
@@ -162,10 +201,15 @@ __device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_AC
 //            serialises); chunk fill levels are compacted into the caller's
 //            buffer afterwards.  Every hit is counted even if the scratch
 //            runs out, so the exact count is always known.
+//   kAppend  batch of joins: per-wave LDS staging flushed at the end of every
+//            unit (and when full) straight into the output region of the
+//            unit's join, at a position reserved with one 64-bit atomic on
+//            the join's fill counter; pairs past its capacity are counted,
+//            not stored.  No scratch and no compaction.
 // BLOCK: the unit is processed by a whole workgroup (end() has barriers);
 // otherwise by one wavefront.
 // ---------------------------------------------------------------------------
-enum Mode : int { kCount = 0, kWrite = 1, kSingle = 2 };
+enum Mode : int { kCount = 0, kWrite = 1, kSingle = 2, kAppend = 3 };
 constexpr int kRegions = 32;    // scratch regions / reservation counters
 constexpr int kChunkP = 512;    // pairs per scratch chunk
 constexpr int kTotals = 64;     // spread counters of the per-wave hit totals
@@ -183,6 +227,9 @@ struct Sink {
     bool have, ok;
     unsigned long long total;       // hits seen by this wave (kSingle)
     uint32_t cand;                  // this lane's filter pairs (distance join; not kWrite)
+    unsigned long long* jout;       // kAppend: the current unit's join: output region,
+    unsigned long long* jfill;      //   fill counter,
+    int64_t jcap;                   //   capacity
 
     __device__ void init(uint32_t wave_gid) {
         n = 0;
@@ -195,6 +242,16 @@ struct Sink {
         ok = true;
         total = 0;
         cand = 0;
+        jout = nullptr;
+        jfill = nullptr;
+        jcap = 0;
+    }
+
+    // kAppend: the join whose pairs the following units emit
+    __device__ void set_job(const Job& j) {
+        jout = j.out;
+        jfill = j.fill;
+        jcap = j.capacity;
     }
 
     __device__ void begin(const Args& a, int64_t slot) {
@@ -209,7 +266,13 @@ struct Sink {
 
     __device__ void flush(const Args& a) {
         lds_fence();
-        if (MODE == kWrite) {
+        if (MODE == kAppend) {
+            unsigned long long b = 0;
+            if (lane_id() == 0) b = atomicAdd(jfill, (unsigned long long)n);
+            b = __shfl(b, 0, kWave);
+            for (uint32_t q = lane_id(); q < n; q += kWave)
+                if (b + q < (unsigned long long)jcap) jout[b + q] = buf[q];
+        } else if (MODE == kWrite) {
             uint32_t b = cfill;  // one wave per unit: a register counter
             if (BLOCK) {
                 if (lane_id() == 0) b = atomicAdd(s_acc, n);
@@ -281,7 +344,7 @@ struct Sink {
     }
 
     __device__ void end(const Args& a, int64_t slot) {
-        if (MODE == kWrite) {
+        if (MODE == kWrite || MODE == kAppend) {
             if (n) flush(a);
         } else if (MODE == kCount) {
             uint32_t v = cnt;
@@ -359,7 +422,7 @@ constexpr int kChunkC = 8;  // consecutive candidates per lane and round (LDS un
 
 template <int MODE, bool BLOCK, bool REF = true, class Acc>
 __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_end, uint32_t* next,
-                             Sink<MODE, BLOCK>& sk) {
+                             Sink<MODE, BLOCK>& sk, bool dist, double e2) {
     bool scanning = false, exhausted = false, isR = false;
     int j = 0, jend = 0;
     float pxl = 0.f, pxu = 0.f, pyl = 0.f, pyu = 0.f;
@@ -410,8 +473,8 @@ __device__ void sweep_pivots(const Args& a, const Acc& acc, int p_begin, int p_e
                 go = go && (j + k < jend) && (c[k].x <= pxu);
                 const bool f = go && (pyl <= c[k].w) && (c[k].y <= pyu) &&
                                (!REF || ref_point_here(pid, qid[k]));
-                hit[k] = f && (!a.dist || within_eps(make_float4(pxl, pyl, pxu, pyu), c[k], a.e2));
-                if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
+                hit[k] = f && (!dist || within_eps(make_float4(pxl, pyl, pxu, pyu), c[k], e2));
+                if (MODE != kWrite) sk.cand += (dist && f) ? 1u : 0u;
                 used += go ? 1 : 0;
                 const uint32_t other = qid[k] & kIdMask;
                 er[k] = isR ? me : other;
@@ -525,8 +588,10 @@ __device__ __forceinline__ int seg_rank(const uint32_t* key, int lo, int hi, int
 // y; the write-back exchanges them again.  The duplicate test of Eq. (1) is
 // symmetric in x and y, so the pairs reported do not change.
 template <int NT, int Q, int TC, int MODE, class TileOf, class Prefetch>
-__device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, int c, const TileOf& tile_of,
-                             const Prefetch& prefetch, Sink<MODE, true>& sk, bool swap = false) {
+__device__ __forceinline__ void run_lds_unit(const Args& a, const Src& src, bool dist, double e2,
+                                             const LdsLayout& L, int c, const TileOf& tile_of,
+                                             const Prefetch& prefetch, Sink<MODE, true>& sk,
+                                             bool swap = false) {
     constexpr int E = NT * Q;
     const int tid = threadIdx.x;
     if (c > TC) {  // more tiles than the LDS tile table holds: cannot happen
@@ -654,8 +719,8 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
             const int k = L.tk[e];
             const uint32_t g = isR ? L.rg[k] + (uint32_t)e - L.rl[k]
                                    : L.sg[k] + (uint32_t)(e - NR) - L.sl[k];
-            pb[q] = (isR ? a.entR : a.entS)[g];
-            pi[q] = (isR ? a.idR : a.idS)[g];
+            pb[q] = (isR ? src.entR : src.entS)[g];
+            pi[q] = (isR ? src.idR : src.idS)[g];
             pg[q] = g;
         }
     }
@@ -760,11 +825,11 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
                 float4 b = L.bx[e];
                 if (swap) b = make_float4(b.y, b.x, b.w, b.z);
                 if (e < NR) {
-                    a.entR[pg[q]] = b;
-                    a.idR[pg[q]] = L.id[e];
+                    src.entR[pg[q]] = b;
+                    src.idR[pg[q]] = L.id[e];
                 } else {
-                    a.entS[pg[q]] = b;
-                    a.idS[pg[q]] = L.id[e];
+                    src.entS[pg[q]] = b;
+                    src.idS[pg[q]] = L.id[e];
                 }
             }
         }
@@ -875,8 +940,8 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const LdsLayout& L, 
                 const float4 q4 = L.bx[j];
                 const uint32_t qid = L.id[j];
                 const bool f = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
-                hit[0] = f && (!a.dist || within_eps(pb4, q4, a.e2));
-                if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
+                hit[0] = f && (!dist || within_eps(pb4, q4, e2));
+                if (MODE != kWrite) sk.cand += (dist && f) ? 1u : 0u;
                 const bool isR = p < NR;
                 er[0] = (isR ? pid : qid) & kIdMask;
                 es[0] = (isR ? qid : pid) & kIdMask;
@@ -966,7 +1031,7 @@ typedef float vf4 __attribute__((ext_vector_type(4)));  // a box held in registe
 // so that no instruction here waits for a load) and its entries
 // e = tid + q * NT.
 template <int NT, int Q>
-__device__ __forceinline__ void span_issue(const Args& a, int tid, const uint4& sp, const uint2& ut,
+__device__ __forceinline__ void span_issue(const Src& a, int tid, const uint4& sp, const uint2& ut,
                                            uint32_t& tr, uint32_t& ts, vf4 (&pb)[Q],
                                            uint32_t (&pi)[Q]) {
     if (tid <= (int)ut.y) {
@@ -1016,6 +1081,7 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
     // entries would wait for the entries too.
     uint4 rsp = make_uint4(0, 0, 0, 0);
     uint2 rut = make_uint2(0, 0);
+    uint32_t rjob = 0;
     int i0 = 0;
     auto load_records = [&](int base) {
         i0 = base;
@@ -1023,17 +1089,21 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
         if (uu < nu) {
             rsp = a.uspan[uu];
             rut = a.units[uu];
+            if (a.batch) rjob = a.ujob[uu];
         }
     };
-    auto record = [&](int i, uint4& s, uint2& t) {  // i0 <= i < i0 + kWave
+    auto record = [&](int i, uint4& s, uint2& t, uint32_t& j) {  // i0 <= i < i0 + kWave
         const int l = i - i0;
         s = make_uint4(__builtin_amdgcn_readlane(rsp.x, l), __builtin_amdgcn_readlane(rsp.y, l),
                        __builtin_amdgcn_readlane(rsp.z, l), __builtin_amdgcn_readlane(rsp.w, l));
         t = make_uint2(__builtin_amdgcn_readlane(rut.x, l), __builtin_amdgcn_readlane(rut.y, l));
+        j = a.batch ? __builtin_amdgcn_readlane(rjob, l) : 0u;
     };
-    // staged unit: record, this thread's table words and entries (in flight)
+    auto src_for = [&](uint32_t j) { return a.batch ? src_of(a.jobs[j]) : src_of(a); };
+    // staged unit: record, join, this thread's table words and entries (in flight)
     uint4 sp = make_uint4(0, 0, 0, 0);
     uint2 ut = make_uint2(0, 0);
+    uint32_t sjob = 0;
     uint32_t tr = 0, ts = 0;
     vf4 pb[Q];
     uint32_t pi[Q];
@@ -1041,17 +1111,20 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
     int i = 0;
     if (u < nu) {
         load_records(0);
-        record(0, sp, ut);
-        span_issue<NT, Q>(a, tid, sp, ut, tr, ts, pb, pi);
+        record(0, sp, ut, sjob);
+        span_issue<NT, Q>(src_for(sjob), tid, sp, ut, tr, ts, pb, pi);
     }
     for (; u < nu; u += G, ++i) {
         const uint4 cur = sp;
+        const uint32_t cjob = sjob;
+        const JobFlags jf = flags_of(a, cjob);
         const int NR = (int)cur.y, NE = (int)(cur.y + cur.w), c = (int)ut.y;
         if (NE > E || c < 1 || c >= NT) {  // cannot happen for units built by k_classify
             if (tid == 0) atomicOr(&a.st->flags, kStatInternal);
             break;
         }
         sk.begin(a, u);  // per-unit count / output region; thread 0 clears the accumulator
+        if (MODE == kAppend) sk.set_job(a.jobs[cjob]);
         // 1. tile table and sort keys (the writing pass reads slabs left sorted)
         if (tid <= c) {
             L.rl[tid] = (uint16_t)(tr - cur.x);
@@ -1108,20 +1181,21 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
         // the staged registers are free: start the next unit's loads
         if (u + G < nu) {
             if (i + 1 - i0 >= kWave) load_records(i + 1);
-            record(i + 1, sp, ut);
-            span_issue<NT, Q>(a, tid, sp, ut, tr, ts, pb, pi);
+            record(i + 1, sp, ut, sjob);
+            span_issue<NT, Q>(src_for(sjob), tid, sp, ut, tr, ts, pb, pi);
         }
         __syncthreads();
         if (MODE == kCount && a.writeback) {  // slabs left sorted for the writing pass
+            const Src cs = src_for(cjob);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int e = tid + q * NT;
                 if (e < NR) {
-                    a.entR[cur.x + e] = L.bx[e];
-                    a.idR[cur.x + e] = L.id[e];
+                    cs.entR[cur.x + e] = L.bx[e];
+                    cs.idR[cur.x + e] = L.id[e];
                 } else if (e < NE) {
-                    a.entS[cur.z + (e - NR)] = L.bx[e];
-                    a.idS[cur.z + (e - NR)] = L.id[e];
+                    cs.entS[cur.z + (e - NR)] = L.bx[e];
+                    cs.idS[cur.z + (e - NR)] = L.id[e];
                 }
             }
         }
@@ -1205,8 +1279,8 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
                     const float4 q4 = L.bx[j];
                     const uint32_t qid = L.id[j];
                     const bool f = (pb4.y <= q4.w) && (q4.y <= pb4.w) && ref_point_here(pid, qid);
-                    hit[0] = f && (!a.dist || within_eps(pb4, q4, a.e2));
-                    if (MODE != kWrite) sk.cand += (a.dist && f) ? 1u : 0u;
+                    hit[0] = f && (!jf.dist || within_eps(pb4, q4, jf.e2));
+                    if (MODE != kWrite) sk.cand += (jf.dist && f) ? 1u : 0u;
                     const bool isR = p < NR;
                     er[0] = (isR ? pid : qid) & kIdMask;
                     es[0] = (isR ? qid : pid) & kIdMask;
@@ -1215,7 +1289,7 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
             }
         }
         // 5. unit end: counts / remaining staged pairs, then LDS is free
-        if (MODE == kWrite && sk.n) sk.flush(a);
+        if ((MODE == kWrite || MODE == kAppend) && sk.n) sk.flush(a);
         if (MODE == kCount) {
             uint32_t v = sk.cnt;
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
@@ -1251,9 +1325,10 @@ constexpr int kClassChunk = kClassNT * kClassPer;
 __device__ __forceinline__ void append_dense(const Args& a, uint32_t t, uint32_t nr, uint32_t ns) {
     const uint32_t d = atomicAdd(&a.ctr[kDenseCount], 1u);
     const uint32_t base = atomicAdd(&a.ctr[kDenseEntries], nr + ns);
-    if (d < (uint32_t)a.cap_dense && (int64_t)base + nr + ns <= a.cap_dent)
+    if (d < (uint32_t)a.cap_dense && (int64_t)base + nr + ns <= a.cap_dent) {
         a.dense[d] = make_uint4(t, base, nr, ns);
-    else
+        if (a.batch) a.djob[d] = a.jid;
+    } else
         atomicOr(&a.st->flags, kStatCapacity);
 }
 
@@ -1417,6 +1492,7 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
                 --ui;
                 a.uspan[ui] = make_uint4(oR[q + 1], rend - oR[q + 1], oS[q + 1], send - oS[q + 1]);
                 a.units[ui] = make_uint2((uint32_t)t, (uint32_t)(te - t));
+                if (a.batch) a.ujob[ui] = a.jid;
             }
             if ((cutm >> q) & 1u) next = (uint32_t)(tl0 + q);
         }
@@ -1428,6 +1504,7 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
         const uint32_t nr = oR[q + 2] - oR[q + 1], ns = oS[q + 2] - oS[q + 1];
         if (t < a.C && nr && ns && nr + ns > SC && nr + ns <= (uint32_t)a.med_cap) {
             if (a.axis_model) a.medt[mi] = (uint32_t)t;
+            if (a.batch) a.mjob[mi] = a.jid;
             a.med[mi++] = make_uint4(oR[q + 1], nr, oS[q + 1], ns);
         }
     }
@@ -1625,6 +1702,11 @@ __global__ __launch_bounds__(kAxisNT) void k_axis(Args a) {
     uint32_t nt = 0, ny = 0;
     for (uint32_t j = blockIdx.x; j < nm + nd; j += gridDim.x) {
         const bool med = j < nm;
+        const uint32_t job = a.batch ? (med ? a.mjob[j] : a.djob[j - nm]) : 0u;
+        if (a.batch && !(a.jobs[job].flags & kJobAxis)) continue;  // (uniform per block)
+        const Src src = a.batch ? src_of(a.jobs[job]) : src_of(a);
+        const GridDev gd = a.batch ? a.jobs[job].gd : a.gd;
+        const Blocking bl = a.batch ? a.jobs[job].bl : a.bl;
         const uint4 rec = med ? a.med[j] : a.dense[j - nm];
         uint32_t t, nr, ns, r0, s0;
         if (med) {
@@ -1635,15 +1717,15 @@ __global__ __launch_bounds__(kAxisNT) void k_axis(Args a) {
             ns = rec.w;
         } else {
             t = rec.x;
-            r0 = a.offR[t];
+            r0 = src.offR[t];
             nr = rec.z;
-            s0 = a.offS[t];
+            s0 = src.offS[t];
             ns = rec.w;
         }
         int tx, ty;
-        blocked_xy(a.bl, t, tx, ty);
-        const AxisOut o = axis_eval(a.entR + r0, a.idR + r0, nr, a.entS + s0, a.idS + s0, ns, tx, ty,
-                                    a.gd, L);
+        blocked_xy(bl, t, tx, ty);
+        const AxisOut o = axis_eval(src.entR + r0, src.idR + r0, nr, src.entS + s0, src.idS + s0, ns,
+                                    tx, ty, gd, L);
         if (threadIdx.x == 0) {
             ++nt;
             if (o.iy < o.ix) {
@@ -1705,6 +1787,10 @@ __global__ __launch_bounds__(NT) void k_lds_medium(Args a) {
     if (blockIdx.x < nu) pf = a.med[blockIdx.x];
     for (uint32_t u = blockIdx.x; u < nu; u += G) {
         const int64_t slot = a.base_med + u;
+        const uint32_t job = a.batch ? a.mjob[u] : 0u;
+        const JobFlags jf = flags_of(a, job);
+        const Src src = a.batch ? src_of(a.jobs[job]) : src_of(a);
+        if (MODE == kAppend) sk.set_job(a.jobs[job]);
         uint4 c0 = pf;
         const bool swap = (c0.y & kAxisBit) != 0;  // sweeping axis in bit 31 of the R count
         c0.y &= ~kAxisBit;
@@ -1713,7 +1799,8 @@ __global__ __launch_bounds__(NT) void k_lds_medium(Args a) {
             if (un < nu) pf = a.med[un];
         };
         sk.begin(a, slot);
-        run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int, int) { return c0; }, prefetch, sk, swap);
+        run_lds_unit<NT, Q, TC, MODE>(a, src, jf.dist, jf.e2, L, 1, [&](int, int) { return c0; },
+                                      prefetch, sk, swap);
         sk.end(a, slot);
     }
     sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
@@ -1739,7 +1826,8 @@ __global__ __launch_bounds__(NT) void k_plain_tiles(Args a) {
         }
         const uint4 ti = make_uint4(a.offR[t], nr, a.offS[t], ns);
         sk.begin(a, t);
-        run_lds_unit<NT, Q, TC, MODE>(a, L, 1, [&](int, int) { return ti; }, [] {}, sk);
+        run_lds_unit<NT, Q, TC, MODE>(a, src_of(a), a.dist, a.e2, L, 1, [&](int, int) { return ti; },
+                                      [] {}, sk);
         sk.end(a, t);
     }
     sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
@@ -1774,22 +1862,25 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
     const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
     for (uint32_t seg = blockIdx.x; seg < 2 * nd; seg += gridDim.x) {
         const uint4 dd = a.dense[seg >> 1];
+        const uint32_t job = a.batch ? a.djob[seg >> 1] : 0u;
+        const Src sj = a.batch ? src_of(a.jobs[job]) : src_of(a);
+        const bool gbda = flags_of(a, job).gbda != 0;
         const bool sideS = seg & 1;
         const bool swap = (dd.x & kAxisBit) != 0;  // swept along y: sort by y_l
         const uint32_t tile = dd.x & ~kAxisBit;
-        const uint32_t src = sideS ? a.offS[tile] : a.offR[tile];
+        const uint32_t src = sideS ? sj.offS[tile] : sj.offR[tile];
         const uint32_t L = sideS ? dd.w : dd.z;
         const uint32_t dst = dd.y + (sideS ? dd.z : 0u);
-        const float4* ent = sideS ? a.entS : a.entR;
-        const uint32_t* eid = sideS ? a.idS : a.idR;
+        const float4* ent = sideS ? sj.entS : sj.entR;
+        const uint32_t* eid = sideS ? sj.idS : sj.idR;
         // key: (GBDA class,) order key of the lower edge, position
         auto key_of = [&](uint32_t i) -> unsigned long long {
             const unsigned long long ok = order_key(lower_edge(ent[src + i], swap));
-            return a.gbda ? ((unsigned long long)gbda_class(eid[src + i]) << 62) | (ok << 30) | i
-                          : (ok << 32) | i;
+            return gbda ? ((unsigned long long)gbda_class(eid[src + i]) << 62) | (ok << 30) | i
+                        : (ok << 32) | i;
         };
-        const unsigned long long pos_mask = a.gbda ? 0x3FFFFFFFull : 0xFFFFFFFFull;
-        if (a.gbda) {  // class group starts of this list
+        const unsigned long long pos_mask = gbda ? 0x3FFFFFFFull : 0xFFFFFFFFull;
+        if (gbda) {  // class group starts of this list
             if (threadIdx.x < 4) s_cls[threadIdx.x] = 0u;
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < L; i += blockDim.x)
@@ -1881,7 +1972,8 @@ __global__ __launch_bounds__(1024) void k_dense_plan(Args a) {
         if (d < nd) {
             const uint4 dd = a.dense[d];
             const uint32_t n = dd.z + dd.w;
-            if (a.gbda) {
+            const JobFlags jf = flags_of(a, a.batch ? a.djob[d] : 0u);
+            if (jf.gbda) {
                 // units of the 9 mini-joins (R class X x S class Y), each split
                 // into ranges of split_tau pivots; units before each in dmj
                 const uint32_t* g = a.dgrp + (size_t)d * 10;
@@ -1890,11 +1982,11 @@ __global__ __launch_bounds__(1024) void k_dense_plan(Args a) {
                     mj[j] = v;
                     const int X = kMiniJoin[j][0], Y = kMiniJoin[j][1];
                     const uint32_t nx = g[X + 1] - g[X], ny = g[5 + Y + 1] - g[5 + Y];
-                    if (nx && ny) v += (nx + ny + (uint32_t)a.split_tau - 1u) / (uint32_t)a.split_tau;
+                    if (nx && ny) v += (nx + ny + (uint32_t)jf.split_tau - 1u) / (uint32_t)jf.split_tau;
                 }
                 mj[9] = v;
             } else {
-                v = a.plain ? 1u : (n + (uint32_t)a.split_tau - 1u) / (uint32_t)a.split_tau;
+                v = jf.plain ? 1u : (n + (uint32_t)jf.split_tau - 1u) / (uint32_t)jf.split_tau;
             }
         }
         uint32_t inc = v;
@@ -2001,10 +2093,13 @@ __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
         }
         const uint4 dd = a.dense[lo];
         const int64_t slot = a.base_dense + u;
+        const uint32_t job = a.batch ? a.djob[lo] : 0u;
+        const JobFlags jf = flags_of(a, job);
         sk.begin(a, slot);
+        if (MODE == kAppend) sk.set_job(a.jobs[job]);
         if (threadIdx.x == 0) s_next = 0u;
         __syncthreads();
-        if (a.gbda) {
+        if (jf.gbda) {
             // mini-join j of the tile and its range of pivots
             const uint32_t r = u - a.dprefix[lo];
             const uint32_t* mj = a.dmj + (size_t)lo * 10;
@@ -2013,19 +2108,19 @@ __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
             const int X = kMiniJoin[jm][0], Y = kMiniJoin[jm][1];
             const uint32_t* g = a.dgrp + (size_t)lo * 10;
             const int nx = (int)(g[X + 1] - g[X]), ny = (int)(g[5 + Y + 1] - g[5 + Y]);
-            const int p0 = (int)(r - mj[jm]) * a.split_tau;
-            const int p1 = min(p0 + a.split_tau, nx + ny);
+            const int p0 = (int)(r - mj[jm]) * jf.split_tau;
+            const int p1 = min(p0 + jf.split_tau, nx + ny);
             GbdaAcc acc{a.dbox, a.didf, (int)(dd.y + g[X]), nx, (int)(dd.y + dd.z + g[5 + Y]), ny};
-            sweep_pivots<MODE, true, false>(a, acc, p0, p1, &s_next, sk);
+            sweep_pivots<MODE, true, false>(a, acc, p0, p1, &s_next, sk, jf.dist, jf.e2);
         } else {
             const int n = (int)(dd.z + dd.w);
             int p0 = 0, p1 = n;
-            if (!a.plain) {
-                p0 = (int)(u - a.dprefix[lo]) * a.split_tau;
-                p1 = min(p0 + a.split_tau, n);
+            if (!jf.plain) {
+                p0 = (int)(u - a.dprefix[lo]) * jf.split_tau;
+                p1 = min(p0 + jf.split_tau, n);
             }
             GlobAcc acc{a.dbox, a.didf, (int)dd.y, (int)dd.z, (int)dd.w};
-            sweep_pivots<MODE, true>(a, acc, p0, p1, &s_next, sk);
+            sweep_pivots<MODE, true>(a, acc, p0, p1, &s_next, sk, jf.dist, jf.e2);
         }
         sk.end(a, slot);
     }
@@ -2079,6 +2174,28 @@ __global__ void k_finish(const uint32_t* ctr, DevStatus* st, const DevStatus* st
         st->n_pairs = t;
         if (!(st->flags & kStatScratch) && t != st->m_total) st->flags |= kStatInternal;
     }
+}
+
+// Batch of joins: clear the shared counters and every join's fill counter
+// and status (grid-stride over the joins).
+__global__ void k_batch_reset(uint32_t* ctr, DevStatus* st, const Job* jobs, int n_jobs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNumCtr) ctr[i] = 0u;
+    if (i == 0) *st = DevStatus{};
+    for (int j = i; j < n_jobs; j += gridDim.x * blockDim.x) {
+        *jobs[j].fill = 0ull;
+        *jobs[j].st = DevStatus{};
+    }
+}
+
+// ... and after the join: every join's pair count (its fill counter) and
+// status (its partitions' flags and the flags of the shared lists).
+__global__ void k_batch_finish(const DevStatus* st, const Job* jobs, int n_jobs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_jobs) return;
+    const Job& J = jobs[j];
+    J.st->n_pairs = *J.fill;
+    J.st->flags |= J.stR->flags | J.stS->flags | st->flags;
 }
 
 template <class F>
@@ -2184,6 +2301,7 @@ hipError_t join_pass(const Args& a0, const JoinParams& p, const JoinWork& w, hip
 }  // namespace
 
 int lds_unit_entries(int block) { return block == 128 ? 1024 : block * 4; }
+int batch_block() { return kBatchBlock; }
 int lds_unit_tiles(int block) { return block - 1; }
 int lds_medium_entries() { return kMedE; }
 int64_t classify_blocks(int64_t C) { return (C + kClassChunk - 1) / kClassChunk; }
@@ -2195,8 +2313,8 @@ int64_t join_slots(const JoinParams& p, const JoinWork& w) {
     return (p.plain ? p.C : w.cap_units + w.cap_med) + w.cap_dunits;
 }
 
-hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork& w, sj_pair* out,
-                    int64_t capacity, hipStream_t s) {
+// Kernel arguments of one join over the work lists of w.
+Args join_args(const Part& R, const Part& S, const JoinParams& p, const JoinWork& w) {
     Args a{};
     a.offR = R.off;
     a.offS = S.off;
@@ -2231,10 +2349,6 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     a.st = w.st;
     a.stR = R.st;
     a.stS = S.st;
-    a.out = (unsigned long long*)out;
-    a.capacity = out ? capacity : 0;
-    const bool single = p.single && !p.plain && !p.count_only && w.sc_nch > 0;
-    a.writeback = (!single && !p.count_only) ? 1 : 0;
     a.axis_model = (p.axis_model && !p.plain) ? 1 : 0;
     a.gbda = (p.gbda && !p.plain) ? 1 : 0;
     a.dist = p.dist ? 1 : 0;
@@ -2244,6 +2358,16 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     a.medt = w.medt;
     a.gd = R.gd;
     a.bl = R.bl;
+    return a;
+}
+
+hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork& w, sj_pair* out,
+                    int64_t capacity, hipStream_t s) {
+    Args a = join_args(R, S, p, w);
+    a.out = (unsigned long long*)out;
+    a.capacity = out ? capacity : 0;
+    const bool single = p.single && !p.plain && !p.count_only && w.sc_nch > 0;
+    a.writeback = (!single && !p.count_only) ? 1 : 0;
     if (single) {
         a.sc_buf = w.sc_buf;
         a.sc_fills = w.sc_fills;
@@ -2310,6 +2434,100 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, s, w.ctr, w.st, R.st, S.st,
                        single ? w.sc_total : nullptr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batch of joins.  The classification of every join appends its records,
+// tagged with the join's index, to one set of work lists; one sequence of
+// join launches consumes the records of all joins (the joins' units are the
+// work queue of the persistent workgroups), and each pair goes straight to
+// its join's output region (kAppend).
+// ---------------------------------------------------------------------------
+namespace {
+Args batch_args(BatchWork& b, int n_jobs) {
+    Args a{};
+    JoinWork& w = b.w;
+    a.batch = 1;
+    a.jobs = b.jobs;
+    a.ujob = b.ujob;
+    a.mjob = b.mjob;
+    a.djob = b.djob;
+    a.uspan = w.uspan;
+    a.units = w.units;
+    a.med = w.med;
+    a.medt = w.medt;
+    a.dense = w.dense;
+    a.dprefix = w.dense_unit_prefix;
+    a.cap_units = w.cap_units;
+    a.cap_med = w.cap_med;
+    a.cap_dense = w.cap_dense;
+    a.cap_dent = w.cap_dent;
+    a.cap_dunits = w.cap_dunits;
+    a.dbox = w.dbox;
+    a.didf = w.didf;
+    a.dtmp = w.dtmp;
+    a.dgrp = w.dgrp;
+    a.dmj = w.dmj;
+    a.ctr = w.ctr;
+    a.st = w.st;
+    (void)n_jobs;
+    return a;
+}
+}  // namespace
+
+hipError_t batch_reset(BatchWork& b, int n_jobs, hipStream_t s) {
+    const int nb = std::max(1, std::min(64, (n_jobs + 255) / 256));
+    hipLaunchKernelGGL(k_batch_reset, dim3(nb), dim3(256), 0, s, b.w.ctr, b.w.st, b.jobs, n_jobs);
+    return hipGetLastError();
+}
+
+hipError_t batch_classify(BatchWork& b, const Part& R, const Part& S, const JoinParams& p,
+                          uint32_t jid, hipStream_t s) {
+    Args a = join_args(R, S, p, b.w);
+    a.batch = 1;
+    a.jid = jid;
+    a.jobs = b.jobs;
+    a.ujob = b.ujob;
+    a.mjob = b.mjob;
+    a.djob = b.djob;
+    ProfRange pr("k_classify", s);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)classify_blocks(p.C)), dim3(kClassNT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, int64_t units_bound,
+                      int64_t med_bound, hipStream_t s) {
+    Args a = batch_args(b, n_jobs);
+    const int ncu = b.w.num_cus;
+    if (any_axis) {
+        ProfRange pr("k_axis", s);
+        hipLaunchKernelGGL(k_axis, dim3(ncu * 4), dim3(kAxisNT), 0, s, a);
+    }
+    {
+        ProfRange pr("k_dense_sort", s);
+        hipLaunchKernelGGL(k_dense_sort, dim3(ncu * 2), dim3(kDenseSortNT), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_dense_plan, dim3(1), dim3(1024), 0, s, a);
+    hipError_t e;
+    {
+        ProfRange pr("k_span_units_batch", s);
+        e = launch_small<kAppend>(a, kBatchBlock, std::min<int64_t>(units_bound, b.w.cap_units), ncu, s);
+        if (e != hipSuccess) return e;
+    }
+    {
+        ProfRange pr("k_lds_medium_batch", s);
+        e = launch_medium<kMedNT, kMedE / kMedNT, kAppend>(a, std::min<int64_t>(med_bound, b.w.cap_med),
+                                                           ncu, s);
+        if (e != hipSuccess) return e;
+    }
+    {
+        ProfRange pr("k_dense_sweep_batch", s);
+        hipLaunchKernelGGL(k_dense_sweep<kAppend>, dim3(ncu * 4), dim3(kDenseNT), 0, s, a);
+    }
+    if (n_jobs > 0)
+        hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)((n_jobs + 255) / 256)), dim3(256), 0, s,
+                           b.w.st, b.jobs, n_jobs);
     return hipGetLastError();
 }
 

@@ -123,6 +123,35 @@ struct Part {
     DevStatus* st = nullptr;
 };
 
+// ---------------------------------------------------------------------------
+// One join of a batch as the shared join kernels see it (device memory,
+// 256 bytes).  Every work record of a batch (span unit, medium tile, dense
+// tile) carries its join's index into an array of these; a kernel that
+// pipelines its loads reads a record's descriptor one lane per word and
+// takes fields with readlane where it needs them.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kJobAxis = 1u, kJobGbda = 2u, kJobDist = 4u;
+struct __attribute__((aligned(256))) Job {
+    const uint32_t* offR;       // tile offsets of the two partitions
+    const uint32_t* offS;
+    float4* entR;               // tile slabs: boxes ...
+    float4* entS;
+    uint32_t* idR;              // ... and id words
+    uint32_t* idS;
+    unsigned long long* out;    // this join's output region: pairs (r | s << 32)
+    unsigned long long* fill;   // pairs found so far = next output position
+    DevStatus* st;              // this join's status
+    const DevStatus* stR;       // partition status of the two inputs
+    const DevStatus* stS;
+    int64_t capacity;           // pairs the output region holds
+    double e2;                  // distance join: keep dx*dx + dy*dy <= e2
+    int32_t split_tau;          // pivots per dense unit
+    uint32_t flags;             // kJobAxis | kJobGbda | kJobDist
+    GridDev gd;                 // grid and blocking of the two partitions
+    Blocking bl;
+};
+static_assert(sizeof(Job) == 256, "a job descriptor is 64 words");
+
 // Implemented in partition.hip
 int64_t scan_block_sums_needed(int64_t C);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -196,6 +225,26 @@ struct JoinWork {
 
 hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork& w,
                     sj_pair* out, int64_t capacity, hipStream_t s);
+
+// Work lists shared by the joins of a batch (join.hip): the classification
+// of every join appends records tagged with the join's index, one sequence
+// of join launches consumes them all (capacities: sums over the joins).
+struct BatchWork {
+    JoinWork w;                 // lists, counters and dense buffers
+    uint32_t* ujob = nullptr;   // [cap_ujob] join of each span unit
+    uint32_t* mjob = nullptr;   // [cap_mjob] ... medium tile
+    uint32_t* djob = nullptr;   // [cap_djob] ... dense tile
+    int64_t cap_ujob = 0, cap_mjob = 0, cap_djob = 0;
+    Job* jobs = nullptr;        // [cap_jobs] device descriptors
+    unsigned long long* fill = nullptr;  // [cap_jobs] pairs found per join
+    int64_t cap_jobs = 0, cap_fill = 0;
+};
+int batch_block();  // the small-tile workgroup shape of a batch
+hipError_t batch_reset(BatchWork& b, int n_jobs, hipStream_t s);
+hipError_t batch_classify(BatchWork& b, const Part& R, const Part& S, const JoinParams& p,
+                          uint32_t jid, hipStream_t s);
+hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, int64_t units_bound,
+                      int64_t med_bound, hipStream_t s);
 int64_t join_slots(const JoinParams& p, const JoinWork& w);
 hipError_t join_stats(const JoinWork& w, bool single, sj_join_stats* out);
 // Eq. (2) for the listed tiles (device: n x (tx, ty) int32 in, n x 4 int64

@@ -133,3 +133,33 @@ def test_empty_batch():
     st, n = b.run()
     assert st == sj.SJ_OK and len(n) == 0
     b.free()
+
+
+def test_batch_full_size_256_joins_element_by_element():
+    """The many-join workload at its real sizes: 256 joins, n per side
+    log-uniform in [1e3, 2e6] (1.4e8 rectangles), grids chosen per join.  A
+    count-only batch sizes the output slices, then every join's pair list
+    equals the oracle's PBSM on the same grid, element by element, and so do
+    the counts of a second replay."""
+    n = 256
+    say("full-size batch: generating", n, "joins")
+    host = [datagen.batch_instance(j)[:2] for j in range(n)]
+    dev = [(to_dev(R), to_dev(S)) for R, S in host]
+    say("count-only batch")
+    counting = sj.Batch(dev)
+    st, counts = counting.run()
+    counting.free()
+    assert st == sj.SJ_OK
+    b = sj.Batch(dev, capacities=[int(c) for c in counts])
+    st, npairs = b.run()
+    assert st == sj.SJ_OK and list(npairs) == list(counts)
+    ks, _ = b.grids()
+    for j, (R, S) in enumerate(host):
+        if j % 32 == 0:
+            say("full-size batch: oracle join", j, "K", int(ks[j]))
+        ref = oracle.pbsm(R, S, int(ks[j]))
+        got = sort_pairs(b.pairs(j, npairs[j]).cpu().numpy())
+        assert np.array_equal(got, ref), j
+    st, again = b.run()
+    assert st == sj.SJ_OK and list(again) == list(npairs)
+    b.free()
