@@ -159,6 +159,28 @@ sj_status sj_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
 /* As sj_join, counting |J| without writing pairs. */
 sj_status sj_join_count(const sj_part* R, const sj_part* S, int64_t* n_pairs, void* stream);
 
+/*
+ * Both phases in one call (Sec. 3.4 steps 1-6): sj_partition of R and of S
+ * on grid g, then sj_join, with one status readback (one stream
+ * synchronisation) for the whole sequence instead of one per call.  The
+ * partitions' buffers are sized from bounds (and from earlier calls on the
+ * same handles); the kernels check every capacity on the device, and when a
+ * partition outgrows its buffers they grow and the sequence runs again.
+ *   R, S        nR / nS x 4 float32 AoS, device, 16-byte aligned.
+ *   g           a resolved grid (1 <= k <= SJ_K_MAX; choose one first with
+ *               sj_choose_grid for the learned / rule choice); SJ_PLAIN is
+ *               rejected (SJ_ERR_ARG).
+ *   pr, ps      partition handles as in sj_partition (*p == NULL: created;
+ *               else reused).  On return they hold the two partitions; on
+ *               error handles created by the call are freed and *pr, *ps
+ *               are left as they were.
+ *   out         device buffer of `capacity` pairs; NULL: count only.
+ *   n_pairs     host; receives |J| (SJ_ERR_CAPACITY if it exceeds capacity).
+ */
+sj_status sj_join_rects(const float* R, int64_t nR, const float* S, int64_t nS, const sj_grid* g,
+                        sj_part** pr, sj_part** ps, sj_pair* out, int64_t capacity,
+                        int64_t* n_pairs, void* stream);
+
 /* Entries (rectangle-tile assignments) and rectangles of a partitioned input. */
 sj_status sj_part_info(const sj_part* P, int64_t* n_rects, int64_t* n_entries, sj_grid* g);
 
@@ -270,6 +292,17 @@ sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t*
 sj_status sj_batch_run(sj_batch* batch, int64_t* n_pairs, void* stream);
 /* The grid of every join (k and split_tau; 0 = library default). */
 sj_status sj_batch_info(const sj_batch* batch, int32_t* k, int32_t* split_tau);
+/* One run of the batch without the recorded graph: the same kernels,
+ * launched one by one (so that per-kernel timers see them), with the same
+ * results and status as sj_batch_run. */
+sj_status sj_batch_run_eager(sj_batch* batch, int64_t* n_pairs, void* stream);
+/* Entries of every partition of the last run (host arrays of 2 n_joins, the
+ * R sides then the S sides, either may be NULL): m1 coarse-cell entries,
+ * m tile entries (each rectangle counted once per tile it meets). */
+sj_status sj_batch_entries(const sj_batch* batch, int64_t* m1, int64_t* m);
+/* Work statistics of the batch's last run, summed over its joins (fields as
+ * sj_last_join_stats; pairs_* per work class).  Synchronises the device.
+ * Declared with sj_join_stats below. */
 void sj_batch_free(sj_batch* batch);
 /* One-shot: create (which runs every join), report, free. */
 sj_status sj_batch_join(int32_t n_joins, const float* const* R, const int64_t* nR,
@@ -299,6 +332,7 @@ typedef struct {
 } sj_join_stats;
 
 sj_status sj_last_join_stats(sj_join_stats* out);
+sj_status sj_batch_stats(const sj_batch* batch, sj_join_stats* out);
 
 /*
  * Canonical order of a result set (Sec. 1 defines J as a set; this gives it

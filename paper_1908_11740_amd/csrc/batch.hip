@@ -9,15 +9,18 @@
 //     medium tiles, dense tiles), tagged with the join's index, to one set
 //     of work lists shared by the whole batch;
 //   * then, once, the join launches over the shared lists: persistent
-//     workgroups take the work units of all joins (round-robin over the
-//     lists, which each join's classification filled with its own records),
-//     and every pair goes straight to its join's output region at a
-//     position reserved on the join's fill counter.
+//     workgroups take the work units of all joins (round-robin over stripes
+//     of consecutive records, which mostly belong to one join); the waves
+//     stage pairs into scratch chunks that each hold the pairs of one join,
+//     and a compaction moves every chunk to its join's output region at a
+//     position reserved on the join's fill counter (count-only batches add
+//     per-wave counts to the fill counters instead).
 // A replay is one graph launch and one status readback for the whole
 // batch.  Capacities are bounds checked on the device, as in the single-join
 // path; when a join outgrows them (new data in the same buffers) its buffers
 // grow, the shared lists are resized, the batch runs again eagerly and the
-// graph is recorded again.
+// graph is recorded again; so does the pair scratch, from the chunk counters
+// of the run that outgrew it.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -30,6 +33,10 @@
 namespace sj {
 int64_t classify_chunk_tiles();
 int lds_medium_entries();
+int scratch_totals();
+int scratch_regions();
+int scratch_chunk_pairs();
+int lds_unit_tiles(int block);
 
 namespace {
 
@@ -60,8 +67,8 @@ void free_part(Part& P) {  // st belongs to the batch's status array
 void free_work(BatchWork& bw) {
     JoinWork& w = bw.w;
     void* bufs[] = {w.uspan, w.units, w.med, w.medt, w.dense, w.dense_unit_prefix, w.dgrp, w.dmj,
-                    w.dbox, w.didf, w.dtmp, w.ctr, w.st, bw.ujob, bw.mjob, bw.djob, bw.jobs,
-                    bw.fill};
+                    w.dbox, w.didf, w.dtmp, w.ctr, w.st, w.sc_total, w.sc_buf, w.sc_fills,
+                    w.sc_ctr, bw.ujob, bw.mjob, bw.djob, bw.jobs, bw.fill, bw.sc_job};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     bw = BatchWork{};
@@ -85,7 +92,7 @@ JoinParams batch_join_params(const sj_grid& g, bool count_only) {
     const int E = 4 * p.block;
     p.small_cap = E / 4;
     p.unit_cap = E - p.small_cap;
-    p.unit_tiles = p.block - 1;
+    p.unit_tiles = lds_unit_tiles(p.block);
     p.med_cap = lds_medium_entries();
     return p;
 }
@@ -110,6 +117,7 @@ struct sj_batch {
     sj::DevStatus* hst = nullptr;  // pinned mirror
     sj::BatchWork bw;              // the shared work lists and the job descriptors
     int64_t units_bound = 0, med_bound = 0;
+    int64_t need_sc_nch = 0;  // scratch chunks per region a run needed (0: none yet)
     bool any_axis = false;
     hipStream_t ls[sj::kLanes] = {};
     hipEvent_t fork = nullptr, done[sj::kLanes] = {};
@@ -208,6 +216,20 @@ sj_status prepare_all(sj_batch* b) {
             return from_hip_err(e);
         w.cap_dent = c1;
     }
+    if (!b->count_only) {
+        int64_t pairs = 0;
+        for (int j = 0; j < b->n; ++j) pairs += cap_of(b, j);
+        const int64_t regions = scratch_regions(), cp = scratch_chunk_pairs();
+        const int64_t nch = std::max(b->need_sc_nch,
+                                     batch_scratch_chunks(pairs, units, med, b->num_cus));
+        int64_t cap_ctr = w.sc_ctr ? regions : 0;
+        if ((e = grow_buf(w.sc_buf, w.cap_sc_pairs, regions * nch * cp)) != hipSuccess ||
+            (e = grow_buf(w.sc_fills, w.cap_sc_fills, regions * nch)) != hipSuccess ||
+            (e = grow_buf(bw.sc_job, bw.cap_sc_job, regions * nch)) != hipSuccess ||
+            (e = grow_buf(w.sc_ctr, cap_ctr, regions)) != hipSuccess)
+            return from_hip_err(e);
+        w.sc_nch = nch;
+    }
     if ((e = grow_buf(bw.jobs, bw.cap_jobs, (int64_t)jobs.size())) != hipSuccess ||
         (e = grow_buf(bw.fill, bw.cap_fill, (int64_t)jobs.size())) != hipSuccess)
         return from_hip_err(e);
@@ -237,7 +259,7 @@ hipError_t enqueue_all(sj_batch* b, hipStream_t s) {
         if ((e = hipEventRecord(b->done[l], b->ls[l])) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(s, b->done[l], 0)) != hipSuccess) return e;
     }
-    return batch_join(b->bw, b->n, b->any_axis, b->units_bound, b->med_bound, s);
+    return batch_join(b->bw, b->n, b->any_axis, !b->count_only, b->units_bound, b->med_bound, s);
 }
 
 hipError_t read_all(sj_batch* b, hipStream_t s) {
@@ -251,6 +273,7 @@ hipError_t read_all(sj_batch* b, hipStream_t s) {
 // grow and the batch run again.
 sj_status check(sj_batch* b, bool* again) {
     *again = false;
+    bool scratch = false;
     const int n = b->n;
     for (int j = 0; j < n; ++j) {
         const DevStatus& r = b->hst[j];
@@ -276,6 +299,15 @@ sj_status check(sj_batch* b, bool* again) {
         // the shared lists are sized from bounds of the partitions' capacities,
         // so they overflow only after a partition did (re-sized above)
         if (q.flags & kStatCapacity) *again = true;
+        scratch = scratch || (q.flags & kStatScratch);
+    }
+    if (scratch) {
+        // the waves that found the scratch full stopped reserving, so the
+        // counters undercount: at least double
+        int64_t used = 0;
+        if (batch_scratch_used(b->bw, &used) != hipSuccess) return SJ_ERR_DEVICE;
+        b->need_sc_nch = std::max(2 * b->bw.w.sc_nch, used + used / 4 + 2);
+        *again = true;
     }
     return SJ_OK;
 }
@@ -413,6 +445,9 @@ sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t*
         if (grow_buf(w.ctr, cap, 16, true) != hipSuccess) return fail(SJ_ERR_OOM);
         cap = 0;
         if (grow_buf(w.st, cap, 1, true) != hipSuccess) return fail(SJ_ERR_OOM);
+        cap = 0;
+        if (grow_buf(w.sc_total, cap, (int64_t)scratch_totals(), true) != hipSuccess)
+            return fail(SJ_ERR_OOM);
     }
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
         return fail(SJ_ERR_DEVICE);
@@ -497,6 +532,49 @@ sj_status sj_batch_run(sj_batch* b, int64_t* n_pairs, void* stream) {
         if (!b->count_only && np > cap_of(b, j)) over = true;
     }
     return over ? SJ_ERR_CAPACITY : SJ_OK;
+}
+
+sj_status sj_batch_run_eager(sj_batch* b, int64_t* n_pairs, void* stream) {
+    if (!b) return SJ_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (b->n == 0) return SJ_OK;
+    if (enqueue_all(b, s) != hipSuccess || read_all(b, s) != hipSuccess) return SJ_ERR_DEVICE;
+    bool again = false;
+    sj_status st = check(b, &again);
+    if (st != SJ_OK) return st;
+    if (again) {
+        st = settle(b, s);
+        if (st != SJ_OK) return st;
+    }
+    bool over = false;
+    for (int j = 0; j < b->n; ++j) {
+        const int64_t np = (int64_t)b->hst[2 * b->n + j].n_pairs;
+        if (n_pairs) n_pairs[j] = np;
+        if (!b->count_only && np > cap_of(b, j)) over = true;
+    }
+    return over ? SJ_ERR_CAPACITY : SJ_OK;
+}
+
+sj_status sj_batch_stats(const sj_batch* b, sj_join_stats* o) {
+    if (!b || !o) return SJ_ERR_ARG;
+    std::memset(o, 0, sizeof(*o));
+    if (hipDeviceSynchronize() != hipSuccess) return SJ_ERR_DEVICE;
+    if (join_stats(b->bw.w, true, o) != hipSuccess) return SJ_ERR_DEVICE;
+    for (int j = 0; j < b->n; ++j) o->n_pairs += (int64_t)b->hst[2 * b->n + j].n_pairs;
+    const int E = 4 * batch_block();  // entries of a span unit
+    o->single_pass = 1;
+    o->small_cap = E / 4;
+    o->med_cap = lds_medium_entries();
+    return SJ_OK;
+}
+
+sj_status sj_batch_entries(const sj_batch* b, int64_t* m1, int64_t* m) {
+    if (!b) return SJ_ERR_ARG;
+    for (int i = 0; i < 2 * b->n; ++i) {
+        if (m1) m1[i] = (int64_t)b->hst[i].m1_total;
+        if (m) m[i] = (int64_t)b->hst[i].m_total;
+    }
+    return SJ_OK;
 }
 
 sj_status sj_batch_info(const sj_batch* b, int32_t* k, int32_t* split_tau) {

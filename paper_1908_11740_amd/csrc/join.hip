@@ -68,6 +68,9 @@ static_assert(kMedEntries == kSmallEntries + 1 && kSmallEntries % 2 == 0, "stati
 
 constexpr int kWaveBuf = 256;        // staged pairs per wave (>= 64 lanes x kCand)
 constexpr int kUnitWaveBuf = 128;    // LDS units emit one candidate per lane and call
+constexpr int kSpanWaveBuf = 96;     // ... span units (LDS holds their tile tables)
+constexpr int kSpanTQ = 2;           // tile-table words per thread: span units of
+                                     // up to kSpanTQ * NT - 1 tiles
 constexpr int kMedNT = 512;          // workgroup of the medium-tile kernel
 constexpr int kBatchBlock = 256;     // small-tile workgroup of a batch of joins
 constexpr int kMedE = 2048;          // LDS entries of a medium tile
@@ -132,6 +135,7 @@ struct Args {
     uint32_t* ujob;               // join of each span unit
     uint32_t* mjob;               // ... medium tile
     uint32_t* djob;               // ... dense tile
+    uint32_t* sc_job;             // join of each scratch chunk (single pass)
 };
 
 // One join's tile offsets and slabs: from the arguments (single join) or
@@ -188,6 +192,17 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
 
 __device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
 
+// The i-th work unit of workgroup g of G: round-robin over stripes of S
+// consecutive units.  S = 1 for a single join; a batch uses longer stripes,
+// since consecutive units mostly belong to one join and a wave then rarely
+// changes joins.  Increasing in i.
+__device__ __forceinline__ uint32_t unit_of(uint32_t i, uint32_t g, uint32_t G, uint32_t S) {
+    return ((i / S) * G + g) * S + i % S;
+}
+constexpr uint32_t kSpanStripe = 16;  // batch stripes: span units
+constexpr uint32_t kMedStripe = 2;    // ... medium tiles
+constexpr uint32_t kDenseStripe = 1;  // ... dense units
+
 // ---------------------------------------------------------------------------
 // Pair sink.  Three modes:
 //   kCount   per-lane counters, reduced into the unit's slot of the count
@@ -201,11 +216,14 @@ __device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_AC
 //            serialises); chunk fill levels are compacted into the caller's
 //            buffer afterwards.  Every hit is counted even if the scratch
 //            runs out, so the exact count is always known.
-//   kAppend  batch of joins: per-wave LDS staging flushed at the end of every
-//            unit (and when full) straight into the output region of the
-//            unit's join, at a position reserved with one 64-bit atomic on
-//            the join's fill counter; pairs past its capacity are counted,
-//            not stored.  No scratch and no compaction.
+//   kAppend  batch of joins, count only: per-lane counters, added to the
+//            fill counter of the join with one atomic per wave whenever the
+//            wave moves on to a unit of another join, and at the end.
+// In a batch of joins, kSingle keeps one open scratch chunk per wave for the
+// join of its current unit: the staged pairs are flushed and the chunk is
+// closed when the wave moves on to a unit of another join, so a chunk holds
+// the pairs of one join (tagged in sc_job); the compaction places every
+// chunk into its join's output region with one atomic per chunk.
 // BLOCK: the unit is processed by a whole workgroup (end() has barriers);
 // otherwise by one wavefront.
 // ---------------------------------------------------------------------------
@@ -227,9 +245,7 @@ struct Sink {
     bool have, ok;
     unsigned long long total;       // hits seen by this wave (kSingle)
     uint32_t cand;                  // this lane's filter pairs (distance join; not kWrite)
-    unsigned long long* jout;       // kAppend: the current unit's join: output region,
-    unsigned long long* jfill;      //   fill counter,
-    int64_t jcap;                   //   capacity
+    uint32_t cjob;                  // batch: the join of the current unit
 
     __device__ void init(uint32_t wave_gid) {
         n = 0;
@@ -242,37 +258,47 @@ struct Sink {
         ok = true;
         total = 0;
         cand = 0;
-        jout = nullptr;
-        jfill = nullptr;
-        jcap = 0;
+        cjob = 0;
     }
 
-    // kAppend: the join whose pairs the following units emit
-    __device__ void set_job(const Job& j) {
-        jout = j.out;
-        jfill = j.fill;
-        jcap = j.capacity;
+    // Batch, every lane of the wave: the join of the following units.  On a
+    // change, the pairs of the previous join leave the wave: kAppend adds
+    // its count to the join's fill counter, kSingle flushes the staged pairs
+    // and closes the open chunk.
+    __device__ void set_job(const Args& a, uint32_t j) {
+        if (j == cjob) return;
+        if (MODE == kAppend) {
+            drain_count(a);
+        } else if (MODE == kSingle) {
+            if (n) flush(a);
+            if (have && lane_id() == 0) a.sc_fills[(size_t)region * a.sc_nch + chunk] = cfill;
+            have = false;
+        }
+        cjob = j;
+    }
+
+    // kAppend: the wave's count of the current join into its fill counter
+    __device__ void drain_count(const Args& a) {
+        uint32_t v = cnt;
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+        if (lane_id() == 0 && v) atomicAdd(a.jobs[cjob].fill, (unsigned long long)v);
+        total += v;
+        cnt = 0;
     }
 
     __device__ void begin(const Args& a, int64_t slot) {
-        cnt = 0;
+        if (MODE != kAppend) cnt = 0;
         if (MODE != kSingle) n = 0;
         if (MODE == kWrite) {
             base = a.ucnt[slot];
             cfill = 0;
         }
-        if (MODE != kSingle && BLOCK && threadIdx.x == 0) *s_acc = 0u;
+        if ((MODE == kCount || MODE == kWrite) && BLOCK && threadIdx.x == 0) *s_acc = 0u;
     }
 
     __device__ void flush(const Args& a) {
         lds_fence();
-        if (MODE == kAppend) {
-            unsigned long long b = 0;
-            if (lane_id() == 0) b = atomicAdd(jfill, (unsigned long long)n);
-            b = __shfl(b, 0, kWave);
-            for (uint32_t q = lane_id(); q < n; q += kWave)
-                if (b + q < (unsigned long long)jcap) jout[b + q] = buf[q];
-        } else if (MODE == kWrite) {
+        if (MODE == kWrite) {
             uint32_t b = cfill;  // one wave per unit: a register counter
             if (BLOCK) {
                 if (lane_id() == 0) b = atomicAdd(s_acc, n);
@@ -290,7 +316,10 @@ struct Sink {
                     if (have && lane_id() == 0)
                         a.sc_fills[(size_t)region * a.sc_nch + chunk] = (uint32_t)kChunkP;
                     uint32_t k = 0;
-                    if (lane_id() == 0) k = atomicAdd(&a.sc_ctr[region], 1u);
+                    if (lane_id() == 0) {
+                        k = atomicAdd(&a.sc_ctr[region], 1u);
+                        if (a.batch && (int64_t)k < a.sc_nch) a.sc_job[(size_t)region * a.sc_nch + k] = cjob;
+                    }
                     k = __shfl(k, 0, kWave);
                     have = true;
                     chunk = k;
@@ -319,7 +348,7 @@ struct Sink {
     template <int N>
     __device__ __forceinline__ void emit(const Args& a, const bool (&hit)[N], const uint32_t (&r)[N],
                                          const uint32_t (&s)[N]) {
-        if (MODE == kCount) {
+        if (MODE == kCount || MODE == kAppend) {
 #pragma unroll
             for (int k = 0; k < N; ++k) cnt += hit[k] ? 1u : 0u;
             return;
@@ -344,7 +373,7 @@ struct Sink {
     }
 
     __device__ void end(const Args& a, int64_t slot) {
-        if (MODE == kWrite || MODE == kAppend) {
+        if (MODE == kWrite) {
             if (n) flush(a);
         } else if (MODE == kCount) {
             uint32_t v = cnt;
@@ -369,10 +398,11 @@ struct Sink {
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
             if (lane_id() == 0 && v) atomicAdd(&a.st->n_cand, v);
         }
-        if (MODE != kSingle) return;
+        if (MODE != kSingle && MODE != kAppend) return;
+        if (MODE == kAppend) drain_count(a);
         if (n) flush(a);
         if (lane_id() == 0) {
-            if (have && ok) a.sc_fills[(size_t)region * a.sc_nch + chunk] = cfill;
+            if (MODE == kSingle && have && ok) a.sc_fills[(size_t)region * a.sc_nch + chunk] = cfill;
             if (total) atomicAdd(&a.sc_total[a.cls * kTotalsPer + wave_gid % kTotalsPer], total);
         }
     }
@@ -967,10 +997,10 @@ __device__ __forceinline__ void run_lds_unit(const Args& a, const Src& src, bool
 // barriers: table and keys staged, boxes sorted, LDS free again.
 // ---------------------------------------------------------------------------
 struct SpanLayout {
-    unsigned long long* wbuf;  // [NT / 64 * kUnitWaveBuf] pair staging per wave
+    unsigned long long* wbuf;  // [NT / 64 * kSpanWaveBuf] pair staging per wave
     uint32_t* acc;             // [0] sink accumulator
-    uint16_t* rl;              // [NT] local start of each tile's R segment (count + 1 used)
-    uint16_t* sl;              // [NT] ... of its S segment
+    uint16_t* rl;              // [kSpanTQ * NT] local start of each tile's R segment (c + 1 used)
+    uint16_t* sl;              // [kSpanTQ * NT] ... of its S segment
     float4* bx;                // [E] sorted boxes (R part, then S part)
     uint32_t* id;              // [E] sorted id words
     uint32_t* key;             // [E + 8] sort keys; then per wave the candidate prefix
@@ -978,20 +1008,20 @@ struct SpanLayout {
 };
 
 __host__ __device__ constexpr size_t span_lds_bytes(int nt, int e) {
-    return (size_t)(nt / kWave) * kUnitWaveBuf * 8 + 16 + (size_t)nt * 4 +  // staging, acc, tables
+    return (size_t)(nt / kWave) * kSpanWaveBuf * 8 + 16 + (size_t)kSpanTQ * nt * 4 +  // staging, acc, tables
            (size_t)e * 16 + (size_t)e * 4 + (size_t)(e + 8) * 4 + (size_t)e * 2;
 }
 
 __device__ inline SpanLayout carve_span(unsigned char* p, int nt, int e) {
     SpanLayout L;
     L.wbuf = (unsigned long long*)p;
-    p += (size_t)(nt / kWave) * kUnitWaveBuf * 8;
+    p += (size_t)(nt / kWave) * kSpanWaveBuf * 8;
     L.acc = (uint32_t*)p;
     p += 16;
     L.rl = (uint16_t*)p;
-    p += (size_t)nt * 2;
+    p += (size_t)kSpanTQ * nt * 2;
     L.sl = (uint16_t*)p;
-    p += (size_t)nt * 2;  // nt is a multiple of 64: the boxes stay 16-byte aligned
+    p += (size_t)kSpanTQ * nt * 2;  // nt is a multiple of 64: the boxes stay 16-byte aligned
     L.bx = (float4*)p;
     p += (size_t)e * 16;
     L.id = (uint32_t*)p;
@@ -1026,17 +1056,21 @@ __device__ __forceinline__ int segment_of(const uint16_t* T, int c, int v) {
 
 typedef float vf4 __attribute__((ext_vector_type(4)));  // a box held in registers
 
-// Issue the loads of a staged span unit: thread tid's words of the tile
-// offset tables (raw: made local to the spans only when the unit is staged,
-// so that no instruction here waits for a load) and its entries
+// Issue the loads of a staged span unit: thread tid's words t = tid + k * NT
+// of the tile offset tables (raw: made local to the spans only when the unit
+// is staged, so that no instruction here waits for a load) and its entries
 // e = tid + q * NT.
 template <int NT, int Q>
 __device__ __forceinline__ void span_issue(const Src& a, int tid, const uint4& sp, const uint2& ut,
-                                           uint32_t& tr, uint32_t& ts, vf4 (&pb)[Q],
-                                           uint32_t (&pi)[Q]) {
-    if (tid <= (int)ut.y) {
-        tr = a.offR[ut.x + tid];
-        ts = a.offS[ut.x + tid];
+                                           uint32_t (&tr)[kSpanTQ], uint32_t (&ts)[kSpanTQ],
+                                           vf4 (&pb)[Q], uint32_t (&pi)[Q]) {
+#pragma unroll
+    for (int k = 0; k < kSpanTQ; ++k) {
+        const int t = tid + k * NT;
+        if (t <= (int)ut.y) {
+            tr[k] = a.offR[ut.x + t];
+            ts[k] = a.offS[ut.x + t];
+        }
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -1059,7 +1093,9 @@ __host__ __device__ constexpr int span_waves(int nt, int q) {
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <int NT, int Q, int MODE>
+// BATCH: the units of a batch of joins (job records, stripes); a separate
+// instantiation, so that the single-join kernel carries none of it.
+template <int NT, int Q, int MODE, bool BATCH>
 __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
     constexpr int E = NT * Q;
     constexpr int PW = Q * kWave;  // pivots of one wavefront
@@ -1070,26 +1106,27 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
     const uint32_t nu = min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
     const uint32_t G = gridDim.x;
     Sink<MODE, true> sk;
-    sk.buf = L.wbuf + w * kUnitWaveBuf;
+    sk.buf = L.wbuf + w * kSpanWaveBuf;
     sk.s_acc = L.acc;
-    sk.bufcap = kUnitWaveBuf;
+    sk.bufcap = kSpanWaveBuf;
     sk.init(blockIdx.x * (NT / kWave) + w);
+    const uint32_t S = BATCH ? kSpanStripe : 1u;
     // Unit records of this workgroup, kWave at a time: lane l holds the record
-    // of the workgroup's unit i0 + l (unit blockIdx.x + (i0 + l) * G), read
-    // with readlane.  No memory wait falls inside the loop: vector loads
-    // retire in order, so waiting for a record loaded after the next unit's
-    // entries would wait for the entries too.
+    // of the workgroup's unit i0 + l, read with readlane.  No memory wait
+    // falls inside the loop: vector loads retire in order, so waiting for a
+    // record loaded after the next unit's entries would wait for the entries
+    // too.
     uint4 rsp = make_uint4(0, 0, 0, 0);
     uint2 rut = make_uint2(0, 0);
     uint32_t rjob = 0;
     int i0 = 0;
     auto load_records = [&](int base) {
         i0 = base;
-        const uint32_t uu = blockIdx.x + (uint32_t)(base + lane) * G;
+        const uint32_t uu = unit_of((uint32_t)(base + lane), blockIdx.x, G, S);
         if (uu < nu) {
             rsp = a.uspan[uu];
             rut = a.units[uu];
-            if (a.batch) rjob = a.ujob[uu];
+            if (BATCH) rjob = a.ujob[uu];
         }
     };
     auto record = [&](int i, uint4& s, uint2& t, uint32_t& j) {  // i0 <= i < i0 + kWave
@@ -1097,38 +1134,44 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
         s = make_uint4(__builtin_amdgcn_readlane(rsp.x, l), __builtin_amdgcn_readlane(rsp.y, l),
                        __builtin_amdgcn_readlane(rsp.z, l), __builtin_amdgcn_readlane(rsp.w, l));
         t = make_uint2(__builtin_amdgcn_readlane(rut.x, l), __builtin_amdgcn_readlane(rut.y, l));
-        j = a.batch ? __builtin_amdgcn_readlane(rjob, l) : 0u;
+        j = BATCH ? __builtin_amdgcn_readlane(rjob, l) : 0u;
     };
-    auto src_for = [&](uint32_t j) { return a.batch ? src_of(a.jobs[j]) : src_of(a); };
+    // a batch's job descriptors: scalar loads at every use (kept in
+    // registers across units, they would crowd out the sweep's)
+    auto src_for = [&](uint32_t j) { return BATCH ? src_of(a.jobs[j]) : src_of(a); };
     // staged unit: record, join, this thread's table words and entries (in flight)
     uint4 sp = make_uint4(0, 0, 0, 0);
     uint2 ut = make_uint2(0, 0);
     uint32_t sjob = 0;
-    uint32_t tr = 0, ts = 0;
+    uint32_t tr[kSpanTQ] = {}, ts[kSpanTQ] = {};
     vf4 pb[Q];
     uint32_t pi[Q];
-    uint32_t u = blockIdx.x;
+    uint32_t u = unit_of(0, blockIdx.x, G, S);
     int i = 0;
     if (u < nu) {
         load_records(0);
         record(0, sp, ut, sjob);
         span_issue<NT, Q>(src_for(sjob), tid, sp, ut, tr, ts, pb, pi);
+        sk.cjob = sjob;  // nothing staged yet
     }
-    for (; u < nu; u += G, ++i) {
+    for (; u < nu; ++i, u = unit_of((uint32_t)i, blockIdx.x, G, S)) {
         const uint4 cur = sp;
         const uint32_t cjob = sjob;
         const JobFlags jf = flags_of(a, cjob);
         const int NR = (int)cur.y, NE = (int)(cur.y + cur.w), c = (int)ut.y;
-        if (NE > E || c < 1 || c >= NT) {  // cannot happen for units built by k_classify
+        if (NE > E || c < 1 || c >= kSpanTQ * NT) {  // cannot happen for units built by k_classify
             if (tid == 0) atomicOr(&a.st->flags, kStatInternal);
             break;
         }
         sk.begin(a, u);  // per-unit count / output region; thread 0 clears the accumulator
-        if (MODE == kAppend) sk.set_job(a.jobs[cjob]);
         // 1. tile table and sort keys (the writing pass reads slabs left sorted)
-        if (tid <= c) {
-            L.rl[tid] = (uint16_t)(tr - cur.x);
-            L.sl[tid] = (uint16_t)(ts - cur.z);
+#pragma unroll
+        for (int k = 0; k < kSpanTQ; ++k) {
+            const int t = tid + k * NT;
+            if (t <= c) {
+                L.rl[t] = (uint16_t)(tr[k] - cur.x);
+                L.sl[t] = (uint16_t)(ts[k] - cur.z);
+            }
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -1179,7 +1222,7 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
             }
         }
         // the staged registers are free: start the next unit's loads
-        if (u + G < nu) {
+        if (unit_of((uint32_t)i + 1u, blockIdx.x, G, S) < nu) {
             if (i + 1 - i0 >= kWave) load_records(i + 1);
             record(i + 1, sp, ut, sjob);
             span_issue<NT, Q>(src_for(sjob), tid, sp, ut, tr, ts, pb, pi);
@@ -1213,11 +1256,11 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int p = tid + q * NT;
-                const int k = tk[q];
                 isR[q] = p < NR;
                 lo[q] = hi[q] = 0;
                 xl[q] = xu[q] = 0.f;
                 if (p < NE) {
+                    const int k = tk[q];
                     const float4 b = L.bx[p];
                     xl[q] = b.x;
                     xu[q] = b.z;
@@ -1288,8 +1331,11 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
                 sk.template emit<1>(a, hit, er, es);
             }
         }
-        // 5. unit end: counts / remaining staged pairs, then LDS is free
-        if ((MODE == kWrite || MODE == kAppend) && sk.n) sk.flush(a);
+        // 5. unit end: counts / remaining staged pairs, then LDS is free; a
+        //    batch's pairs leave the wave when the next unit (staged above)
+        //    belongs to another join
+        if (MODE == kWrite && sk.n) sk.flush(a);
+        if (BATCH && sjob != cjob) sk.set_job(a, sjob);
         if (MODE == kCount) {
             uint32_t v = sk.cnt;
             for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
@@ -1367,6 +1413,9 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
     __shared__ uint32_t s_ws[4][kClassNT / kWave];
     __shared__ uint32_t s_fc[kClassNT / kWave];  // first cut of each wave
     __shared__ uint32_t s_base[2];
+    // an input whose partition failed or overflowed holds no valid tile
+    // offsets: no work (the join's status carries its flags)
+    if ((a.stR->flags | a.stS->flags) & (kStatBadRect | kStatCapacity | kStatTooLarge)) return;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const int64_t c0 = (int64_t)blockIdx.x * kClassChunk;  // first tile of the chunk
     const int tl0 = tid * kClassPer;                        // this thread's first local tile
@@ -1783,18 +1832,20 @@ __global__ __launch_bounds__(NT) void k_lds_medium(Args a) {
     const LdsLayout L = carve(smem, NT, NT * Q, TC);
     Sink<MODE, true> sk = make_sink<MODE>(L);
     const uint32_t G = gridDim.x;
+    const uint32_t SP = a.batch ? kMedStripe : 1u;
+    uint32_t i = 0, u = unit_of(0, blockIdx.x, G, SP);
     uint4 pf = make_uint4(0, 0, 0, 0);
-    if (blockIdx.x < nu) pf = a.med[blockIdx.x];
-    for (uint32_t u = blockIdx.x; u < nu; u += G) {
+    if (u < nu) pf = a.med[u];
+    for (; u < nu; ++i, u = unit_of(i, blockIdx.x, G, SP)) {
         const int64_t slot = a.base_med + u;
         const uint32_t job = a.batch ? a.mjob[u] : 0u;
         const JobFlags jf = flags_of(a, job);
         const Src src = a.batch ? src_of(a.jobs[job]) : src_of(a);
-        if (MODE == kAppend) sk.set_job(a.jobs[job]);
+        if (a.batch) sk.set_job(a, job);
         uint4 c0 = pf;
         const bool swap = (c0.y & kAxisBit) != 0;  // sweeping axis in bit 31 of the R count
         c0.y &= ~kAxisBit;
-        const uint32_t un = u + G;
+        const uint32_t un = unit_of(i + 1, blockIdx.x, G, SP);
         auto prefetch = [&]() {
             if (un < nu) pf = a.med[un];
         };
@@ -2083,7 +2134,8 @@ __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
     sk.init(wg);
     const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
     const uint32_t nu = min(a.ctr[kDenseUnits], (uint32_t)a.cap_dunits);
-    for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+    const uint32_t G = gridDim.x, SP = a.batch ? kDenseStripe : 1u;
+    for (uint32_t i = 0, u = unit_of(0, blockIdx.x, G, SP); u < nu; ++i, u = unit_of(i, blockIdx.x, G, SP)) {
         // dense tile of unit u: last d with dprefix[d] <= u
         uint32_t lo = 0, hi = nd;
         while (hi - lo > 1) {
@@ -2096,7 +2148,7 @@ __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
         const uint32_t job = a.batch ? a.djob[lo] : 0u;
         const JobFlags jf = flags_of(a, job);
         sk.begin(a, slot);
-        if (MODE == kAppend) sk.set_job(a.jobs[job]);
+        if (a.batch) sk.set_job(a, job);
         if (threadIdx.x == 0) s_next = 0u;
         __syncthreads();
         if (jf.gbda) {
@@ -2178,13 +2230,38 @@ __global__ void k_finish(const uint32_t* ctr, DevStatus* st, const DevStatus* st
 
 // Batch of joins: clear the shared counters and every join's fill counter
 // and status (grid-stride over the joins).
-__global__ void k_batch_reset(uint32_t* ctr, DevStatus* st, const Job* jobs, int n_jobs) {
+__global__ void k_batch_reset(uint32_t* ctr, DevStatus* st, unsigned long long* totals,
+                              uint32_t* sc_ctr, const Job* jobs, int n_jobs) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kNumCtr) ctr[i] = 0u;
+    if (i < kTotals) totals[i] = 0ull;
+    if (sc_ctr && i < kRegions) sc_ctr[i] = 0u;
     if (i == 0) *st = DevStatus{};
     for (int j = i; j < n_jobs; j += gridDim.x * blockDim.x) {
         *jobs[j].fill = 0ull;
         *jobs[j].st = DevStatus{};
+    }
+}
+
+// Batch compaction: every scratch chunk reserved in the run (the first
+// sc_ctr[r] of region r) goes to the output region of its join, at a
+// position reserved with one atomic on the join's fill counter; pairs past
+// the join's capacity are counted, not stored.  One wavefront per chunk,
+// grid-strided.
+__global__ __launch_bounds__(kCompactNT) void k_compact_batch(Args a) {
+    const uint32_t per = kCompactNT / kWave;
+    const uint32_t nch = (uint32_t)(kRegions * a.sc_nch);
+    for (uint32_t g = blockIdx.x * per + threadIdx.x / kWave; g < nch; g += gridDim.x * per) {
+        const uint32_t r = g / (uint32_t)a.sc_nch, k = g % (uint32_t)a.sc_nch;
+        if (k >= a.sc_ctr[r]) continue;
+        const uint32_t f = a.sc_fills[g];
+        const Job& J = a.jobs[a.sc_job[g]];
+        unsigned long long b = 0;
+        if (lane_id() == 0) b = atomicAdd(J.fill, (unsigned long long)f);
+        b = __shfl(b, 0, kWave);
+        const unsigned long long* src = a.sc_buf + (size_t)g * kChunkP;
+        for (uint32_t q = lane_id(); q < f; q += kWave)
+            if (b + q < (unsigned long long)J.capacity) J.out[b + q] = src[q];
     }
 }
 
@@ -2240,11 +2317,11 @@ hipError_t launch_medium(const Args& a, int64_t bound, int num_cus, hipStream_t 
                              bound, num_cus, per_cu, a, s);
 }
 
-template <int NT, int Q, int MODE>
+template <int NT, int Q, int MODE, bool BATCH = false>
 hipError_t launch_span(const Args& a, int64_t bound, int num_cus, hipStream_t s) {
     static int per_cu = 0;
-    return launch_persistent(k_span_units<NT, Q, MODE>, NT, span_lds_bytes(NT, NT * Q), bound, num_cus,
-                             per_cu, a, s);
+    return launch_persistent(k_span_units<NT, Q, MODE, BATCH>, NT, span_lds_bytes(NT, NT * Q), bound,
+                             num_cus, per_cu, a, s);
 }
 
 // small-tile units: block threads and entries per unit (see lds_unit_entries)
@@ -2302,7 +2379,7 @@ hipError_t join_pass(const Args& a0, const JoinParams& p, const JoinWork& w, hip
 
 int lds_unit_entries(int block) { return block == 128 ? 1024 : block * 4; }
 int batch_block() { return kBatchBlock; }
-int lds_unit_tiles(int block) { return block - 1; }
+int lds_unit_tiles(int block) { return kSpanTQ * block - 1; }
 int lds_medium_entries() { return kMedE; }
 int64_t classify_blocks(int64_t C) { return (C + kClassChunk - 1) / kClassChunk; }
 int64_t classify_chunk_tiles() { return kClassChunk; }
@@ -2471,6 +2548,7 @@ Args batch_args(BatchWork& b, int n_jobs) {
     a.dmj = w.dmj;
     a.ctr = w.ctr;
     a.st = w.st;
+    a.sc_total = w.sc_total;  // pairs per work class
     (void)n_jobs;
     return a;
 }
@@ -2478,8 +2556,32 @@ Args batch_args(BatchWork& b, int n_jobs) {
 
 hipError_t batch_reset(BatchWork& b, int n_jobs, hipStream_t s) {
     const int nb = std::max(1, std::min(64, (n_jobs + 255) / 256));
-    hipLaunchKernelGGL(k_batch_reset, dim3(nb), dim3(256), 0, s, b.w.ctr, b.w.st, b.jobs, n_jobs);
+    hipLaunchKernelGGL(k_batch_reset, dim3(nb), dim3(256), 0, s, b.w.ctr, b.w.st, b.w.sc_total,
+                       b.w.sc_ctr, b.jobs, n_jobs);
     return hipGetLastError();
+}
+
+// Scratch chunks per region for a batch run: the pairs the outputs can hold
+// with 25% headroom, plus the partly filled chunks that waves close when
+// they move on to another join (at most one per wave and stripe, estimated
+// from the list bounds and capped: a run that outgrows the scratch reports
+// it and the batch grows the scratch from the counters).
+int64_t batch_scratch_chunks(int64_t pairs, int64_t units, int64_t med, int num_cus) {
+    const int64_t waves = (int64_t)kBatchBlock / kWave;
+    int64_t partial = waves * (units / kSpanStripe + med / kMedStripe) + 3LL * num_cus * 32;
+    partial = std::min<int64_t>(partial, 65536);
+    const int64_t full = (pairs + pairs / 4) / kChunkP;
+    return (full + partial + kRegions - 1) / kRegions + 2;
+}
+
+hipError_t batch_scratch_used(const BatchWork& b, int64_t* max_chunks) {
+    uint32_t c[kRegions];
+    *max_chunks = 0;
+    if (!b.w.sc_ctr) return hipSuccess;
+    hipError_t e = hipMemcpy(c, b.w.sc_ctr, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    for (int r = 0; r < kRegions; ++r) *max_chunks = std::max<int64_t>(*max_chunks, c[r]);
+    return hipSuccess;
 }
 
 hipError_t batch_classify(BatchWork& b, const Part& R, const Part& S, const JoinParams& p,
@@ -2496,9 +2598,17 @@ hipError_t batch_classify(BatchWork& b, const Part& R, const Part& S, const Join
     return hipGetLastError();
 }
 
-hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, int64_t units_bound,
+hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, bool pairs, int64_t units_bound,
                       int64_t med_bound, hipStream_t s) {
     Args a = batch_args(b, n_jobs);
+    pairs = pairs && b.w.sc_nch > 0;
+    if (pairs) {
+        a.sc_buf = b.w.sc_buf;
+        a.sc_fills = b.w.sc_fills;
+        a.sc_ctr = b.w.sc_ctr;
+        a.sc_nch = b.w.sc_nch;
+        a.sc_job = b.sc_job;
+    }
     const int ncu = b.w.num_cus;
     if (any_axis) {
         ProfRange pr("k_axis", s);
@@ -2510,20 +2620,37 @@ hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, int64_t units_bou
     }
     hipLaunchKernelGGL(k_dense_plan, dim3(1), dim3(1024), 0, s, a);
     hipError_t e;
+    const int64_t ub = std::min<int64_t>(units_bound, b.w.cap_units);
+    const int64_t mb = std::min<int64_t>(med_bound, b.w.cap_med);
     {
         ProfRange pr("k_span_units_batch", s);
-        e = launch_small<kAppend>(a, kBatchBlock, std::min<int64_t>(units_bound, b.w.cap_units), ncu, s);
+        a.cls = 0;
+        static_assert(kBatchBlock == 256, "the batch's span kernel is instantiated for 256 threads");
+        e = pairs ? launch_span<256, 4, kSingle, true>(a, ub, ncu, s)
+                  : launch_span<256, 4, kAppend, true>(a, ub, ncu, s);
         if (e != hipSuccess) return e;
     }
     {
         ProfRange pr("k_lds_medium_batch", s);
-        e = launch_medium<kMedNT, kMedE / kMedNT, kAppend>(a, std::min<int64_t>(med_bound, b.w.cap_med),
-                                                           ncu, s);
+        a.cls = 1;
+        e = pairs ? launch_medium<kMedNT, kMedE / kMedNT, kSingle>(a, mb, ncu, s)
+                  : launch_medium<kMedNT, kMedE / kMedNT, kAppend>(a, mb, ncu, s);
         if (e != hipSuccess) return e;
     }
     {
         ProfRange pr("k_dense_sweep_batch", s);
-        hipLaunchKernelGGL(k_dense_sweep<kAppend>, dim3(ncu * 4), dim3(kDenseNT), 0, s, a);
+        a.cls = 2;
+        if (pairs)
+            hipLaunchKernelGGL(k_dense_sweep<kSingle>, dim3(ncu * 4), dim3(kDenseNT), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_dense_sweep<kAppend>, dim3(ncu * 4), dim3(kDenseNT), 0, s, a);
+    }
+    if (pairs) {
+        ProfRange pr("k_compact_batch", s);
+        const int64_t per = kCompactNT / kWave;
+        const int64_t need = (kRegions * b.w.sc_nch + per - 1) / per;
+        hipLaunchKernelGGL(k_compact_batch, dim3((unsigned)std::min<int64_t>(need, ncu * 8)),
+                           dim3(kCompactNT), 0, s, a);
     }
     if (n_jobs > 0)
         hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)((n_jobs + 255) / 256)), dim3(256), 0, s,

@@ -104,7 +104,7 @@ bool same_grid(const sj_grid& a, const sj_grid& b) {
 
 struct DeviceState {
     JoinWork w;
-    DevStatus* host = nullptr;  // pinned
+    DevStatus* host = nullptr;  // pinned: [3] (R partition, S partition, join)
     bool init = false;
 };
 
@@ -117,7 +117,7 @@ sj_status device_state(int dev, DeviceState** out) {
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return SJ_ERR_DEVICE;
         d.w.device = dev;
         d.w.num_cus = prop.multiProcessorCount;
-        if (hipHostMalloc((void**)&d.host, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void**)&d.host, 3 * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess)
             return SJ_ERR_OOM;
         int64_t cap = 0;
         if (grow(d.w.ctr, cap, 16, true) != hipSuccess) return SJ_ERR_OOM;
@@ -367,6 +367,43 @@ sj_status check_worklists(const Part& R, const Part& S, const JoinParams& p, con
     return SJ_OK;
 }
 
+// After a join's status readback: false if it must run again (the scratch
+// of the single pass ran out although the output fits: two passes then).
+bool join_done(JoinWork& w, JoinParams& p, const DevStatus& hs, int64_t capacity) {
+    w.last_single = p.single;
+    w.last_small_cap = p.plain ? 0 : p.small_cap;
+    w.last_med_cap = p.plain ? 0 : p.med_cap;
+    if (p.single && (hs.flags & kStatScratch) && !(hs.flags & ~kStatScratch) &&
+        (int64_t)hs.n_pairs <= capacity) {
+        p.single = false;
+        return false;
+    }
+    return true;
+}
+
+// The result of a finished join from its status (partition flags folded
+// in): the error it maps to, the pair count, the optional sort.
+sj_status join_outcome(const Part& R, const Part& S, const JoinParams& p, const JoinWork& w,
+                       const DevStatus& hs, sj_pair* out, int64_t capacity, int64_t* n_pairs,
+                       bool count_only, int64_t* cand, hipStream_t s) {
+    const uint32_t flags = hs.flags;
+    if (flags & kStatTooLarge) return SJ_ERR_TOO_LARGE;
+    if (flags & (kStatInternal | kStatCapacity)) {
+        snprintf(g_err, sizeof(g_err), "join: internal status flags 0x%x", flags);
+        return SJ_ERR_DEVICE;
+    }
+    if (!p.plain && check_worklists_enabled()) {
+        sj_status st = check_worklists(R, S, p, w);
+        if (st != SJ_OK) return st;
+    }
+    *n_pairs = (int64_t)hs.n_pairs;
+    if (cand) *cand = (int64_t)hs.n_cand;
+    if (!count_only && (int64_t)hs.n_pairs > capacity) return SJ_ERR_CAPACITY;
+    if (!count_only && (R.grid.flags & SJ_SORTED_OUTPUT))
+        return sj_sort_pairs(out, *n_pairs, R.n, S.n, s);
+    return SJ_OK;
+}
+
 // e2 non-null: distance join of two partitions of anchored squares (pairs
 // with dx*dx + dy*dy <= *e2); *cand then receives the filter's pair count.
 sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capacity,
@@ -406,34 +443,138 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
             return from_hip(e);
         }
         hs = *ds->host;
-        w.last_single = p.single;
-        w.last_small_cap = p.plain ? 0 : p.small_cap;
-        w.last_med_cap = p.plain ? 0 : p.med_cap;
-        // the scratch of the single pass ran out although the output fits:
-        // join again in two passes
-        if (p.single && (hs.flags & kStatScratch) && !(hs.flags & ~kStatScratch) &&
-            (int64_t)hs.n_pairs <= capacity) {
-            p.single = false;
-            continue;
-        }
+        if (!join_done(w, p, hs, capacity)) continue;
         break;
     }
-    const uint32_t flags = hs.flags;
-    if (flags & kStatTooLarge) return SJ_ERR_TOO_LARGE;
-    if (flags & (kStatInternal | kStatCapacity)) {
-        snprintf(g_err, sizeof(g_err), "join: internal status flags 0x%x", flags);
-        return SJ_ERR_DEVICE;
+    return join_outcome(*R, *S, p, w, hs, out, capacity, n_pairs, count_only, cand, s);
+}
+
+// Partitions of both inputs and their join with one status readback (see
+// sj_join_rects): capacities are bounds, checked on the device; when a
+// partition outgrows them, its buffers grow and the sequence runs again.
+sj_status fused_join(const float* Rr, int64_t nR, const float* Sr, int64_t nS, const sj_grid* g,
+                     sj_part** pr, sj_part** ps, sj_pair* out, int64_t capacity,
+                     int64_t* n_pairs, bool count_only, hipStream_t s) {
+    if (!pr || !ps || !n_pairs || nR < 0 || nS < 0 || capacity < 0) return SJ_ERR_ARG;
+    if ((nR > 0 && !Rr) || (nS > 0 && !Sr) || (!count_only && capacity > 0 && !out))
+        return SJ_ERR_ARG;
+    if ((((uintptr_t)Rr | (uintptr_t)Sr) & 15u) != 0) return SJ_ERR_ARG;
+    if (nR >= ((int64_t)1 << 30) || nS >= ((int64_t)1 << 30)) return SJ_ERR_TOO_LARGE;
+    sj_grid grid;
+    GridDev gd;
+    sj_status rs = resolve_grid(g, grid, gd);
+    if (rs != SJ_OK) return rs;
+    if (grid.flags & SJ_PLAIN) return SJ_ERR_ARG;  // the plain schedule reads the offsets unguarded
+    int dev = 0;
+    if (current_device(&dev) != SJ_OK) return SJ_ERR_DEVICE;
+    sj_part* P[2] = {*pr, *ps};
+    const bool fresh[2] = {P[0] == nullptr, P[1] == nullptr};
+    const float* rin[2] = {Rr, Sr};
+    const int64_t nn[2] = {nR, nS};
+    auto fail = [&](sj_status e) {
+        for (int i = 0; i < 2; ++i)
+            if (fresh[i] && P[i]) sj_part_free(P[i]);
+        return e;
+    };
+    for (int i = 0; i < 2; ++i) {
+        if (!P[i]) {
+            P[i] = new (std::nothrow) sj_part();
+            if (!P[i]) return fail(SJ_ERR_OOM);
+            P[i]->device = dev;
+        } else if (P[i]->device != dev) {
+            return fail(SJ_ERR_ARG);
+        }
     }
-    if (!p.plain && check_worklists_enabled()) {
-        st = check_worklists(*R, *S, p, w);
-        if (st != SJ_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceState* ds = nullptr;
+    sj_status st = device_state(dev, &ds);
+    if (st != SJ_OK) return fail(st);
+    JoinWork& w = ds->w;
+    // the tuning key: the entries of the last run on these handles when it
+    // partitioned the same sizes on the same grid, else the rectangle counts
+    int64_t mkey[2], need_m1[2], need_m[2];
+    for (int i = 0; i < 2; ++i) {
+        Part& Q = *P[i];
+        const bool same = Q.st && Q.n == nn[i] && same_grid(Q.grid, grid) && Q.m > 0;
+        mkey[i] = same ? Q.m : nn[i];
+        need_m1[i] = std::max<int64_t>(Q.cap_m1, nn[i] + nn[i] / 4 + 4096);
+        need_m[i] = std::max<int64_t>(Q.cap_m, 2 * nn[i] + 4096);
+        if (!Q.st) {
+            int64_t cap = 0;
+            hipError_t e = grow(Q.st, cap, 1, true);
+            if (e != hipSuccess) return fail(from_hip(e));
+        }
+        Q.bl = blocking_for(gd.kx, gd.ky);
+        Q.gd = gd;
+        Q.grid = grid;
     }
-    *n_pairs = (int64_t)hs.n_pairs;
-    if (cand) *cand = (int64_t)hs.n_cand;
-    if (!count_only && (int64_t)hs.n_pairs > capacity) return SJ_ERR_CAPACITY;
-    if (!count_only && (R->grid.flags & SJ_SORTED_OUTPUT))
-        return sj_sort_pairs(out, *n_pairs, R->n, S->n, s);
-    return SJ_OK;
+    JoinParams p = tuned_params(dev, grid, mkey[0], mkey[1], count_only);
+    DevStatus hs[3] = {};
+    bool parts_done = false;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+        hipError_t e = hipSuccess;
+        if (!parts_done) {
+            for (int i = 0; i < 2; ++i) {
+                if ((e = part_prepare(*P[i], nn[i], need_m1[i], need_m[i])) != hipSuccess)
+                    return fail(from_hip(e));
+                if ((e = run_partition(*P[i], (const float4*)rin[i], nn[i], w.num_cus, s)) !=
+                    hipSuccess) {
+                    set_err("partition launch", e);
+                    return fail(from_hip(e));
+                }
+            }
+        }
+        // work lists sized from the partitions' capacities (bounds of their entries)
+        st = join_prepare(w, p, (int64_t)P[0]->bl.cells() * P[0]->bl.tiles_per_cell(),
+                          P[0]->cap_m, P[1]->cap_m, capacity);
+        if (st != SJ_OK) return fail(st);
+        e = run_join(*P[0], *P[1], p, w, count_only ? nullptr : out, count_only ? 0 : capacity, s);
+        if (e != hipSuccess) {
+            set_err("join launch", e);
+            return fail(from_hip(e));
+        }
+        // the one readback: both partitions' status and the join's
+        if ((e = hipMemcpyAsync(&ds->host[0], P[0]->st, sizeof(DevStatus), hipMemcpyDeviceToHost,
+                                s)) != hipSuccess ||
+            (e = hipMemcpyAsync(&ds->host[1], P[1]->st, sizeof(DevStatus), hipMemcpyDeviceToHost,
+                                s)) != hipSuccess ||
+            (e = hipMemcpyAsync(&ds->host[2], w.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess) {
+            set_err("status readback", e);
+            return fail(from_hip(e));
+        }
+        for (int i = 0; i < 3; ++i) hs[i] = ds->host[i];
+        bool regrow = false;
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t f = hs[i].flags;
+            if (f & kStatBadRect) return fail(SJ_ERR_RECT);
+            if (f & kStatTooLarge) return fail(SJ_ERR_TOO_LARGE);
+            if (f & kStatInternal) {
+                snprintf(g_err, sizeof(g_err), "partition: internal status flags 0x%x", f);
+                return fail(SJ_ERR_DEVICE);
+            }
+            if (f & kStatCapacity) {
+                need_m1[i] = std::max<int64_t>(need_m1[i], (int64_t)hs[i].m1_total + 1);
+                if (hs[i].m_total) need_m[i] = std::max<int64_t>(need_m[i], (int64_t)hs[i].m_total + 1);
+                regrow = true;
+            }
+        }
+        if (regrow) continue;
+        parts_done = true;
+        for (int i = 0; i < 2; ++i) {
+            P[i]->n = nn[i];
+            P[i]->m = (int64_t)hs[i].m_total;
+            P[i]->m1 = (int64_t)hs[i].m1_total;
+        }
+        if (!join_done(w, p, hs[2], capacity)) continue;
+        *pr = P[0];
+        *ps = P[1];
+        return join_outcome(*P[0], *P[1], p, w, hs[2], out, capacity, n_pairs, count_only,
+                            nullptr, s);
+    }
+    snprintf(g_err, sizeof(g_err), "fused join: buffers still too small after regrowth");
+    return fail(SJ_ERR_DEVICE);
 }
 
 
@@ -722,6 +863,13 @@ sj_status sj_tune_load(const char* path, int32_t* n_loaded) {
 
 sj_status sj_join_count(const sj_part* R, const sj_part* S, int64_t* n_pairs, void* stream) {
     return do_join(R, S, nullptr, 0, n_pairs, true, (hipStream_t)stream);
+}
+
+sj_status sj_join_rects(const float* R, int64_t nR, const float* S, int64_t nS, const sj_grid* g,
+                        sj_part** pr, sj_part** ps, sj_pair* out, int64_t capacity,
+                        int64_t* n_pairs, void* stream) {
+    return fused_join(R, nR, S, nS, g, pr, ps, out, capacity, n_pairs, out == nullptr,
+                      (hipStream_t)stream);
 }
 
 sj_status sj_part_info(const sj_part* P, int64_t* n_rects, int64_t* n_entries, sj_grid* g) {

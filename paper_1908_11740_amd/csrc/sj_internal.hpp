@@ -238,13 +238,20 @@ struct BatchWork {
     Job* jobs = nullptr;        // [cap_jobs] device descriptors
     unsigned long long* fill = nullptr;  // [cap_jobs] pairs found per join
     int64_t cap_jobs = 0, cap_fill = 0;
+    // pair scratch (the batch's joins with output): w.sc_buf / sc_fills /
+    // sc_ctr / sc_nch as in a single join, plus the join of every chunk
+    uint32_t* sc_job = nullptr;  // [cap_sc_job]
+    int64_t cap_sc_job = 0;
 };
 int batch_block();  // the small-tile workgroup shape of a batch
 hipError_t batch_reset(BatchWork& b, int n_jobs, hipStream_t s);
 hipError_t batch_classify(BatchWork& b, const Part& R, const Part& S, const JoinParams& p,
                           uint32_t jid, hipStream_t s);
-hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, int64_t units_bound,
+hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, bool pairs, int64_t units_bound,
                       int64_t med_bound, hipStream_t s);
+int64_t batch_scratch_chunks(int64_t pairs, int64_t units, int64_t med, int num_cus);
+// chunks reserved per scratch region by the last batch run (host copy)
+hipError_t batch_scratch_used(const BatchWork& b, int64_t* max_chunks);
 int64_t join_slots(const JoinParams& p, const JoinWork& w);
 hipError_t join_stats(const JoinWork& w, bool single, sj_join_stats* out);
 // Eq. (2) for the listed tiles (device: n x (tx, ty) int32 in, n x 4 int64

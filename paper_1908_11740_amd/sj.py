@@ -88,6 +88,8 @@ def lib():
         L.sj_partition.argtypes = [vp, i64, ctypes.POINTER(Grid), ctypes.POINTER(vp), vp]
         L.sj_join.argtypes = [vp, vp, vp, i64, i64p, vp]
         L.sj_join_count.argtypes = [vp, vp, i64p, vp]
+        L.sj_join_rects.argtypes = [vp, i64, vp, i64, ctypes.POINTER(Grid), ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp), vp, i64, i64p, vp]
         L.sj_part_info.argtypes = [vp, i64p, i64p, ctypes.POINTER(Grid)]
         L.sj_part_download.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_int32), vp]
         L.sj_part_free.argtypes = [vp]
@@ -125,11 +127,15 @@ def lib():
         L.sj_batch_create.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(vp), vp]
         L.sj_batch_run.argtypes = [vp, vp, vp]
+        L.sj_batch_run_eager.argtypes = [vp, vp, vp]
+        L.sj_batch_stats.argtypes = [vp, vp]
+        L.sj_batch_entries.argtypes = [vp, vp, vp]
         L.sj_batch_info.argtypes = [vp, vp, vp]
         L.sj_batch_free.argtypes = [vp]
         L.sj_batch_free.restype = None
         L.sj_batch_join.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-        for f in ("sj_batch_create", "sj_batch_run", "sj_batch_info", "sj_batch_join"):
+        for f in ("sj_batch_create", "sj_batch_run", "sj_batch_run_eager", "sj_batch_stats",
+                  "sj_batch_entries", "sj_batch_info", "sj_batch_join"):
             getattr(L, f).restype = ctypes.c_int
         L.sj_generate.argtypes = [vp, i64, vp, vp, vp, ctypes.c_int32, f32, ctypes.c_int32, f32,
                                   f32, ctypes.c_uint64, ctypes.c_uint32, vp]
@@ -275,6 +281,29 @@ def join_into(R, S, out, stream=None):
     if s not in (SJ_OK, SJ_ERR_CAPACITY):
         raise SjError(s, "sj_join")
     return s, n.value
+
+
+def join_rects(R, S, k, split_tau=0, domain=None, flags=0, out=None, parts=None, stream=None):
+    """Partition both inputs and join them with one status readback
+    (sj_join_rects).  out: (cap, 2) int32 device tensor, None = count only.
+    parts: (PR, PS) Part handles to reuse (None: created).  Returns
+    (status, n_pairs, (PR, PS)); status SJ_OK or SJ_ERR_CAPACITY."""
+    R, S = _rects(R), _rects(S)
+    g = make_grid(k, split_tau, domain, flags)
+    hr = ctypes.c_void_p(parts[0].handle if parts is not None else None)
+    hs = ctypes.c_void_p(parts[1].handle if parts is not None else None)
+    n = ctypes.c_int64()
+    cap = 0 if out is None else out.shape[0]
+    s = lib().sj_join_rects(ctypes.c_void_p(R.data_ptr() if R.numel() else None), R.shape[0],
+                            ctypes.c_void_p(S.data_ptr() if S.numel() else None), S.shape[0],
+                            ctypes.byref(g), ctypes.byref(hr), ctypes.byref(hs),
+                            ctypes.c_void_p(out.data_ptr() if cap else None), cap,
+                            ctypes.byref(n), _stream(stream))
+    if s not in (SJ_OK, SJ_ERR_CAPACITY):
+        raise SjError(s, "sj_join_rects")
+    if parts is None:
+        parts = (Part(hr.value, R.shape[0]), Part(hs.value, S.shape[0]))
+    return s, n.value, parts
 
 
 def join(R, S, capacity=None, stream=None):
@@ -506,14 +535,32 @@ class Batch:
                "sj_batch_create")
         self._h = h.value
 
-    def run(self, stream=None):
-        """Replay; returns (status, n_pairs array)."""
+    def run(self, stream=None, eager=False):
+        """Replay (eager: the same kernels launched one by one, without the
+        recorded graph); returns (status, n_pairs array)."""
         import numpy as np
         n = np.zeros(max(self.n, 1), np.int64)
-        s = lib().sj_batch_run(self._h, n.ctypes.data_as(ctypes.c_void_p), _stream(stream))
+        f = lib().sj_batch_run_eager if eager else lib().sj_batch_run
+        s = f(self._h, n.ctypes.data_as(ctypes.c_void_p), _stream(stream))
         if s not in (SJ_OK, SJ_ERR_CAPACITY):
             raise SjError(s, "sj_batch_run")
         return s, n[:self.n]
+
+    def entries(self):
+        """(m1, m): coarse-cell and tile entries of every partition of the
+        last run, arrays of 2n (R sides, then S sides)."""
+        import numpy as np
+        m1 = np.zeros(max(2 * self.n, 1), np.int64)
+        m = np.zeros(max(2 * self.n, 1), np.int64)
+        _check(lib().sj_batch_entries(self._h, m1.ctypes.data_as(ctypes.c_void_p),
+                                      m.ctypes.data_as(ctypes.c_void_p)), "sj_batch_entries")
+        return m1[:2 * self.n], m[:2 * self.n]
+
+    def stats(self):
+        """Work statistics of the last run, summed over the joins (dict)."""
+        st = JoinStats()
+        _check(lib().sj_batch_stats(self._h, ctypes.byref(st)), "sj_batch_stats")
+        return {f: getattr(st, f) for f, _ in JoinStats._fields_}
 
     def grids(self):
         import numpy as np

@@ -60,6 +60,14 @@ def test_batch_pairs_match_oracle_and_replays(joins):
     for rep in range(3):
         st, n = b.run()
         _check_batch(b, js, refs, st, n)
+    # the same kernels launched one by one, and the work statistics
+    b.out.fill_(-1)
+    st, n = b.run(eager=True)
+    _check_batch(b, js, refs, st, n)
+    stats = b.stats()
+    assert stats["n_pairs"] == sum(len(r) for r in refs)
+    assert stats["pairs_small"] + stats["pairs_medium"] + stats["pairs_dense"] == stats["n_pairs"]
+    assert stats["small_units"] > 0 and stats["small_entries"] > 0
     b.free()
 
 
