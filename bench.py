@@ -291,8 +291,9 @@ def bench_batch(args, pk, sj, torch):
         "config": {"workload": WORKLOADS["batch256"], "joins": n, "rects": nrects,
                    "grid_choice": "learned" if use_learned else "rule",
                    "grid_k_min": int(ks.min()), "grid_k_max": int(ks.max()),
-                   "schedule": "one recorded graph: partitions and classification per join on 4 "
-                               "streams, one set of join launches over the units of all joins",
+                   "schedule": "one recorded graph: each partitioning launch and the "
+                               "classification run the workgroups of all joins, then one set of "
+                               "join launches over the work units of all joins",
                    "mode": "pairs"},
         "pairs_per_s": round(P / (ms * 1e-3), 1), "n_pairs": P,
         "pairs_match_oracle_count": verified, "median_ms_per_step": round(statistics.median(times) * 1e3, 4),

@@ -412,6 +412,8 @@ typedef struct {
     int32_t tau_learned;   /* the picker's split threshold (0 if not used)       */
     int32_t used_learned;  /* 1 if the picker chose                              */
     double mean_x_extent;  /* mean over R and S of w (the 1-D rule's statistic)  */
+    int32_t k_cap;         /* largest K chosen for a 2-D grid: floor(sqrt(8 (nR + nS)))
+                              clamped to [1, SJ_K_MAX]; SJ_K_MAX with SJ_STRIPES     */
 } sj_choice;
 
 /* The rule's K for a mean extent e (domain units): clamp(round(1/(10 e)),
@@ -431,6 +433,8 @@ sj_status sj_features(const float* R, int64_t nR, const float* S, int64_t nS, co
  * Fill in g->k when it is 0 and g->split_tau when it is 0: with the loaded
  * picker unless g->flags has SJ_RULE_ONLY, else with the rule (the split
  * threshold then stays 0 = library default).  Non-zero fields are kept.
+ * A chosen 2-D K is at most k_cap = floor(sqrt(8 (nR + nS))): the per-tile
+ * arrays cost O(K^2) whatever the input size.
  * With SJ_STRIPES the rule is the 1-D one, k = clamp(round(1 / (10 e_x)),
  * 1, SJ_K_MAX) from the mean x-extent e_x, and the picker is not used.
  * info (host, may be NULL) receives the statistics and both choices.

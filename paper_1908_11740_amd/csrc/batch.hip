@@ -2,12 +2,16 @@
 //
 // Tiles are independent tasks (Sec. 3.4); so are whole joins.  A batch
 // plans every join once -- grid choice (learned picker or rule), buffer
-// capacities, a longest-processing-time assignment of the joins to a few
-// streams -- and records one hipGraph per batch:
-//   * on the streams, each join's two partitions and its classification,
-//     which appends the join's work records (span units of small tiles,
-//     medium tiles, dense tiles), tagged with the join's index, to one set
-//     of work lists shared by the whole batch;
+// capacities, the workgroups of every partition in the batched launches --
+// and records one hipGraph per batch:
+//   * the partitioning sequence once for all 2n inputs: every launch runs
+//     the workgroups of all partitions (each finds its partition in a prefix
+//     of the per-partition workgroup counts), then one classification
+//     launch over all joins, which appends every join's work records (span
+//     units of small tiles, medium tiles, dense tiles), tagged with the
+//     join's index, to one set of work lists shared by the whole batch
+//     (inputs too large for the batched scans run per join instead, on a
+//     few streams, longest first);
 //   * then, once, the join launches over the shared lists: persistent
 //     workgroups take the work units of all joins (round-robin over stripes
 //     of consecutive records, which mostly belong to one join); the waves
@@ -116,6 +120,10 @@ struct sj_batch {
     sj::DevStatus* dst = nullptr;  // [3n]: R partitions, S partitions, joins
     sj::DevStatus* hst = nullptr;  // pinned mirror
     sj::BatchWork bw;              // the shared work lists and the job descriptors
+    sj::PartBatch pb;              // all partitions as one set of launches
+    uint32_t* cls_pre = nullptr;   // device [n + 1]: classification workgroups per join, prefix
+    uint32_t cls_blocks = 0;
+    bool fused = false;            // partitions and classification batched (else per join on lanes)
     int64_t units_bound = 0, med_bound = 0;
     int64_t need_sc_nch = 0;  // scratch chunks per region a run needed (0: none yet)
     bool any_axis = false;
@@ -184,6 +192,7 @@ sj_status prepare_all(sj_batch* b) {
         J.flags = (p.axis_model ? kJobAxis : 0u) | (p.gbda ? kJobGbda : 0u);
         J.gd = R.gd;
         J.bl = R.bl;
+        J.C = p.C;
     }
     b->units_bound = units;
     b->med_bound = med;
@@ -238,6 +247,42 @@ sj_status prepare_all(sj_batch* b) {
         (e = hipMemcpy(bw.jobs, jobs.data(), sizeof(Job) * (size_t)b->n, hipMemcpyHostToDevice)) !=
             hipSuccess)
         return from_hip_err(e);
+    // all partitions and classifications as single launches when every
+    // partition's scans take the direct form (else each join on its lane)
+    b->fused = b->n > 0;
+    for (int j = 0; j < b->n && b->fused; ++j)
+        b->fused = part_batchable(b->R[j], b->nr[j]) && part_batchable(b->S[j], b->ns[j]);
+    if (b->fused) {
+        std::vector<Part*> parts;
+        std::vector<const float4*> rects;
+        std::vector<int64_t> ns;
+        for (int j = 0; j < b->n; ++j) {
+            parts.push_back(&b->R[j]);
+            rects.push_back(b->rin[j]);
+            ns.push_back(b->nr[j]);
+            parts.push_back(&b->S[j]);
+            rects.push_back(b->sin[j]);
+            ns.push_back(b->ns[j]);
+        }
+        if ((e = part_batch_plan(b->pb, parts.data(), rects.data(), ns.data(), (int)parts.size(),
+                                 b->num_cus)) != hipSuccess)
+            return from_hip_err(e);
+        std::vector<uint32_t> pre((size_t)b->n + 1, 0u);
+        int64_t acc = 0;
+        for (int j = 0; j < b->n; ++j) {
+            pre[(size_t)j] = (uint32_t)acc;
+            acc += classify_blocks(b->jp[j].C);
+        }
+        if (acc >= ((int64_t)1 << 31)) return SJ_ERR_TOO_LARGE;
+        pre[(size_t)b->n] = (uint32_t)acc;
+        b->cls_blocks = (uint32_t)acc;
+        if (b->cls_pre) (void)hipFree(b->cls_pre);
+        b->cls_pre = nullptr;
+        if ((e = hipMalloc((void**)&b->cls_pre, sizeof(uint32_t) * pre.size())) != hipSuccess ||
+            (e = hipMemcpy(b->cls_pre, pre.data(), sizeof(uint32_t) * pre.size(),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return from_hip_err(e);
+    }
     return SJ_OK;
 }
 
@@ -246,6 +291,14 @@ sj_status prepare_all(sj_batch* b) {
 hipError_t enqueue_all(sj_batch* b, hipStream_t s) {
     hipError_t e;
     if ((e = batch_reset(b->bw, b->n, s)) != hipSuccess) return e;
+    if (b->fused) {
+        if ((e = run_partition_batch(b->pb, s)) != hipSuccess ||
+            (e = batch_classify_all(b->bw, b->jp[0], b->cls_pre, b->n, b->cls_blocks, s)) !=
+                hipSuccess)
+            return e;
+        return batch_join(b->bw, b->n, b->any_axis, !b->count_only, b->units_bound, b->med_bound,
+                          s);
+    }
     if ((e = hipEventRecord(b->fork, s)) != hipSuccess) return e;
     for (int l = 0; l < kLanes; ++l) {
         if ((e = hipStreamWaitEvent(b->ls[l], b->fork, 0)) != hipSuccess) return e;
@@ -372,6 +425,8 @@ void destroy(sj_batch* b) {
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->dst) (void)hipFree(b->dst);
     if (b->hst) (void)hipHostFree(b->hst);
+    if (b->cls_pre) (void)hipFree(b->cls_pre);
+    part_batch_free(b->pb);
     delete b;
 }
 

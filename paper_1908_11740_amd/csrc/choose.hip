@@ -392,7 +392,16 @@ sj_status sj_choose_grid(const float* R, int64_t nR, const float* S, int64_t nS,
         return SJ_ERR_DEVICE;
     const ChooseOut o = *c->host;
     if (o.invalid) return SJ_ERR_RECT;
-    if (g->k == 0) g->k = learned ? o.k_pick : (stripes ? o.k_rule_x : o.k_rule);
+    // a K x K grid costs O(K^2) per pass whatever the input size, so a chosen
+    // 2-D grid keeps K^2 <= 8 (nR + nS): the fastest measured grid of every
+    // picker-corpus instance has fewer tiles than that, and inputs far smaller
+    // than the corpus's (a batch's small joins) get no grid of mostly empty tiles
+    int32_t kcap = SJ_K_MAX;
+    if (!stripes) {
+        const double c = std::floor(std::sqrt(8.0 * (double)(nR + nS)));
+        kcap = (int32_t)std::max(1.0, std::min(c, (double)SJ_K_MAX));
+    }
+    if (g->k == 0) g->k = std::min(learned ? o.k_pick : (stripes ? o.k_rule_x : o.k_rule), kcap);
     if (g->split_tau == 0 && learned) g->split_tau = o.tau_pick;
     if (info) {
         info->mean_extent = o.ebar;
@@ -401,6 +410,7 @@ sj_status sj_choose_grid(const float* R, int64_t nR, const float* S, int64_t nS,
         info->k_learned = learned ? o.k_pick : 0;
         info->tau_learned = learned ? o.tau_pick : 0;
         info->used_learned = learned ? 1 : 0;
+        info->k_cap = kcap;
     }
     return SJ_OK;
 }

@@ -1408,7 +1408,7 @@ __device__ __forceinline__ void block_excl4(uint32_t (&v)[4], uint32_t (&tot)[4]
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
+__device__ __forceinline__ void classify_body(const Args& a, uint32_t blk) {
     __shared__ uint16_t s_j[kClassChunk + 1];  // joinable small tiles before each tile of the chunk
     __shared__ uint32_t s_ws[4][kClassNT / kWave];
     __shared__ uint32_t s_fc[kClassNT / kWave];  // first cut of each wave
@@ -1417,7 +1417,7 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
     // offsets: no work (the join's status carries its flags)
     if ((a.stR->flags | a.stS->flags) & (kStatBadRect | kStatCapacity | kStatTooLarge)) return;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-    const int64_t c0 = (int64_t)blockIdx.x * kClassChunk;  // first tile of the chunk
+    const int64_t c0 = (int64_t)blk * kClassChunk;  // first tile of the chunk
     const int tl0 = tid * kClassPer;                        // this thread's first local tile
     const int64_t t0 = c0 + tl0;
     const uint32_t SC = (uint32_t)a.small_cap, B = (uint32_t)a.unit_cap;
@@ -1557,6 +1557,25 @@ __global__ __launch_bounds__(kClassNT) void k_classify(Args a) {
             a.med[mi++] = make_uint4(oR[q + 1], nr, oS[q + 1], ns);
         }
     }
+}
+
+__global__ __launch_bounds__(kClassNT) void k_classify(Args a) { classify_body(a, blockIdx.x); }
+
+// Every join of a batch in one launch: the workgroups of join j classify its
+// grid's chunks (job_slot over the prefix of their counts).
+__global__ __launch_bounds__(kClassNT) void k_classify_b(Args a, const uint32_t* __restrict__ pre,
+                                                         int nj) {
+    const JobSlot t = job_slot(pre, nj);
+    const Job& J = a.jobs[t.j];
+    Args b = a;
+    b.offR = J.offR;
+    b.offS = J.offS;
+    b.stR = J.stR;
+    b.stS = J.stS;
+    b.C = J.C;
+    b.jid = (uint32_t)t.j;
+    b.axis_model = (J.flags & kJobAxis) ? 1 : 0;
+    classify_body(b, t.wg);
 }
 
 // ---------------------------------------------------------------------------
@@ -2595,6 +2614,36 @@ hipError_t batch_classify(BatchWork& b, const Part& R, const Part& S, const Join
     a.djob = b.djob;
     ProfRange pr("k_classify", s);
     hipLaunchKernelGGL(k_classify, dim3((unsigned)classify_blocks(p.C)), dim3(kClassNT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_classify_all(BatchWork& b, const JoinParams& p, const uint32_t* pre, int n_jobs,
+                              uint32_t blocks, hipStream_t s) {
+    if (n_jobs == 0 || blocks == 0) return hipSuccess;
+    Args a{};
+    JoinWork& w = b.w;
+    a.batch = 1;
+    a.jobs = b.jobs;
+    a.ujob = b.ujob;
+    a.mjob = b.mjob;
+    a.djob = b.djob;
+    a.small_cap = p.small_cap;
+    a.unit_cap = p.unit_cap;
+    a.med_cap = p.med_cap;
+    a.unit_tiles = p.unit_tiles;
+    a.uspan = w.uspan;
+    a.units = w.units;
+    a.med = w.med;
+    a.medt = w.medt;
+    a.dense = w.dense;
+    a.cap_units = w.cap_units;
+    a.cap_med = w.cap_med;
+    a.cap_dense = w.cap_dense;
+    a.cap_dent = w.cap_dent;
+    a.ctr = w.ctr;
+    a.st = w.st;
+    ProfRange pr("k_classify", s);
+    hipLaunchKernelGGL(k_classify_b, dim3(blocks), dim3(kClassNT), 0, s, a, pre, n_jobs);
     return hipGetLastError();
 }
 

@@ -28,7 +28,9 @@
 // Every kernel checks the status word first and does nothing if an earlier
 // stage reported a bad rectangle or a full buffer; the host then grows the
 // buffers (sizes are reported in the status) and runs the partition again.
+#include <algorithm>
 #include <cstdlib>
+#include <vector>
 
 #include "sj_internal.hpp"
 #include "sj_prof.hpp"
@@ -97,13 +99,18 @@ __device__ __forceinline__ Cells cells_of(float4 a, const GridDev& g) {
 // ---------------------------------------------------------------------------
 // Level 1
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ rects, int64_t n,
-                                                    GridDev g, Blocking bl, int64_t ch1,
-                                                    uint32_t* __restrict__ h1,
-                                                    DevStatus* __restrict__ st) {
-    extern __shared__ uint32_t hist[];  // [G1]
+__device__ __forceinline__ void l1_count_body(const float4* __restrict__ rects,
+    int64_t n,
+    GridDev g,
+    Blocking bl,
+    int64_t ch1,
+    uint32_t* __restrict__ h1,
+    DevStatus* __restrict__ st,
+    uint32_t* hist,
+    uint32_t wg,
+    uint32_t nwg) {
     const int64_t nb = (n + ch1 - 1) / ch1;  // chunks (the grid is rounded up to whole XCD rows)
-    const int64_t q = xcd_slot(blockIdx.x, gridDim.x);
+    const int64_t q = xcd_slot(wg, nwg);
     if (q >= nb) return;
     const int G1 = bl.cells();
     for (int i = threadIdx.x; i < G1; i += blockDim.x) hist[i] = 0u;
@@ -132,16 +139,30 @@ __global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ r
     for (int i = threadIdx.x; i < G1; i += blockDim.x) h1[(int64_t)i * nb + q] = hist[i];
 }
 
-__global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__ rects, int64_t n,
-                                                      GridDev g, Blocking bl, int64_t ch1,
-                                                      const uint32_t* __restrict__ o1,
-                                                      float4* __restrict__ e1,
-                                                      uint32_t* __restrict__ e1i, int64_t cap_m1,
-                                                      DevStatus* __restrict__ st) {
-    extern __shared__ uint32_t cur[];  // [G1]
+__global__ __launch_bounds__(kL1NT) void k_l1_count(const float4* __restrict__ rects, int64_t n,
+                                                    GridDev g, Blocking bl, int64_t ch1,
+                                                    uint32_t* __restrict__ h1,
+                                                    DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t hist[];
+    l1_count_body(rects, n, g, bl, ch1, h1, st, hist, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void l1_scatter_body(const float4* __restrict__ rects,
+    int64_t n,
+    GridDev g,
+    Blocking bl,
+    int64_t ch1,
+    const uint32_t* __restrict__ o1,
+    float4* __restrict__ e1,
+    uint32_t* __restrict__ e1i,
+    int64_t cap_m1,
+    DevStatus* __restrict__ st,
+    uint32_t* cur,
+    uint32_t wg,
+    uint32_t nwg) {
     if (aborted(st)) return;
     const int64_t nb = (n + ch1 - 1) / ch1;  // chunks (the grid is rounded up to whole XCD rows)
-    const int64_t q = xcd_slot(blockIdx.x, gridDim.x);
+    const int64_t q = xcd_slot(wg, nwg);
     if (q >= nb) return;
     const int G1 = bl.cells();
     for (int i = threadIdx.x; i < G1; i += blockDim.x) cur[i] = o1[(int64_t)i * nb + q];
@@ -176,6 +197,16 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
     if (err) atomicOr(&st->flags, err);
 }
 
+__global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__ rects, int64_t n,
+                                                      GridDev g, Blocking bl, int64_t ch1,
+                                                      const uint32_t* __restrict__ o1,
+                                                      float4* __restrict__ e1,
+                                                      uint32_t* __restrict__ e1i, int64_t cap_m1,
+                                                      DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t cur[];
+    l1_scatter_body(rects, n, g, bl, ch1, o1, e1, e1i, cap_m1, st, cur, blockIdx.x, gridDim.x);
+}
+
 // Level-1 scatter with the chunk staged in LDS (grids of at most
 // kL1StageMaxG1 coarse cells, chunks of kL1StageChunk rectangles): the same
 // scheme as the staged level-2 scatter.  The chunk's rectangles (partition
@@ -185,11 +216,19 @@ __global__ __launch_bounds__(kL1NT) void k_l1_scatter(const float4* __restrict__
 constexpr int kL1Stage = 5120;  // staged level-1 entries per chunk
 static_assert(kL1StageChunk <= (1 << 16), "chunk positions take 16 bits");
 
-__global__ __launch_bounds__(1024) void k_l1_scatter_staged(
-    const float4* __restrict__ rects, int64_t n, GridDev g, Blocking bl, int64_t ch1, int64_t nb1,
-    const uint32_t* __restrict__ o1, float4* __restrict__ e1, uint32_t* __restrict__ e1i,
+__device__ __forceinline__ void l1_scatter_staged_body(const float4* __restrict__ rects,
+    int64_t n,
+    GridDev g,
+    Blocking bl,
+    int64_t ch1,
+    int64_t nb1,
+    const uint32_t* __restrict__ o1,
+    float4* __restrict__ e1,
+    uint32_t* __restrict__ e1i,
     int64_t cap_m1,
-    DevStatus* __restrict__ st) {
+    DevStatus* __restrict__ st,
+    uint32_t wg,
+    uint32_t nwg) {
     constexpr int NT = 1024;
     __shared__ float4 s_box[kL1StageChunk];
     __shared__ uint32_t s_dst[kL1Stage];
@@ -204,7 +243,7 @@ __global__ __launch_bounds__(1024) void k_l1_scatter_staged(
     const int64_t last = (int64_t)G1 * nb1;
     const uint32_t m1_total = (uint32_t)st->m1_total;
     uint32_t err = 0;
-    for (int64_t q = xcd_slot(blockIdx.x, gridDim.x); q < nb1; q += gridDim.x) {
+    for (int64_t q = xcd_slot(wg, nwg); q < nb1; q += nwg) {
         const int64_t lo = q * ch1;
         const int64_t hi = lo + ch1 < n ? lo + ch1 : n;
         // entries of this chunk per coarse cell (one cell per thread)
@@ -289,13 +328,26 @@ __global__ __launch_bounds__(1024) void k_l1_scatter_staged(
     if (err) atomicOr(&st->flags, err);
 }
 
+__global__ __launch_bounds__(1024) void k_l1_scatter_staged(
+    const float4* __restrict__ rects, int64_t n, GridDev g, Blocking bl, int64_t ch1, int64_t nb1,
+    const uint32_t* __restrict__ o1, float4* __restrict__ e1, uint32_t* __restrict__ e1i,
+    int64_t cap_m1,
+    DevStatus* __restrict__ st) {
+    l1_scatter_staged_body(rects, n, g, bl, ch1, nb1, o1, e1, e1i, cap_m1, st, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Level-2 chunk plan (one workgroup): chunks per coarse cell and their prefix.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_plan(const uint32_t* __restrict__ o1, int64_t nb1,
-                                              Blocking bl, uint32_t* __restrict__ cp,
-                                              uint32_t* __restrict__ chunk_cell,
-                                              int64_t cap_chunks, DevStatus* __restrict__ st) {
+__device__ __forceinline__ void plan_body(const uint32_t* __restrict__ o1,
+    int64_t nb1,
+    Blocking bl,
+    uint32_t* __restrict__ cp,
+    uint32_t* __restrict__ chunk_cell,
+    int64_t cap_chunks,
+    DevStatus* __restrict__ st,
+    uint32_t wg,
+    uint32_t nwg) {
     __shared__ uint32_t lds[1024 / kWave + 1];
     if (aborted(st)) return;
     const int G1 = bl.cells();
@@ -341,6 +393,13 @@ __global__ __launch_bounds__(1024) void k_plan(const uint32_t* __restrict__ o1, 
     }
 }
 
+__global__ __launch_bounds__(1024) void k_plan(const uint32_t* __restrict__ o1, int64_t nb1,
+                                              Blocking bl, uint32_t* __restrict__ cp,
+                                              uint32_t* __restrict__ chunk_cell,
+                                              int64_t cap_chunks, DevStatus* __restrict__ st) {
+    plan_body(o1, nb1, bl, cp, chunk_cell, cap_chunks, st, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Level 2 (persistent over chunks)
 // ---------------------------------------------------------------------------
@@ -381,19 +440,28 @@ __device__ __forceinline__ Local local_range(const Cells& c, const Chunk& k, con
     return l;
 }
 
-__global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e1,
-                                                    const uint32_t* __restrict__ o1, int64_t nb1,
-                                                    const uint32_t* __restrict__ cp,
-                                                    const uint32_t* __restrict__ chunk_cell,
-                                                    GridDev g, Blocking bl,
-                                                    uint32_t* __restrict__ h2,
-                                                    DevStatus* __restrict__ st) {
-    extern __shared__ uint32_t hist[];  // [B*B]
+__device__ __forceinline__ void l2_count_body(const float4* __restrict__ e1,
+    const uint32_t* __restrict__ o1,
+    int64_t nb1,
+    const uint32_t* __restrict__ cp,
+    const uint32_t* __restrict__ chunk_cell,
+    GridDev g,
+    Blocking bl,
+    uint32_t* __restrict__ h2,
+    DevStatus* __restrict__ st,
+    uint32_t* hist,
+    uint32_t wg,
+    uint32_t nwg) {
     if (aborted(st)) return;
     const int B2 = bl.tiles_per_cell();
     const uint32_t nchunks = st->n_chunks;
-    for (uint32_t q = xcd_slot(blockIdx.x, gridDim.x); q < nchunks; q += gridDim.x) {
+    for (uint32_t q = xcd_slot(wg, nwg); q < nchunks; q += nwg) {
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
+        if (k.e0 == k.e1) {  // an empty coarse cell: zero counts, no LDS pass
+            for (int t = threadIdx.x; t < B2; t += blockDim.x)
+                h2[k.h2base + (uint32_t)t * k.nch + k.c] = 0u;
+            continue;
+        }
         for (int i = threadIdx.x; i < B2; i += blockDim.x) hist[i] = 0u;
         __syncthreads();
         uint32_t e = k.e0 + threadIdx.x;
@@ -412,23 +480,40 @@ __global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e
     }
 }
 
-__global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__ e1,
-                                                      const uint32_t* __restrict__ e1i,
-                                                      const uint32_t* __restrict__ o1, int64_t nb1,
-                                                      const uint32_t* __restrict__ cp,
-                                                      const uint32_t* __restrict__ chunk_cell,
-                                                      GridDev g, Blocking bl,
-                                                      const uint32_t* __restrict__ o2,
-                                                      float4* __restrict__ entb,
-                                                      uint32_t* __restrict__ enti, int64_t cap_m,
-                                                      DevStatus* __restrict__ st) {
-    extern __shared__ uint32_t cur[];  // [B*B]
+__global__ __launch_bounds__(kL1NT) void k_l2_count(const float4* __restrict__ e1,
+                                                    const uint32_t* __restrict__ o1, int64_t nb1,
+                                                    const uint32_t* __restrict__ cp,
+                                                    const uint32_t* __restrict__ chunk_cell,
+                                                    GridDev g, Blocking bl,
+                                                    uint32_t* __restrict__ h2,
+                                                    DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t hist[];
+    l2_count_body(e1, o1, nb1, cp, chunk_cell, g, bl, h2, st, hist, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void l2_scatter_body(const float4* __restrict__ e1,
+    const uint32_t* __restrict__ e1i,
+    const uint32_t* __restrict__ o1,
+    int64_t nb1,
+    const uint32_t* __restrict__ cp,
+    const uint32_t* __restrict__ chunk_cell,
+    GridDev g,
+    Blocking bl,
+    const uint32_t* __restrict__ o2,
+    float4* __restrict__ entb,
+    uint32_t* __restrict__ enti,
+    int64_t cap_m,
+    DevStatus* __restrict__ st,
+    uint32_t* cur,
+    uint32_t wg,
+    uint32_t nwg) {
     if (aborted(st)) return;
     const int B2 = bl.tiles_per_cell();
     const uint32_t nchunks = st->n_chunks;
     uint32_t err = 0;
-    for (uint32_t q = xcd_slot(blockIdx.x, gridDim.x); q < nchunks; q += gridDim.x) {
+    for (uint32_t q = xcd_slot(wg, nwg); q < nchunks; q += nwg) {
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
+        if (k.e0 == k.e1) continue;  // an empty coarse cell: nothing to place
         for (int t = threadIdx.x; t < B2; t += blockDim.x)
             cur[t] = o2[k.h2base + (uint32_t)t * k.nch + k.c];
         __syncthreads();
@@ -467,6 +552,20 @@ __global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__
     if (err) atomicOr(&st->flags, err);
 }
 
+__global__ __launch_bounds__(kL1NT) void k_l2_scatter(const float4* __restrict__ e1,
+                                                      const uint32_t* __restrict__ e1i,
+                                                      const uint32_t* __restrict__ o1, int64_t nb1,
+                                                      const uint32_t* __restrict__ cp,
+                                                      const uint32_t* __restrict__ chunk_cell,
+                                                      GridDev g, Blocking bl,
+                                                      const uint32_t* __restrict__ o2,
+                                                      float4* __restrict__ entb,
+                                                      uint32_t* __restrict__ enti, int64_t cap_m,
+                                                      DevStatus* __restrict__ st) {
+    extern __shared__ uint32_t cur[];
+    l2_scatter_body(e1, e1i, o1, nb1, cp, chunk_cell, g, bl, o2, entb, enti, cap_m, st, cur, blockIdx.x, gridDim.x);
+}
+
 // Level-2 scatter with the chunk staged in LDS.  Scattered 32-byte stores run
 // at well under half of HBM speed on this GPU, so a workgroup keeps its
 // chunk's level-1 entries (box, id word) in LDS, ranks the chunk's tile
@@ -481,12 +580,21 @@ constexpr int kStagePer = kStageMaxB2 / kStageNT;
 constexpr uint32_t kSrcFx = 1u << 12, kSrcFy = 1u << 13;  // start bits of a staged entry
 static_assert(kChunk2 <= (1 << 12), "chunk positions take 12 bits");
 
-__global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
-    const float4* __restrict__ e1, const uint32_t* __restrict__ e1i, const uint32_t* __restrict__ o1,
+__device__ __forceinline__ void l2_scatter_staged_body(const float4* __restrict__ e1,
+    const uint32_t* __restrict__ e1i,
+    const uint32_t* __restrict__ o1,
     int64_t nb1,
-    const uint32_t* __restrict__ cp, const uint32_t* __restrict__ chunk_cell, GridDev g, Blocking bl,
-    const uint32_t* __restrict__ o2, float4* __restrict__ entb, uint32_t* __restrict__ enti,
-    int64_t cap_m, DevStatus* __restrict__ st) {
+    const uint32_t* __restrict__ cp,
+    const uint32_t* __restrict__ chunk_cell,
+    GridDev g,
+    Blocking bl,
+    const uint32_t* __restrict__ o2,
+    float4* __restrict__ entb,
+    uint32_t* __restrict__ enti,
+    int64_t cap_m,
+    DevStatus* __restrict__ st,
+    uint32_t wg,
+    uint32_t nwg) {
     __shared__ float4 s_box[kChunk2];      // the chunk's level-1 entries
     __shared__ uint32_t s_id[kChunk2];
     __shared__ uint32_t s_dst[kStage];     // destination of each staged tile entry
@@ -502,8 +610,9 @@ __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
     // the scan leaves the total in the status word, not after the last count
     const uint32_t last = (uint32_t)B2 * nchunks, m_total = (uint32_t)st->m_total;
     uint32_t err = 0;
-    for (uint32_t q = xcd_slot(blockIdx.x, gridDim.x); q < nchunks; q += gridDim.x) {
+    for (uint32_t q = xcd_slot(wg, nwg); q < nchunks; q += nwg) {
         const Chunk k = chunk_info(q, cp, chunk_cell, o1, nb1, bl);
+        if (k.e0 == k.e1) continue;  // an empty coarse cell: nothing to place
         // per-tile counts of this chunk from the scanned level-2 histogram
         uint32_t gb[kStagePer], cnt[kStagePer], sum = 0;
 #pragma unroll
@@ -605,17 +714,29 @@ __global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
     if (err) atomicOr(&st->flags, err);
 }
 
+__global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged(
+    const float4* __restrict__ e1, const uint32_t* __restrict__ e1i, const uint32_t* __restrict__ o1,
+    int64_t nb1,
+    const uint32_t* __restrict__ cp, const uint32_t* __restrict__ chunk_cell, GridDev g, Blocking bl,
+    const uint32_t* __restrict__ o2, float4* __restrict__ entb, uint32_t* __restrict__ enti,
+    int64_t cap_m, DevStatus* __restrict__ st) {
+    l2_scatter_staged_body(e1, e1i, o1, nb1, cp, chunk_cell, g, bl, o2, entb, enti, cap_m, st, blockIdx.x, gridDim.x);
+}
+
 // Segment start of every blocked tile: the start of its first chunk's
 // sub-segment; the last entry is the total.
-__global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t* __restrict__ cp,
-                                                        const uint32_t* __restrict__ o2,
-                                                        Blocking bl, uint32_t* __restrict__ off,
-                                                        DevStatus* __restrict__ st) {
+__device__ __forceinline__ void tile_offsets_body(const uint32_t* __restrict__ cp,
+    const uint32_t* __restrict__ o2,
+    Blocking bl,
+    uint32_t* __restrict__ off,
+    DevStatus* __restrict__ st,
+    uint32_t wg,
+    uint32_t nwg) {
     if (aborted(st)) return;
     const int64_t B2 = bl.tiles_per_cell();
     const int64_t Cb = (int64_t)bl.cells() * B2;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= Cb;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = (int64_t)wg * blockDim.x + threadIdx.x; t <= Cb;
+         t += (int64_t)nwg * blockDim.x) {
         if (t == Cb) {
             off[Cb] = (uint32_t)st->m_total;
             continue;
@@ -624,6 +745,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t* __restr
         const uint32_t nch = cp[cell + 1] - cp[cell];
         off[t] = o2[(uint32_t)B2 * cp[cell] + (uint32_t)lt * nch];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t* __restrict__ cp,
+                                                        const uint32_t* __restrict__ o2,
+                                                        Blocking bl, uint32_t* __restrict__ off,
+                                                        DevStatus* __restrict__ st) {
+    tile_offsets_body(cp, o2, bl, off, st, blockIdx.x, gridDim.x);
 }
 
 // ---- exclusive scan, in place allowed ----
@@ -692,14 +820,18 @@ __device__ __forceinline__ void load_tile(const uint32_t* cnt, int64_t base, int
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt,
-                                                       int64_t cmax, const uint32_t* dyn,
-                                                       int64_t mult, uint32_t* __restrict__ bs,
-                                                       const DevStatus* __restrict__ st) {
+__device__ __forceinline__ void scan_reduce_body(const uint32_t* __restrict__ cnt,
+    int64_t cmax,
+    const uint32_t* dyn,
+    int64_t mult,
+    uint32_t* __restrict__ bs,
+    const DevStatus* __restrict__ st,
+    uint32_t wg,
+    uint32_t nwg) {
     __shared__ uint32_t red[kBlock / kWave];
     if (aborted(st)) return;
     const int64_t C = scan_len(cmax, dyn, mult);
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    const int64_t base = (int64_t)wg * kScanChunk;
     if (base >= C) return;
     uint4 v[kScanRounds];
     load_tile(cnt, base, C, v);
@@ -712,8 +844,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int k = 0; k < kBlock / kWave; ++k) t += red[k];
-        bs[blockIdx.x] = t;
+        bs[wg] = t;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt,
+                                                       int64_t cmax, const uint32_t* dyn,
+                                                       int64_t mult, uint32_t* __restrict__ bs,
+                                                       const DevStatus* __restrict__ st) {
+    scan_reduce_body(cnt, cmax, dyn, mult, bs, st, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bs, int64_t cmax,
@@ -746,19 +885,17 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ bs, in
 }
 
 template <bool DIRECT>
-__global__ __launch_bounds__(kBlock) void k_scan_final(const uint32_t* cnt, int64_t cmax,
-                                                      const uint32_t* dyn, int64_t mult,
-                                                      const uint32_t* __restrict__ bs,
-                                                      uint32_t* off,
-                                                      unsigned long long* __restrict__ total_out,
-                                                      DevStatus* __restrict__ st) {
+__device__ __forceinline__ void scan_final_body(const uint32_t* cnt, int64_t cmax,
+                                                const uint32_t* dyn, int64_t mult,
+                                                const uint32_t* __restrict__ bs, uint32_t* off,
+                                                unsigned long long* __restrict__ total_out,
+                                                DevStatus* __restrict__ st, int64_t tile) {
     constexpr int kNW = kBlock / kWave;
     __shared__ uint32_t s_wsum[kScanRounds][kNW];
     __shared__ unsigned long long s_part[kNW];
     if (aborted(st)) return;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int64_t C = scan_len(cmax, dyn, mult);
-    const int64_t tile = blockIdx.x;
     const int64_t ntiles = (C + kScanChunk - 1) / kScanChunk;
     if (C == 0) {
         if (tile == 0 && tid == 0) {
@@ -835,6 +972,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const uint32_t* cnt, int6
     }
 }
 
+template <bool DIRECT>
+__global__ __launch_bounds__(kBlock) void k_scan_final(const uint32_t* cnt, int64_t cmax,
+                                                      const uint32_t* dyn, int64_t mult,
+                                                      const uint32_t* __restrict__ bs,
+                                                      uint32_t* off,
+                                                      unsigned long long* __restrict__ total_out,
+                                                      DevStatus* __restrict__ st) {
+    scan_final_body<DIRECT>(cnt, cmax, dyn, mult, bs, off, total_out, st, blockIdx.x);
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -868,6 +1015,118 @@ void scan(uint32_t* data, int64_t cmax, const uint32_t* dyn, int64_t mult, uint3
         hipLaunchKernelGGL(k_scan_final<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, data, cmax,
                            dyn, mult, bs, data, total, st);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Batched partitions: the bodies above, one launch for every partition of a
+// batch (job_slot finds a workgroup's partition).
+// ---------------------------------------------------------------------------
+__global__ void k_part_reset_b(const PartJob* __restrict__ J, int nj) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nj) *J[j].st = DevStatus{};
+}
+
+__global__ __launch_bounds__(kL1NT) void k_l1_count_b(const PartJob* __restrict__ J,
+                                                      const uint32_t* __restrict__ pre, int nj) {
+    extern __shared__ uint32_t hist[];
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    if (p.n == 0) {  // an empty input: a zero level-1 histogram
+        const int G1 = p.bl.cells();
+        for (int i = (int)t.wg * kL1NT + threadIdx.x; i < G1; i += (int)t.nwg * kL1NT) p.h1[i] = 0u;
+        return;
+    }
+    l1_count_body(p.rects, p.n, p.gd, p.bl, p.ch1, p.h1, p.st, hist, t.wg, t.nwg);
+}
+
+// the two exclusive scans of a partition: 0 = level-1 histogram (G1 * nb1
+// counters), 1 = level-2 histogram (B2 per level-2 chunk)
+struct ScanOf {
+    uint32_t* cnt;
+    int64_t cmax;
+    const uint32_t* dyn;
+    int64_t mult;
+    unsigned long long* total;
+};
+
+__device__ __forceinline__ ScanOf scan_of(const PartJob& p, int which) {
+    if (which == 0) return ScanOf{p.h1, (int64_t)p.bl.cells() * p.nb1, nullptr, 1, &p.st->m1_total};
+    const int64_t B2 = p.bl.tiles_per_cell();
+    return ScanOf{p.h2, B2 * p.cap_chunks, &p.st->n_chunks, B2, &p.st->m_total};
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce_b(const PartJob* __restrict__ J,
+                                                         const uint32_t* __restrict__ pre, int nj,
+                                                         int which) {
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    const ScanOf c = scan_of(p, which);
+    scan_reduce_body(c.cnt, c.cmax, c.dyn, c.mult, p.scan_tmp, p.st, t.wg, t.nwg);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_final_b(const PartJob* __restrict__ J,
+                                                        const uint32_t* __restrict__ pre, int nj,
+                                                        int which) {
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    const ScanOf c = scan_of(p, which);
+    scan_final_body<true>(c.cnt, c.cmax, c.dyn, c.mult, p.scan_tmp, c.cnt, c.total, p.st, t.wg);
+}
+
+__global__ __launch_bounds__(kL1NT) void k_l1_scatter_b(const PartJob* __restrict__ J,
+                                                       const uint32_t* __restrict__ pre, int nj) {
+    extern __shared__ uint32_t cur[];
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    l1_scatter_body(p.rects, p.n, p.gd, p.bl, p.ch1, p.h1, p.e1, p.e1i, p.cap_m1, p.st, cur, t.wg,
+                    t.nwg);
+}
+
+__global__ __launch_bounds__(1024) void k_l1_scatter_staged_b(const PartJob* __restrict__ J,
+                                                              const uint32_t* __restrict__ pre,
+                                                              int nj) {
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    l1_scatter_staged_body(p.rects, p.n, p.gd, p.bl, p.ch1, p.nb1, p.h1, p.e1, p.e1i, p.cap_m1,
+                           p.st, t.wg, t.nwg);
+}
+
+__global__ __launch_bounds__(1024) void k_plan_b(const PartJob* __restrict__ J) {
+    const PartJob& p = J[blockIdx.x];
+    plan_body(p.h1, p.nb1, p.bl, p.cp, p.chunk_cell, p.cap_chunks, p.st, 0, 1);
+}
+
+__global__ __launch_bounds__(kL1NT) void k_l2_count_b(const PartJob* __restrict__ J,
+                                                      const uint32_t* __restrict__ pre, int nj) {
+    extern __shared__ uint32_t hist[];
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    l2_count_body(p.e1, p.h1, p.nb1, p.cp, p.chunk_cell, p.gd, p.bl, p.h2, p.st, hist, t.wg, t.nwg);
+}
+
+__global__ __launch_bounds__(kL1NT) void k_l2_scatter_b(const PartJob* __restrict__ J,
+                                                       const uint32_t* __restrict__ pre, int nj) {
+    extern __shared__ uint32_t cur[];
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    l2_scatter_body(p.e1, p.e1i, p.h1, p.nb1, p.cp, p.chunk_cell, p.gd, p.bl, p.h2, p.entb, p.enti,
+                    p.cap_m, p.st, cur, t.wg, t.nwg);
+}
+
+__global__ __launch_bounds__(kStageNT) void k_l2_scatter_staged_b(const PartJob* __restrict__ J,
+                                                                  const uint32_t* __restrict__ pre,
+                                                                  int nj) {
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    l2_scatter_staged_body(p.e1, p.e1i, p.h1, p.nb1, p.cp, p.chunk_cell, p.gd, p.bl, p.h2, p.entb,
+                           p.enti, p.cap_m, p.st, t.wg, t.nwg);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_offsets_b(const PartJob* __restrict__ J,
+                                                          const uint32_t* __restrict__ pre, int nj) {
+    const JobSlot t = job_slot(pre, nj);
+    const PartJob& p = J[t.j];
+    tile_offsets_body(p.cp, p.h2, p.bl, p.off, p.st, t.wg, t.nwg);
 }
 
 }  // namespace
@@ -991,6 +1250,175 @@ hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, h
         const int64_t Cb = G1 * B2;
         hipLaunchKernelGGL(k_tile_offsets, dim3(grid_for(Cb + 1, kBlock, 65536)), dim3(kBlock), 0,
                            s, P.cp, P.h2, bl, P.off, P.st);
+    }
+    return hipGetLastError();
+}
+
+bool part_batchable(const Part& P, int64_t n) {
+    const int64_t G1 = P.bl.cells(), B2 = P.bl.tiles_per_cell();
+    const int64_t ch1 = l1_chunk(n, G1), nb1 = n > 0 ? (n + ch1 - 1) / ch1 : 1;
+    const int64_t t1 = (G1 * nb1 + kScanChunk - 1) / kScanChunk;
+    const int64_t t2 = (B2 * P.cap_chunks + kScanChunk - 1) / kScanChunk;
+    return t1 <= kScanDirect && t2 <= kScanDirect;
+}
+
+hipError_t part_batch_plan(PartBatch& b, Part* const* parts, const float4* const* rects,
+                           const int64_t* n, int count, int num_cus) {
+    std::vector<PartJob> jobs((size_t)std::max(count, 1));
+    std::vector<uint32_t> pre((size_t)kPlLaunches * (count + 1), 0u);
+    int64_t acc[kPlLaunches] = {};
+    int max_g1 = 1, max_b2 = 1;
+    auto x8 = [](int64_t v) { return (v + 7) / 8 * 8; };  // whole XCD rows per partition
+    for (int j = 0; j < count; ++j) {
+        Part& P = *parts[j];
+        const int64_t G1 = P.bl.cells(), B2 = P.bl.tiles_per_cell();
+        const int64_t ch1 = l1_chunk(n[j], G1);
+        const int64_t nb1 = n[j] > 0 ? (n[j] + ch1 - 1) / ch1 : 1;
+        P.nb1 = nb1;
+        PartJob& J = jobs[(size_t)j];
+        J.rects = rects[j];
+        J.n = n[j];
+        J.ch1 = ch1;
+        J.nb1 = nb1;
+        J.gd = P.gd;
+        J.bl = P.bl;
+        J.h1 = P.h1;
+        J.e1 = P.e1;
+        J.e1i = P.e1i;
+        J.cp = P.cp;
+        J.chunk_cell = P.chunk_cell;
+        J.h2 = P.h2;
+        J.entb = P.entb;
+        J.enti = P.enti;
+        J.off = P.off;
+        J.scan_tmp = P.scan_tmp;
+        J.cap_m1 = P.cap_m1;
+        J.cap_m = P.cap_m;
+        J.cap_chunks = P.cap_chunks;
+        J.st = P.st;
+        const int64_t chunks = x8(std::max<int64_t>(P.cap_chunks, 1));
+        const bool st1 = l1_staged(n[j], G1), st2 = B2 <= kStageMaxB2;
+        int64_t blk[kPlLaunches];
+        blk[kPlL1Count] = n[j] > 0 ? xcd_grid(nb1) : 8;
+        blk[kPlScan1] = x8((G1 * nb1 + kScanChunk - 1) / kScanChunk);
+        blk[kPlL1Direct] = n[j] > 0 && !st1 ? xcd_grid(nb1) : 0;
+        blk[kPlL1Staged] = n[j] > 0 && st1 ? std::min<int64_t>(xcd_grid(nb1), num_cus) : 0;
+        blk[kPlL2Count] = std::min<int64_t>(chunks, 4LL * num_cus);
+        blk[kPlScan2] = x8((B2 * P.cap_chunks + kScanChunk - 1) / kScanChunk);
+        blk[kPlL2Direct] = st2 ? 0 : std::min<int64_t>(chunks, 4LL * num_cus);
+        blk[kPlL2Staged] = st2 ? std::min<int64_t>(chunks, num_cus) : 0;
+        blk[kPlOffsets] = x8(grid_for(G1 * B2 + 1, kBlock, 65536));
+        for (int k = 0; k < kPlLaunches; ++k) {
+            pre[(size_t)k * (count + 1) + j] = (uint32_t)acc[k];
+            acc[k] += blk[k];
+        }
+        max_g1 = std::max<int>(max_g1, (int)G1);
+        max_b2 = std::max<int>(max_b2, (int)B2);
+    }
+    for (int k = 0; k < kPlLaunches; ++k) {
+        if (acc[k] >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+        pre[(size_t)k * (count + 1) + count] = (uint32_t)acc[k];
+    }
+    if (count > b.cap || !b.jobs) {
+        part_batch_free(b);
+        const int64_t cap = std::max(count, 1);
+        hipError_t e = hipMalloc((void**)&b.jobs, sizeof(PartJob) * (size_t)cap);
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&b.pre, sizeof(uint32_t) * (size_t)kPlLaunches * (cap + 1));
+        if (e != hipSuccess) {
+            part_batch_free(b);
+            return e;
+        }
+        b.cap = cap;
+    }
+    b.n = count;
+    b.max_g1 = max_g1;
+    b.max_b2 = max_b2;
+    for (int k = 0; k < kPlLaunches; ++k) b.blocks[k] = (uint32_t)acc[k];
+    hipError_t e = hipMemcpy(b.jobs, jobs.data(), sizeof(PartJob) * (size_t)std::max(count, 1),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    // prefixes at a stride of cap + 1 per launch
+    std::vector<uint32_t> dev((size_t)kPlLaunches * (b.cap + 1), 0u);
+    for (int k = 0; k < kPlLaunches; ++k)
+        std::copy(pre.begin() + (size_t)k * (count + 1), pre.begin() + (size_t)(k + 1) * (count + 1),
+                  dev.begin() + (size_t)k * (b.cap + 1));
+    return hipMemcpy(b.pre, dev.data(), sizeof(uint32_t) * dev.size(), hipMemcpyHostToDevice);
+}
+
+void part_batch_free(PartBatch& b) {
+    if (b.jobs) (void)hipFree(b.jobs);
+    if (b.pre) (void)hipFree(b.pre);
+    b = PartBatch{};
+}
+
+hipError_t run_partition_batch(const PartBatch& b, hipStream_t s) {
+    if (b.n == 0) return hipSuccess;
+    static bool attrs = false;
+    if (!attrs) {  // level-2 histograms take up to 64 KB of LDS (K = 8192)
+        const int lds = kMaxB * kMaxB * 4;
+        hipError_t e = hipFuncSetAttribute((const void*)k_l2_count_b,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_l2_scatter_b,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        attrs = true;
+    }
+    const int nj = b.n;
+    auto pre = [&](int k) { return (const uint32_t*)(b.pre + (size_t)k * (b.cap + 1)); };
+    auto grid = [&](int k) { return dim3(b.blocks[k]); };
+    hipLaunchKernelGGL(k_part_reset_b, dim3((nj + 255) / 256), dim3(256), 0, s, b.jobs, nj);
+    {
+        ProfRange pr("k_l1_count", s);
+        hipLaunchKernelGGL(k_l1_count_b, grid(kPlL1Count), dim3(kL1NT), (size_t)b.max_g1 * 4, s,
+                           b.jobs, pre(kPlL1Count), nj);
+    }
+    {
+        ProfRange pr("k_scan_l1", s);
+        hipLaunchKernelGGL(k_scan_reduce_b, grid(kPlScan1), dim3(kBlock), 0, s, b.jobs,
+                           pre(kPlScan1), nj, 0);
+        hipLaunchKernelGGL(k_scan_final_b, grid(kPlScan1), dim3(kBlock), 0, s, b.jobs,
+                           pre(kPlScan1), nj, 0);
+    }
+    {
+        ProfRange pr("k_l1_scatter", s);
+        if (b.blocks[kPlL1Staged])
+            hipLaunchKernelGGL(k_l1_scatter_staged_b, grid(kPlL1Staged), dim3(1024), 0, s, b.jobs,
+                               pre(kPlL1Staged), nj);
+        if (b.blocks[kPlL1Direct])
+            hipLaunchKernelGGL(k_l1_scatter_b, grid(kPlL1Direct), dim3(kL1NT),
+                               (size_t)b.max_g1 * 4, s, b.jobs, pre(kPlL1Direct), nj);
+    }
+    {
+        ProfRange pr("k_plan", s);
+        hipLaunchKernelGGL(k_plan_b, dim3(nj), dim3(1024), 0, s, b.jobs);
+    }
+    {
+        ProfRange pr("k_l2_count", s);
+        hipLaunchKernelGGL(k_l2_count_b, grid(kPlL2Count), dim3(kL1NT), (size_t)b.max_b2 * 4, s,
+                           b.jobs, pre(kPlL2Count), nj);
+    }
+    {
+        ProfRange pr("k_scan_l2", s);
+        hipLaunchKernelGGL(k_scan_reduce_b, grid(kPlScan2), dim3(kBlock), 0, s, b.jobs,
+                           pre(kPlScan2), nj, 1);
+        hipLaunchKernelGGL(k_scan_final_b, grid(kPlScan2), dim3(kBlock), 0, s, b.jobs,
+                           pre(kPlScan2), nj, 1);
+    }
+    {
+        ProfRange pr("k_l2_scatter", s);
+        if (b.blocks[kPlL2Staged])
+            hipLaunchKernelGGL(k_l2_scatter_staged_b, grid(kPlL2Staged), dim3(kStageNT), 0, s,
+                               b.jobs, pre(kPlL2Staged), nj);
+        if (b.blocks[kPlL2Direct])
+            hipLaunchKernelGGL(k_l2_scatter_b, grid(kPlL2Direct), dim3(kL1NT),
+                               (size_t)b.max_b2 * 4, s, b.jobs, pre(kPlL2Direct), nj);
+    }
+    {
+        ProfRange pr("k_tile_offsets", s);
+        hipLaunchKernelGGL(k_tile_offsets_b, grid(kPlOffsets), dim3(kBlock), 0, s, b.jobs,
+                           pre(kPlOffsets), nj);
     }
     return hipGetLastError();
 }

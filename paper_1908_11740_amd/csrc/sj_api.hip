@@ -104,7 +104,7 @@ bool same_grid(const sj_grid& a, const sj_grid& b) {
 
 struct DeviceState {
     JoinWork w;
-    DevStatus* host = nullptr;  // pinned: [3] (R partition, S partition, join)
+    DevStatus* host = nullptr;  // pinned [3]: readbacks; [0] ends as the last join's status
     bool init = false;
 };
 
@@ -568,6 +568,7 @@ sj_status fused_join(const float* Rr, int64_t nR, const float* Sr, int64_t nS, c
             P[i]->m1 = (int64_t)hs[i].m1_total;
         }
         if (!join_done(w, p, hs[2], capacity)) continue;
+        ds->host[0] = hs[2];  // the last join's status, as sj_join leaves it
         *pr = P[0];
         *ps = P[1];
         return join_outcome(*P[0], *P[1], p, w, hs[2], out, capacity, n_pairs, count_only,

@@ -149,6 +149,7 @@ struct __attribute__((aligned(256))) Job {
     uint32_t flags;             // kJobAxis | kJobGbda | kJobDist
     GridDev gd;                 // grid and blocking of the two partitions
     Blocking bl;
+    int64_t C;                  // tiles of the grid
 };
 static_assert(sizeof(Job) == 256, "a job descriptor is 64 words");
 
@@ -156,6 +157,68 @@ static_assert(sizeof(Job) == 256, "a job descriptor is 64 words");
 int64_t scan_block_sums_needed(int64_t C);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t run_partition(Part& P, const float4* rects, int64_t n, int num_cus, hipStream_t s);
+
+// Many partitions in one set of launches (a batch of joins): each launch of
+// the partitioning sequence runs the workgroups of every partition, and a
+// workgroup finds its partition in a prefix of the per-partition workgroup
+// counts.  PartJob is one partition as the kernels see it (device memory).
+struct PartJob {
+    const float4* rects;
+    int64_t n, ch1, nb1;
+    GridDev gd;
+    Blocking bl;
+    uint32_t* h1;
+    float4* e1;
+    uint32_t* e1i;
+    uint32_t* cp;
+    uint32_t* chunk_cell;
+    uint32_t* h2;
+    float4* entb;
+    uint32_t* enti;
+    uint32_t* off;
+    uint32_t* scan_tmp;
+    int64_t cap_m1, cap_m, cap_chunks;
+    DevStatus* st;
+};
+enum PartLaunch : int {
+    kPlL1Count = 0, kPlScan1, kPlL1Direct, kPlL1Staged, kPlL2Count, kPlScan2, kPlL2Direct,
+    kPlL2Staged, kPlOffsets, kPlLaunches
+};
+// A workgroup of a batched launch: workgroup blk belongs to the job j with
+// pre[j] <= blk < pre[j + 1] (jobs without workgroups have equal prefixes)
+// and is that job's workgroup wg of nwg.
+struct JobSlot {
+    int j;
+    uint32_t wg, nwg;
+};
+
+__device__ __forceinline__ JobSlot job_slot(const uint32_t* pre, int nj) {
+    const uint32_t blk = blockIdx.x;
+    int lo = 0, hi = nj;  // pre[lo] <= blk < pre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    return JobSlot{lo, blk - pre[lo], pre[lo + 1] - pre[lo]};
+}
+
+struct PartBatch {
+    int n = 0;                      // partitions
+    PartJob* jobs = nullptr;        // device [cap]
+    uint32_t* pre = nullptr;        // device [kPlLaunches][cap + 1] workgroup prefixes
+    int64_t cap = 0;
+    uint32_t blocks[kPlLaunches] = {};  // workgroups of every launch
+    int max_g1 = 1, max_b2 = 1;     // LDS histogram sizes of the direct kernels
+};
+// Whether the batched form serves a partition of n rectangles (prepared
+// buffers): its scans must take the direct form.
+bool part_batchable(const Part& P, int64_t n);
+// Write the job table and workgroup prefixes (host -> device, synchronous).
+hipError_t part_batch_plan(PartBatch& b, Part* const* parts, const float4* const* rects,
+                           const int64_t* n, int count, int num_cus);
+hipError_t run_partition_batch(const PartBatch& b, hipStream_t s);
+void part_batch_free(PartBatch& b);
 
 // ---------------------------------------------------------------------------
 // Join workspace and launch helpers implemented in join.hip
@@ -247,6 +310,12 @@ int batch_block();  // the small-tile workgroup shape of a batch
 hipError_t batch_reset(BatchWork& b, int n_jobs, hipStream_t s);
 hipError_t batch_classify(BatchWork& b, const Part& R, const Part& S, const JoinParams& p,
                           uint32_t jid, hipStream_t s);
+// every join's classification in one launch: p (any join's parameters) gives
+// the batch-wide caps, the job table the rest; pre: device [n_jobs + 1]
+// prefix of classify_blocks(C) per join
+hipError_t batch_classify_all(BatchWork& b, const JoinParams& p, const uint32_t* pre, int n_jobs,
+                              uint32_t blocks, hipStream_t s);
+int64_t classify_blocks(int64_t C);
 hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, bool pairs, int64_t units_bound,
                       int64_t med_bound, hipStream_t s);
 int64_t batch_scratch_chunks(int64_t pairs, int64_t units, int64_t med, int num_cus);

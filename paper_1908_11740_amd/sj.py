@@ -48,7 +48,8 @@ class Grid(ctypes.Structure):
 class Choice(ctypes.Structure):
     _fields_ = [("mean_extent", ctypes.c_double), ("k_rule", ctypes.c_int32),
                 ("k_learned", ctypes.c_int32), ("tau_learned", ctypes.c_int32),
-                ("used_learned", ctypes.c_int32), ("mean_x_extent", ctypes.c_double)]
+                ("used_learned", ctypes.c_int32), ("mean_x_extent", ctypes.c_double),
+                ("k_cap", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):

@@ -171,3 +171,19 @@ def test_batch_full_size_256_joins_element_by_element():
     st, again = b.run()
     assert st == sj.SJ_OK and list(again) == list(npairs)
     b.free()
+
+
+def test_batch_with_a_grid_beyond_the_batched_scans(joins):
+    """A join on a 4096 x 4096 grid has more level-2 counters than the
+    batched partition scans take: the batch then runs every join's
+    partitions and classification on its own stream, with the same pairs."""
+    js, refs = joins
+    grids = [(64, 0)] * len(js)
+    grids[3] = (4096, 0)
+    say("batch with a 4096 grid")
+    b = sj.Batch([(to_dev(R), to_dev(S)) for R, S in js], grids=grids,
+                 capacities=[len(r) for r in refs])
+    for rep in range(2):
+        st, n = b.run()
+        _check_batch(b, js, refs, st, n)
+    b.free()

@@ -44,6 +44,7 @@ def test_small_case_matches_the_oracle(K):
     st, n, got, parts = fused(R, S, K)
     assert st == sj.SJ_OK and n == len(ref)
     assert np.array_equal(got, ref)
+    assert sj.last_join_stats()["n_pairs"] == len(ref)
     st, n, _, _ = fused(R, S, K, cap=0, parts=parts)  # count only, same handles
     assert st == sj.SJ_OK and n == len(ref)
     for P in parts:

@@ -72,6 +72,20 @@ def test_rule_on_skewed_10m():
     assert info["used_learned"] == 0
 
 
+def test_chosen_grid_is_capped_by_the_input_size():
+    """A 2-D grid chosen for n rectangles keeps K^2 <= 8 n: 300 + 200 tiny
+    rectangles (rule K = SJ_K_MAX) get K = floor(sqrt(4000)) = 63; stripes
+    and caller-fixed grids are not capped."""
+    R = datagen.uniform(300, 1e-6, 61)
+    S = datagen.uniform(200, 1e-6, 62)
+    k, _, info = sj.choose_grid(to_dev(R), to_dev(S), flags=sj.SJ_RULE_ONLY)
+    assert info["k_rule"] == sj.SJ_K_MAX and info["k_cap"] == 63 and k == 63
+    k, _, info = sj.choose_grid(to_dev(R), to_dev(S), flags=sj.SJ_STRIPES)
+    assert info["k_cap"] == sj.SJ_K_MAX and k == info["k_rule"]
+    k, _, _ = sj.choose_grid(to_dev(R), to_dev(S), k=4000)
+    assert k == 4000
+
+
 def test_invalid_rectangle_rejected_by_choose():
     R = datagen.uniform(1000, 0.01, 5)
     R[10, 2] = np.nan
@@ -197,7 +211,10 @@ def test_choose_grid_with_loaded_picker_follows_the_network():
         l2k = np.clip(y[0] * ys[2] + ys[0], 0, 13)
         l2t = np.clip(y[1] * ys[3] + ys[1], 3, 20)
         assert info["used_learned"] == 1
-        assert abs(np.log2(k) - l2k) < 0.01 and abs(np.log2(tau) - l2t) < 0.01
+        assert abs(np.log2(info["k_learned"]) - l2k) < 0.01 and abs(np.log2(tau) - l2t) < 0.01
+        # the chosen K is the network's, at most k_cap = floor(sqrt(8 N))
+        assert info["k_cap"] == int(np.floor(np.sqrt(8.0 * (len(R) + len(S)))))
+        assert k == min(info["k_learned"], info["k_cap"])
         # the rule is still reported, and SJ_RULE_ONLY bypasses the picker
         k2, tau2, info2 = sj.choose_grid(to_dev(R), to_dev(S), flags=sj.SJ_RULE_ONLY)
         assert k2 == info["k_rule"] == 1000 and tau2 == 0 and info2["used_learned"] == 0
