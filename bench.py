@@ -94,12 +94,17 @@ def inputs(name):
     return datagen.uniform_1m()
 
 
-def kernel_bytes(name, w):
-    """Algorithmic HBM bytes of one launch (partition kernels: mean of the two
-    sides).  Entries are 20 B (box + id word), pairs 8 B."""
-    n = (w["nR"] + w["nS"]) / 2
-    m1 = (w["m1R"] + w["m1S"]) / 2
-    m = (w["mR"] + w["mS"]) / 2
+PARTITION_KERNELS = ("k_l1_count", "k_l1_scatter", "k_l2_count", "k_l2_scatter")
+
+
+def kernel_bytes(name, w, sides=1):
+    """Algorithmic HBM bytes of one launch.  A partition kernel launched for
+    one side takes the mean of the two sides (sides=1); launched once for
+    both (sj_join_rects batches them: sides=2), the sum.  Entries are 20 B
+    (box + id word), pairs 8 B."""
+    n = (w["nR"] + w["nS"]) / 2 * sides
+    m1 = (w["m1R"] + w["m1S"]) / 2 * sides
+    m = (w["mR"] + w["mS"]) / 2 * sides
     st = w["stats"]
     table = {
         "k_features": 16 * (w["nR"] + w["nS"]),
@@ -560,7 +565,9 @@ def main():
     kernels = {}
     for name, (tot, calls) in r["kern"].items():
         avg = tot / max(calls, 1)
-        b = kernel_bytes(name, w)
+        # partition kernels: one launch per side, or one for both sides
+        sides = 2 if name in PARTITION_KERNELS and calls <= args.steps else 1
+        b = kernel_bytes(name, w, sides)
         kernels[name] = {"avg_ms": round(avg, 5), "calls": calls,
                          "alg_bytes": None if b is None else int(b),
                          "gbs": None if b is None else round(b / (avg * 1e-3) / 1e9, 1)}

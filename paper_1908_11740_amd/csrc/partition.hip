@@ -30,6 +30,7 @@
 // buffers (sizes are reported in the status) and runs the partition again.
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "sj_internal.hpp"
@@ -1264,7 +1265,7 @@ bool part_batchable(const Part& P, int64_t n) {
 
 hipError_t part_batch_plan(PartBatch& b, Part* const* parts, const float4* const* rects,
                            const int64_t* n, int count, int num_cus) {
-    std::vector<PartJob> jobs((size_t)std::max(count, 1));
+    std::vector<PartJob> jobs((size_t)std::max(count, 1));  // zero-initialised, padding too
     std::vector<uint32_t> pre((size_t)kPlLaunches * (count + 1), 0u);
     int64_t acc[kPlLaunches] = {};
     int max_g1 = 1, max_b2 = 1;
@@ -1335,15 +1336,24 @@ hipError_t part_batch_plan(PartBatch& b, Part* const* parts, const float4* const
     b.max_g1 = max_g1;
     b.max_b2 = max_b2;
     for (int k = 0; k < kPlLaunches; ++k) b.blocks[k] = (uint32_t)acc[k];
-    hipError_t e = hipMemcpy(b.jobs, jobs.data(), sizeof(PartJob) * (size_t)std::max(count, 1),
-                             hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
     // prefixes at a stride of cap + 1 per launch
     std::vector<uint32_t> dev((size_t)kPlLaunches * (b.cap + 1), 0u);
     for (int k = 0; k < kPlLaunches; ++k)
         std::copy(pre.begin() + (size_t)k * (count + 1), pre.begin() + (size_t)(k + 1) * (count + 1),
                   dev.begin() + (size_t)k * (b.cap + 1));
-    return hipMemcpy(b.pre, dev.data(), sizeof(uint32_t) * dev.size(), hipMemcpyHostToDevice);
+    const bool same = b.hjobs.size() == jobs.size() && b.hpre == dev &&
+                      std::memcmp(b.hjobs.data(), jobs.data(), sizeof(PartJob) * jobs.size()) == 0;
+    if (same) return hipSuccess;  // the device already holds this plan
+    b.hjobs.clear();
+    b.hpre.clear();
+    hipError_t e = hipMemcpy(b.jobs, jobs.data(), sizeof(PartJob) * jobs.size(),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b.pre, dev.data(), sizeof(uint32_t) * dev.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    b.hjobs = std::move(jobs);
+    b.hpre = std::move(dev);
+    return hipSuccess;
 }
 
 void part_batch_free(PartBatch& b) {

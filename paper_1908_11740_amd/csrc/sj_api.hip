@@ -104,6 +104,7 @@ bool same_grid(const sj_grid& a, const sj_grid& b) {
 
 struct DeviceState {
     JoinWork w;
+    PartBatch pb;  // the two partitions of sj_join_rects as one set of launches
     DevStatus* host = nullptr;  // pinned [3]: readbacks; [0] ends as the last join's status
     bool init = false;
 };
@@ -514,14 +515,23 @@ sj_status fused_join(const float* Rr, int64_t nR, const float* Sr, int64_t nS, c
     for (int attempt = 0; attempt < 6; ++attempt) {
         hipError_t e = hipSuccess;
         if (!parts_done) {
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < 2; ++i)
                 if ((e = part_prepare(*P[i], nn[i], need_m1[i], need_m[i])) != hipSuccess)
                     return fail(from_hip(e));
-                if ((e = run_partition(*P[i], (const float4*)rin[i], nn[i], w.num_cus, s)) !=
-                    hipSuccess) {
-                    set_err("partition launch", e);
-                    return fail(from_hip(e));
-                }
+            // both inputs in one set of launches where the batched scans take
+            // them (their small launches then fill the GPU together)
+            if (part_batchable(*P[0], nn[0]) && part_batchable(*P[1], nn[1])) {
+                const float4* rr[2] = {(const float4*)rin[0], (const float4*)rin[1]};
+                Part* pp[2] = {P[0], P[1]};
+                e = part_batch_plan(ds->pb, pp, rr, nn, 2, w.num_cus);
+                if (e == hipSuccess) e = run_partition_batch(ds->pb, s);
+            } else {
+                for (int i = 0; i < 2 && e == hipSuccess; ++i)
+                    e = run_partition(*P[i], (const float4*)rin[i], nn[i], w.num_cus, s);
+            }
+            if (e != hipSuccess) {
+                set_err("partition launch", e);
+                return fail(from_hip(e));
             }
         }
         // work lists sized from the partitions' capacities (bounds of their entries)

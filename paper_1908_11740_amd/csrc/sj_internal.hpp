@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <vector>
 
 #include "../../include/sj.h"
 
@@ -210,6 +211,8 @@ struct PartBatch {
     int64_t cap = 0;
     uint32_t blocks[kPlLaunches] = {};  // workgroups of every launch
     int max_g1 = 1, max_b2 = 1;     // LDS histogram sizes of the direct kernels
+    std::vector<PartJob> hjobs;     // host copies of the uploaded tables: a plan
+    std::vector<uint32_t> hpre;     //   equal to the last one is not uploaded again
 };
 // Whether the batched form serves a partition of n rectangles (prepared
 // buffers): its scans must take the direct form.
