@@ -240,7 +240,7 @@ sj_status sj_tune_set(const sj_part* R, const sj_part* S, int32_t count_only,
  * its profiling run) join with the same schedule.  sj_tune_save writes every
  * cached entry as one text line: the device's architecture name (e.g.
  * gfx950), K, log2 |entries| of R and of S, the mode (bit 0 count only,
- * bit 1 distance join) and the schedule.  sj_tune_load adds the entries of
+ * bit 1 distance join, bit 2 SJ_STRIPES, bit 3 SJ_GBDA) and the schedule.  sj_tune_load adds the entries of
  * a file whose architecture name matches the current device (others are
  * skipped) to the cache, replacing entries of the same class; *n_loaded (may
  * be NULL) receives their count.  Errors: SJ_ERR_ARG for a NULL path, a

@@ -119,7 +119,7 @@ inline int parse_tune_line(const char* line, int k_max, TuneLine* t) {
     if (got != 10) return -1;
     if (x.block != 64 && x.block != 128 && x.block != 256 && x.block != 512) return -1;
     if (x.small_cap < 2 || x.med_cap < 2 || x.split_tau < 0 || x.k < 1 || x.k > k_max) return -1;
-    if (x.lr < 0 || x.lr > 62 || x.ls < 0 || x.ls > 62 || x.mode < 0 || x.mode > 3) return -1;
+    if (x.lr < 0 || x.lr > 62 || x.ls < 0 || x.ls > 62 || x.mode < 0 || x.mode > 15) return -1;
     *t = x;
     return 1;
 }

@@ -169,8 +169,11 @@ int log2_bucket(int64_t m) {
     return b;
 }
 
-// mode: 1 = count only, 2 = distance join (tuned apart from rectangle joins)
+// mode: bit 0 count only, bit 1 distance join; the grid adds bit 2 for
+// stripes and bit 3 for GBDA dense tiles (each tuned apart: a 1 x K grid of
+// dense stripes shares K and entry counts with a K x K grid)
 TuneKey tune_key(int dev, const sj_grid& g, int64_t mR, int64_t mS, int mode) {
+    mode |= ((g.flags & SJ_STRIPES) ? 4 : 0) | ((g.flags & SJ_GBDA) ? 8 : 0);
     return TuneKey{dev, g.k, log2_bucket(mR), log2_bucket(mS), mode};
 }
 

@@ -139,7 +139,7 @@ static void tune_lines() {
                          "gfx950 9000 2 3 0 256 256 1024 0 1.0\n",
                          "gfx950 64 2 3 0 256 1 1024 0 1.0\n",
                          "gfx950 64 2 3 0 256 256 1024 0 1.0 extra\n",
-                         "gfx950 64 2 3 7 256 256 1024 0 1.0\n"};
+                         "gfx950 64 2 3 16 256 256 1024 0 1.0\n"};
     for (const char* b : bad) CHECK(parse_tune_line(b, 8192, &u) == -1);
     // an over-long architecture name is cut at 63 characters, not overflowed
     std::string longname(200, 'g');

@@ -100,6 +100,12 @@ def test_tune_cache_save_and_load(tmp_path):
     assert sj.tune_load(path) == 1
     assert sj.tune_lookup(PR, PS)["small_cap"] == 256
     assert sj.tune_lookup(PR, PS, count_only=True) is None
+    # stripes on the same K and entry counts are another class
+    QR = sj.partition(to_dev(R), K, flags=sj.SJ_STRIPES)
+    QS = sj.partition(to_dev(S), K, flags=sj.SJ_STRIPES)
+    assert sj.tune_lookup(QR, QS) is None
+    QR.free()
+    QS.free()
     st, n = sj.join_into(PR, PS, out)
     assert st == sj.SJ_OK and np.array_equal(sort_pairs(out[:n].cpu().numpy()), ref)
     assert sj.last_join_stats()["small_cap"] == 256
