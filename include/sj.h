@@ -255,15 +255,19 @@ sj_status sj_tune_load(const char* path, int32_t* n_loaded);
  * Many independent joins in one replayable launch.  Joins, like tiles, are
  * independent tasks (Sec. 3.4): a batch plans every join once (grid from
  * grids[j], or where its k or split_tau is 0 the picker / rule of
- * sj_choose_grid), sizes its buffers and records one hipGraph: each join's
- * two partitions and its tile classification (on a few concurrent streams,
- * joins assigned longest-first), the classification appending the join's
- * work units -- span units of small tiles, medium tiles, dense tiles split
- * into pivot ranges -- tagged with the join's index to work lists shared by
- * the batch; then one sequence of join launches whose persistent workgroups
- * take the units of all joins from those lists, each pair going straight to
- * its join's slice of `out` at a position reserved on the join's counter
- * (pair order within a slice unspecified).  Every join uses the batch's
+ * sj_choose_grid), sizes its buffers and records one hipGraph: the
+ * partitioning sequence once for all 2 n_joins inputs (every launch runs the
+ * workgroups of all inputs) and one classification launch for all joins,
+ * which appends every join's work units -- span units of small tiles, medium
+ * tiles, dense tiles split into pivot ranges -- tagged with the join's index
+ * to work lists shared by the batch (a batch holding an input too large for
+ * the batched scans runs each join's partitions and classification on a few
+ * concurrent streams instead, joins assigned longest-first); then one
+ * sequence of join launches whose persistent workgroups take the units of
+ * all joins from those lists.  The pairs are staged in scratch chunks that
+ * each hold one join's pairs, and a compaction moves every chunk into its
+ * join's slice of `out` at a position reserved on the join's counter (pair
+ * order within a slice unspecified).  Every join uses the batch's
  * small-tile workgroup shape and default caps, its grid's split threshold
  * and flags; SJ_PLAIN and SJ_TWO_PASS do not apply to batches.
  * sj_batch_run replays it: one graph launch and one status readback for

@@ -2537,11 +2537,13 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
 // Batch of joins.  The classification of every join appends its records,
 // tagged with the join's index, to one set of work lists; one sequence of
 // join launches consumes the records of all joins (the joins' units are the
-// work queue of the persistent workgroups), and each pair goes straight to
-// its join's output region (kAppend).
+// work queue of the persistent workgroups).  Pairs go to scratch chunks of
+// one join each and k_compact_batch moves the chunks into the joins' output
+// regions (kSingle); count-only batches add per-wave counts to the joins'
+// fill counters (kAppend).
 // ---------------------------------------------------------------------------
 namespace {
-Args batch_args(BatchWork& b, int n_jobs) {
+Args batch_args(BatchWork& b) {
     Args a{};
     JoinWork& w = b.w;
     a.batch = 1;
@@ -2568,7 +2570,6 @@ Args batch_args(BatchWork& b, int n_jobs) {
     a.ctr = w.ctr;
     a.st = w.st;
     a.sc_total = w.sc_total;  // pairs per work class
-    (void)n_jobs;
     return a;
 }
 }  // namespace
@@ -2649,7 +2650,7 @@ hipError_t batch_classify_all(BatchWork& b, const JoinParams& p, const uint32_t*
 
 hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, bool pairs, int64_t units_bound,
                       int64_t med_bound, hipStream_t s) {
-    Args a = batch_args(b, n_jobs);
+    Args a = batch_args(b);
     pairs = pairs && b.w.sc_nch > 0;
     if (pairs) {
         a.sc_buf = b.w.sc_buf;
