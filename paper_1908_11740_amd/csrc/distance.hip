@@ -120,10 +120,11 @@ extern "C" {
 
 namespace {
 
-// Squares of both point sets, the grid (chosen when g->k is 0) and the two
-// partitions, in the device state d.  The caller holds g_dmu.
+// Squares of both point sets and the grid (chosen when g->k is 0), and,
+// with partition, the two partitions, in the device state d.  The caller
+// holds g_dmu.
 sj_status prepare(DistState& d, const float* P, int64_t nP, const float* Q, int64_t nQ, float eps,
-                  sj_grid* g, hipStream_t s) {
+                  sj_grid* g, hipStream_t s, bool partition = true) {
     if (grow_to(d.sqP, d.capP, std::max<int64_t>(nP, 1)) != hipSuccess ||
         grow_to(d.sqQ, d.capQ, std::max<int64_t>(nQ, 1)) != hipSuccess)
         return SJ_ERR_OOM;
@@ -142,6 +143,7 @@ sj_status prepare(DistState& d, const float* P, int64_t nP, const float* Q, int6
         st = sj_choose_grid((const float*)d.sqP, nP, (const float*)d.sqQ, nQ, g, nullptr, s);
         if (st != SJ_OK) return st;
     }
+    if (!partition) return SJ_OK;
     st = sj_partition((const float*)d.sqP, nP, g, &d.PP, s);
     if (st != SJ_OK) return st;
     return sj_partition((const float*)d.sqQ, nQ, g, &d.PQ, s);
@@ -173,12 +175,17 @@ sj_status sj_distance_join(const float* P, int64_t nP, const float* Q, int64_t n
     const hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g_dmu);
     DistState& d = g_ds[dev];
-    st = prepare(d, P, nP, Q, nQ, eps, g, s);
+    st = prepare(d, P, nP, Q, nQ, eps, g, s, (g->flags & SJ_PLAIN) != 0);
     if (st != SJ_OK) return st;
     // the join tests the distance of every filter pair and writes the result
-    // (sorted by (i, j) when the grid asks for it)
+    // (sorted by (i, j) when the grid asks for it); both partitions and the
+    // join with one status readback, except on the plain schedule
     int64_t cand = 0;
-    st = api_distance_pairs(d.PP, d.PQ, eps_sq(eps), out, capacity, n_pairs, &cand, s);
+    if (g->flags & SJ_PLAIN)
+        st = api_distance_pairs(d.PP, d.PQ, eps_sq(eps), out, capacity, n_pairs, &cand, s);
+    else
+        st = api_distance_fused((const float*)d.sqP, nP, (const float*)d.sqQ, nQ, g, &d.PP,
+                                &d.PQ, eps_sq(eps), out, capacity, n_pairs, &cand, s);
     if (st == SJ_OK || st == SJ_ERR_CAPACITY) d.last_candidates = cand;
     return st;
 }

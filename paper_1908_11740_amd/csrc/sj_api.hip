@@ -456,9 +456,11 @@ sj_status do_join(const sj_part* R, const sj_part* S, sj_pair* out, int64_t capa
 // Partitions of both inputs and their join with one status readback (see
 // sj_join_rects): capacities are bounds, checked on the device; when a
 // partition outgrows them, its buffers grow and the sequence runs again.
+// e2 non-null: distance join of two sets of anchored squares, as do_join.
 sj_status fused_join(const float* Rr, int64_t nR, const float* Sr, int64_t nS, const sj_grid* g,
                      sj_part** pr, sj_part** ps, sj_pair* out, int64_t capacity,
-                     int64_t* n_pairs, bool count_only, hipStream_t s) {
+                     int64_t* n_pairs, bool count_only, hipStream_t s, const double* e2 = nullptr,
+                     int64_t* cand = nullptr) {
     if (!pr || !ps || !n_pairs || nR < 0 || nS < 0 || capacity < 0) return SJ_ERR_ARG;
     if ((nR > 0 && !Rr) || (nS > 0 && !Sr) || (!count_only && capacity > 0 && !out))
         return SJ_ERR_ARG;
@@ -512,7 +514,11 @@ sj_status fused_join(const float* Rr, int64_t nR, const float* Sr, int64_t nS, c
         Q.gd = gd;
         Q.grid = grid;
     }
-    JoinParams p = tuned_params(dev, grid, mkey[0], mkey[1], count_only);
+    JoinParams p = tuned_params(dev, grid, mkey[0], mkey[1], count_only, e2 != nullptr);
+    if (e2) {
+        p.dist = true;
+        p.e2 = *e2;
+    }
     DevStatus hs[3] = {};
     bool parts_done = false;
     for (int attempt = 0; attempt < 6; ++attempt) {
@@ -585,7 +591,7 @@ sj_status fused_join(const float* Rr, int64_t nR, const float* Sr, int64_t nS, c
         *pr = P[0];
         *ps = P[1];
         return join_outcome(*P[0], *P[1], p, w, hs[2], out, capacity, n_pairs, count_only,
-                            nullptr, s);
+                            cand, s);
     }
     snprintf(g_err, sizeof(g_err), "fused join: buffers still too small after regrowth");
     return fail(SJ_ERR_DEVICE);
@@ -687,6 +693,12 @@ hipError_t api_part_prepare(Part& P, int64_t n, int64_t need_m1, int64_t need_m)
 sj_status api_distance_pairs(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
                              int64_t capacity, int64_t* n_pairs, int64_t* cand, hipStream_t s) {
     return do_join(R, S, out, capacity, n_pairs, out == nullptr, s, &e2, cand);
+}
+sj_status api_distance_fused(const float* R, int64_t nR, const float* S, int64_t nS,
+                             const sj_grid* g, sj_part** pr, sj_part** ps, double e2, sj_pair* out,
+                             int64_t capacity, int64_t* n_pairs, int64_t* cand, hipStream_t s) {
+    return fused_join(R, nR, S, nS, g, pr, ps, out, capacity, n_pairs, out == nullptr, s, &e2,
+                      cand);
 }
 sj_status api_distance_tune(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
                             int64_t capacity, int32_t reps, sj_tuning* best, hipStream_t s) {

@@ -348,6 +348,10 @@ hipError_t api_part_prepare(Part& P, int64_t n, int64_t need_m1, int64_t need_m)
 // receives the pairs the filter passed to the distance test
 sj_status api_distance_pairs(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
                              int64_t capacity, int64_t* n_pairs, int64_t* cand, hipStream_t s);
+// both partitions of the squares and the distance join with one status readback
+sj_status api_distance_fused(const float* R, int64_t nR, const float* S, int64_t nS,
+                             const sj_grid* g, sj_part** pr, sj_part** ps, double e2, sj_pair* out,
+                             int64_t capacity, int64_t* n_pairs, int64_t* cand, hipStream_t s);
 sj_status api_distance_tune(const sj_part* R, const sj_part* S, double e2, sj_pair* out,
                             int64_t capacity, int32_t reps, sj_tuning* best, hipStream_t s);
 bool prof_pause(bool pause);  // prof.hip: suspend event brackets (graph capture)

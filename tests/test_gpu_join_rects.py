@@ -125,3 +125,34 @@ def test_empty_inputs():
         assert st == sj.SJ_OK and n == 0
         for P in parts:
             P.free()
+
+
+@pytest.fixture(scope="module")
+def mid():
+    R = datagen.uniform(20000, 0.01, 51)
+    S = datagen.uniform(15000, 0.01, 52)
+    return R, S, oracle.bruteforce(R, S)
+
+
+@pytest.mark.parametrize("name", ["stripes", "gbda", "sorted", "twopass", "sweepx", "tau1"])
+def test_schedule_flags_match_the_oracle(mid, name):
+    """Every schedule flag through the one-readback path, on a grid of one
+    tile (a single dense tile), a coarse grid and a fine one."""
+    R, S, ref = mid
+    kw = {"stripes": dict(flags=sj.SJ_STRIPES), "gbda": dict(flags=sj.SJ_GBDA),
+          "sorted": dict(flags=sj.SJ_SORTED_OUTPUT), "twopass": dict(flags=sj.SJ_TWO_PASS),
+          "sweepx": dict(flags=sj.SJ_SWEEP_X), "tau1": dict(split_tau=1)}[name]
+    Rd, Sd = to_dev(R), to_dev(S)
+    parts = None
+    for K in (1, 16, 200):
+        say("join_rects", name, "K", K)
+        out = torch.empty((len(ref) + 10, 2), dtype=torch.int32, device="cuda")
+        st, n, parts = sj.join_rects(Rd, Sd, K, out=out, parts=parts, **kw)
+        assert st == sj.SJ_OK and n == len(ref), (name, K)
+        raw = out[:n].cpu().numpy()
+        if name == "sorted":  # the library's own order: no sort here
+            assert np.array_equal(raw, ref), K
+        else:
+            assert np.array_equal(sort_pairs(raw), ref), (name, K)
+    for P in parts:
+        P.free()
