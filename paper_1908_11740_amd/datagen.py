@@ -184,6 +184,19 @@ def picker_instance_spec(i):
     return InstanceSpec(n_r, n_s, k, bg, med, 4000 + int(i))
 
 
+def small_instance_spec(i):
+    """Instance i of the picker's small-input corpus: the distributions of
+    picker_instance_spec with 1e3 to 1e6 rectangles per side (the sizes of a
+    batch's joins, which the main corpus does not reach)."""
+    rng = np.random.default_rng(6000 + int(i))
+    n_r = int(round(_log_uniform(rng, 1e3, 1e6)))
+    n_s = int(round(_log_uniform(rng, 1e3, 1e6)))
+    k = int(min(500, max(1, np.floor(_log_uniform(rng, 1.0, 501.0)))))
+    bg = float(rng.uniform(0.0, 0.5))
+    med = _log_uniform(rng, 1e-5, 1e-3)
+    return InstanceSpec(n_r, n_s, k, bg, med, 6000 + int(i))
+
+
 def picker_instance(i, scale=1.0):
     """Instance i of the learned-picker corpus (sizes optionally scaled down)."""
     sp = picker_instance_spec(i)

@@ -39,15 +39,21 @@ TAUS = (64, 256, 1024, 4096)
 DEFAULT_TAU = 256
 
 
+def spec(i, kind):
+    from . import datagen
+    return {"picker": datagen.picker_instance_spec, "small": datagen.small_instance_spec,
+            "batch": datagen.batch_instance_spec}[kind](i)
+
+
 def instance(i, scale=1.0, kind="picker"):
     """Device tensors (R, S) and the spec of corpus instance i (same
-    distributions as datagen's picker / batch instances, drawn on the device)."""
+    distributions as datagen's picker / small / batch instances, drawn on the
+    device)."""
     from . import datagen, sj
-    if kind == "picker":
-        sp = datagen.picker_instance_spec(i)
+    sp = spec(i, kind)
+    if kind in ("picker", "small"):
         ext = dict(extent="lognormal", ext_a=sp.median, ext_b=1.0)
     else:
-        sp = datagen.batch_instance_spec(i)
         ext = dict(extent="uniform", ext_a=sp.median)
     mix = datagen.mixture_spec(sp.clusters, sp.seed * 7 + 1)
     nr = max(1, int(sp.n_r * scale))
@@ -67,9 +73,9 @@ def sized_instance(i, scale=1.0, kind="picker"):
     output would exceed the caps above -- the dense corner of the corpus
     (large n with extents near 1e-3) yields 1e9+ pairs per join, far beyond
     what a training label needs.  Deterministic in i."""
-    from . import datagen, sj
-    sp = datagen.picker_instance_spec(i) if kind == "picker" else datagen.batch_instance_spec(i)
-    me = sp.median * np.exp(0.5) if kind == "picker" else sp.median / 2
+    from . import sj
+    sp = spec(i, kind)
+    me = sp.median * np.exp(0.5) if kind in ("picker", "small") else sp.median / 2
     pu = sp.n_r * sp.n_s * scale * scale * (2 * me) ** 2
     if pu > P_UNIFORM_CAP:
         scale *= np.sqrt(P_UNIFORM_CAP / pu)
@@ -93,10 +99,17 @@ def sized_instance(i, scale=1.0, kind="picker"):
     return R, S, sp, scale
 
 
-def k_candidates(k_rule):
-    """Half-octave steps around the rule's K: K_rule * 2^(j/2), j = -6..6."""
-    ks = sorted({int(min(8192, max(8, round(k_rule * 2.0 ** (j / 2))))) for j in range(-6, 7)})
+def k_candidates(k_rule, lo=8):
+    """Half-octave steps around the rule's K: K_rule * 2^(j/2), j = -6..6,
+    clamped to [lo, 8192]."""
+    ks = sorted({int(min(8192, max(lo, round(k_rule * 2.0 ** (j / 2))))) for j in range(-6, 7)})
     return ks
+
+
+def capped_rule_k(k_rule, n_r, n_s):
+    """The rule's K as sj_choose_grid applies it to a 2-D grid: at most
+    sqrt(8 (nR + nS))."""
+    return int(max(1, min(k_rule, np.floor(np.sqrt(8.0 * (n_r + n_s))))))
 
 
 class Timer:
@@ -140,26 +153,33 @@ class Timer:
                 p.free()
 
 
-def collect(indices, scale=1.0, log=print):
+def collect(indices, scale=1.0, log=print, kind="picker"):
     """Features and candidate timings for corpus instances; returns a dict of
     arrays.  Label = (K, tau) of the fastest candidate: K over the rule's
-    half-octave neighbourhood at the default tau, then tau at that K."""
+    half-octave neighbourhood at the default tau, then tau at that K.  The
+    small-input corpus centres the neighbourhood on the capped rule, lets K
+    go down to 2 and takes the median of three timed runs per candidate
+    (joins of well under a millisecond)."""
     from . import sj
+    small = kind == "small"
+    reps, lo = (3, 2) if small else (1, 8)
     feats, krule, kbest, tbest, trule, tbestv, nrs, nss = [], [], [], [], [], [], [], []
     scales = []
     for c, i in enumerate(indices):
-        R, S, sp, sc = sized_instance(i, scale)
+        R, S, sp, sc = sized_instance(i, scale, kind)
         scales.append(sc)
         f, e = sj.features(R, S)
         kr = sj.rule_k(e)
+        if small:
+            kr = capped_rule_k(kr, R.shape[0], S.shape[0])
         tm = Timer(R, S)
         times = {}
-        for K in k_candidates(kr):
-            times[(K, DEFAULT_TAU)] = tm.time(K, DEFAULT_TAU)
+        for K in k_candidates(kr, lo):
+            times[(K, DEFAULT_TAU)] = tm.time(K, DEFAULT_TAU, reps=reps)
         kb = min(times, key=times.get)[0]
         for tau in TAUS:
             if (kb, tau) not in times:
-                times[(kb, tau)] = tm.time(kb, tau)
+                times[(kb, tau)] = tm.time(kb, tau, reps=reps)
         best = min(times, key=times.get)
         tm.free()
         feats.append(f.cpu().numpy())
@@ -243,15 +263,16 @@ def targets(corpus):
     return np.stack([np.log2(corpus["k_best"]), np.log2(corpus["tau_best"])], 1)
 
 
-def evaluate(indices, scale=1.0, reps=3, log=print):
+def evaluate(indices, scale=1.0, reps=3, log=print, kind="picker"):
     """Per held-out instance: time of the learned pick (tuned schedule), of
-    the rule (tuned schedule) and of the rule with the plain schedule."""
+    the rule (tuned schedule) and of the rule with the plain schedule.  The
+    rule's K is capped as sj_choose_grid caps it."""
     from . import sj
     rows = []
     for c, i in enumerate(indices):
-        R, S, _, _ = sized_instance(i, scale)
+        R, S, _, _ = sized_instance(i, scale, kind)
         kl, tl, info = sj.choose_grid(R, S)
-        kr = info["k_rule"]
+        kr = min(info["k_rule"], info["k_cap"])
         tm = Timer(R, S)
         t_learned = tm.time(kl, tl, reps=reps)
         t_rule = tm.time(kr, 0, reps=reps)
@@ -291,6 +312,7 @@ def main(argv=None):
     c.add_argument("--count", type=int, default=1800)
     c.add_argument("--scale", type=float, default=1.0)
     c.add_argument("--out", required=True)
+    c.add_argument("--kind", default="picker", choices=["picker", "small", "batch"])
     t = sub.add_parser("train")
     t.add_argument("--corpus", nargs="+", required=True)
     t.add_argument("--epochs", type=int, default=400)
@@ -301,6 +323,7 @@ def main(argv=None):
     e.add_argument("--count", type=int, default=200)
     e.add_argument("--scale", type=float, default=1.0)
     e.add_argument("--out", default=None)
+    e.add_argument("--kind", default="picker", choices=["picker", "small", "batch"])
     a = ap.parse_args(argv)
 
     def log(*x):
@@ -308,7 +331,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     if a.cmd == "collect":
-        cor = collect(range(a.start, a.start + a.count), a.scale, log)
+        cor = collect(range(a.start, a.start + a.count), a.scale, log, a.kind)
         np.savez(a.out, **cor)
         log("wrote", a.out)
     elif a.cmd == "train":
@@ -319,7 +342,7 @@ def main(argv=None):
         log("wrote", a.out)
     else:
         load(a.weights)
-        ev = evaluate(range(a.start, a.start + a.count), a.scale, log=log)
+        ev = evaluate(range(a.start, a.start + a.count), a.scale, log=log, kind=a.kind)
         if a.out:
             np.savez(a.out, **ev)
         print(json.dumps(summary(ev)), flush=True)
