@@ -294,7 +294,7 @@ def bench_batch(args, pk, sj, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS["batch256"], "joins": n, "rects": nrects,
-                   "grid_choice": "learned" if use_learned else "rule",
+                   "grid_choice": ("learned" if use_learned else "rule") + ", K^2 <= (nR + nS) / 4",
                    "grid_k_min": int(ks.min()), "grid_k_max": int(ks.max()),
                    "schedule": "one recorded graph: each partitioning launch and the "
                                "classification run the workgroups of all joins, then one set of "

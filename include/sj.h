@@ -275,7 +275,16 @@ sj_status sj_tune_load(const char* path, int32_t* n_loaded);
  *   R[j], S[j]   device rectangle arrays (as sj_partition) of nR[j], nS[j]
  *                rectangles; borrowed for the batch's lifetime (replays
  *                read them again, so their contents may change between runs).
- *   grids        n_joins grids, or NULL (all chosen).
+ *   grids        n_joins grids, or NULL (all chosen).  A K the batch
+ *                chooses (sj_choose_grid: picker or rule) is further capped
+ *                at floor(sqrt((nR + nS) / 4)) on a 2-D grid: inside one
+ *                replay a join's per-tile passes are not hidden behind call
+ *                overhead (of the caps 8N ... N/32 timed on a held-out batch
+ *                of 256 joins, N/4 replayed fastest).  A caller's K is kept.
+ *                The coarse cells of a batch's two-level partitions are
+ *                sized for the join's larger input (about 8192 rectangles
+ *                each), so that a small join does not pay for 32 x 32
+ *                nearly empty cells.
  *   out          device pair buffer, or NULL for count-only joins; join j
  *                writes [out_offsets[j], out_offsets[j+1]) (host array of
  *                n_joins + 1).  Borrowed like the inputs.

@@ -26,6 +26,7 @@
 // graph is recorded again; so does the pair scratch, from the chunk counters
 // of the run that outgrew it.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -45,6 +46,11 @@ int lds_unit_tiles(int block);
 namespace {
 
 constexpr int kLanes = 4;  // concurrent graph branches (HIP's hardware queues per process)
+// Grids chosen for a batch: at most this many tiles per input rectangle
+// (K^2 <= (nR + nS) / 4).  Of the caps 8, 4, 2, 1, 1/2, 1/4, 1/8, 1/16, 1/32
+// timed on a batch of 256 joins drawn like the 256-join benchmark batch but
+// from other seeds, 1/4 replayed fastest.
+constexpr double kBatchTilesPerRect = 0.25;
 
 template <class T>
 hipError_t grow_buf(T*& p, int64_t& cap, int64_t need, bool zero = false) {
@@ -514,8 +520,15 @@ sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t*
         b->rin[j] = (const float4*)R[j];
         b->sin[j] = (const float4*)S[j];
         if (g.k == 0 || g.split_tau == 0) {
+            const bool chosen_k = g.k == 0;
             sj_status st = sj_choose_grid(R[j], nR[j], S[j], nS[j], &g, nullptr, stream);
             if (st != SJ_OK) return fail(st);
+            // inside one replay a join's per-tile passes are not hidden behind
+            // call overhead: a chosen 2-D grid keeps K^2 <= (nR + nS) / 4
+            if (chosen_k && !(g.flags & SJ_STRIPES)) {
+                const double c = std::floor(std::sqrt(kBatchTilesPerRect * (double)(nR[j] + nS[j])));
+                g.k = std::max(1, std::min(g.k, (int32_t)c));
+            }
         }
         GridDev gd;
         sj_grid rg;
@@ -526,7 +539,9 @@ sj_status sj_batch_create(int32_t n_joins, const float* const* R, const int64_t*
             P->device = b->device;
             P->grid = rg;
             P->gd = gd;
-            P->bl = blocking_for(gd.kx, gd.ky);
+            // coarse cells sized for the join's larger input, so that the
+            // small joins of a batch fill their level-2 chunks
+            P->bl = blocking_for(gd.kx, gd.ky, std::max(nR[j], nS[j]));
         }
         b->R[j].n = nR[j];
         b->S[j].n = nS[j];

@@ -60,8 +60,11 @@ enum Ctr : int {
     kMedEntries = 7,
     kAxisTiles = 8,     // statistics: tiles that evaluated the sweeping-axis model ...
     kAxisY = 9,         // ... and those of them swept along y
-    kNumCtr = 10
+    kMedTaken = 10,     // single join: medium tiles claimed (counting or single pass) ...
+    kMedTaken2 = 11,    // ... and by the writing pass
+    kNumCtr = 12
 };
+static_assert(kNumCtr <= 16, "the join's counter array holds 16 words");
 // k_classify adds to each of these pairs of counters with one 64-bit atomic
 static_assert(kUnitsWritten == kTilesWritten + 1 && kTilesWritten % 2 == 0, "tile/unit pair");
 static_assert(kMedEntries == kSmallEntries + 1 && kSmallEntries % 2 == 0, "statistics pair");
@@ -95,6 +98,8 @@ struct Args {
     uint4* uspan;     // small units: (R start, NR, S start, NS) of the unit's entry spans
     uint2* units;     // small units: (first blocked tile, tile count)
     uint4* med;       // medium tiles: (R start, nr, S start, ns)
+    uint4* med_lpt;   // single join: the medium records by decreasing entry count
+                      // (k_med_order), claimed one at a time by the workgroups
     uint4* dense;     // dense tiles: (tile, base in dense buffer, nr, ns)
     uint32_t* dprefix;  // dense units before each dense tile
     int64_t cap_units, cap_med, cap_dense, cap_dent, cap_dunits;
@@ -1850,12 +1855,31 @@ __global__ __launch_bounds__(NT) void k_lds_medium(Args a) {
     const uint32_t nu = min(a.ctr[kMedCount], (uint32_t)a.cap_med);
     const LdsLayout L = carve(smem, NT, NT * Q, TC);
     Sink<MODE, true> sk = make_sink<MODE>(L);
+    __shared__ uint4 s_rec;
+    __shared__ uint32_t s_u;
     const uint32_t G = gridDim.x;
     const uint32_t SP = a.batch ? kMedStripe : 1u;
-    uint32_t i = 0, u = unit_of(0, blockIdx.x, G, SP);
+    // a single join claims its tiles largest first (LPT order); thread 0
+    // claims the next one as the current one starts and loads its record
+    // during the sweep, so neither wait is exposed
+    const bool dyn = !a.batch && a.med_lpt;
+    uint32_t* taken = &a.ctr[MODE == kWrite ? kMedTaken2 : kMedTaken];
+    uint32_t i = 0, u;
     uint4 pf = make_uint4(0, 0, 0, 0);
-    if (u < nu) pf = a.med[u];
-    for (; u < nu; ++i, u = unit_of(i, blockIdx.x, G, SP)) {
+    if (dyn) {
+        if (threadIdx.x == 0) {
+            const uint32_t f = atomicAdd(taken, 1u);
+            s_u = f;
+            if (f < nu) s_rec = a.med_lpt[f];
+        }
+        __syncthreads();
+        u = s_u;
+        pf = s_rec;
+    } else {
+        u = unit_of(0, blockIdx.x, G, SP);
+        if (u < nu) pf = a.med[u];
+    }
+    while (u < nu) {
         const int64_t slot = a.base_med + u;
         const uint32_t job = a.batch ? a.mjob[u] : 0u;
         const JobFlags jf = flags_of(a, job);
@@ -1864,16 +1888,72 @@ __global__ __launch_bounds__(NT) void k_lds_medium(Args a) {
         uint4 c0 = pf;
         const bool swap = (c0.y & kAxisBit) != 0;  // sweeping axis in bit 31 of the R count
         c0.y &= ~kAxisBit;
-        const uint32_t un = unit_of(i + 1, blockIdx.x, G, SP);
+        uint32_t nx = 0;
+        uint4 nrec = make_uint4(0, 0, 0, 0);
+        if (dyn && threadIdx.x == 0) nx = atomicAdd(taken, 1u);
+        const uint32_t un = dyn ? 0u : unit_of(i + 1, blockIdx.x, G, SP);
         auto prefetch = [&]() {
-            if (un < nu) pf = a.med[un];
+            if (dyn) {
+                if (threadIdx.x == 0 && nx < nu) nrec = a.med_lpt[nx];
+            } else if (un < nu) {
+                pf = a.med[un];
+            }
         };
         sk.begin(a, slot);
         run_lds_unit<NT, Q, TC, MODE>(a, src, jf.dist, jf.e2, L, 1, [&](int, int) { return c0; },
                                       prefetch, sk, swap);
-        sk.end(a, slot);
+        sk.end(a, slot);  // ends with a workgroup barrier: s_u and s_rec are free
+        if (dyn) {
+            if (threadIdx.x == 0) {
+                s_u = nx;
+                s_rec = nrec;
+            }
+            __syncthreads();
+            u = s_u;
+            pf = s_rec;
+        } else {
+            u = unit_of(++i, blockIdx.x, G, SP);
+        }
     }
     sk.finish(a, blockIdx.x * (NT / kWave) + threadIdx.x / kWave);
+}
+
+// ---------------------------------------------------------------------------
+// k_med_order (single join, one workgroup): the medium records in
+// decreasing order of their entry counts, by a counting sort over 64
+// classes of 32 entries, into med_lpt.  Largest first, the tiles claimed
+// last are the shortest, so the workgroups finish together.
+// ---------------------------------------------------------------------------
+constexpr int kOrderNT = 1024;
+constexpr int kOrderClasses = 64;
+
+__device__ __forceinline__ uint32_t med_class(const uint4& r) {
+    const uint32_t n = (r.y & ~kAxisBit) + r.w;  // <= med_cap <= kMedE
+    const uint32_t c = (n - 1u) / 32u;
+    return (uint32_t)kOrderClasses - 1u - (c < (uint32_t)kOrderClasses ? c : (uint32_t)kOrderClasses - 1u);
+}
+
+__global__ __launch_bounds__(kOrderNT) void k_med_order(Args a) {
+    __shared__ uint32_t s_cnt[kOrderClasses];
+    const uint32_t nm = min(a.ctr[kMedCount], (uint32_t)a.cap_med);
+    const int tid = threadIdx.x;
+    if (tid < kOrderClasses) s_cnt[tid] = 0u;
+    __syncthreads();
+    for (uint32_t m = tid; m < nm; m += kOrderNT) atomicAdd(&s_cnt[med_class(a.med[m])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (int c = 0; c < kOrderClasses; ++c) {
+            const uint32_t v = s_cnt[c];
+            s_cnt[c] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    for (uint32_t m = tid; m < nm; m += kOrderNT) {
+        const uint4 r = a.med[m];
+        a.med_lpt[atomicAdd(&s_cnt[med_class(r)], 1u)] = r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2428,6 +2508,7 @@ Args join_args(const Part& R, const Part& S, const JoinParams& p, const JoinWork
     a.uspan = w.uspan;
     a.units = w.units;
     a.med = w.med;
+    a.med_lpt = p.plain ? nullptr : w.med_lpt;
     a.dense = w.dense;
     a.dprefix = w.dense_unit_prefix;
     a.cap_units = w.cap_units;
@@ -2498,6 +2579,10 @@ hipError_t run_join(const Part& R, const Part& S, const JoinParams& p, JoinWork&
         hipLaunchKernelGGL(k_dense_sort, dim3(w.num_cus * 2), dim3(kDenseSortNT), 0, s, a);
     }
     hipLaunchKernelGGL(k_dense_plan, dim3(1), dim3(1024), 0, s, a);
+    if (a.med_lpt) {
+        ProfRange pr("k_med_order", s);
+        hipLaunchKernelGGL(k_med_order, dim3(1), dim3(kOrderNT), 0, s, a);
+    }
     if (single) {
         e = join_pass<kSingle>(a, p, w, s);
         if (e != hipSuccess) return e;

@@ -1155,6 +1155,38 @@ Blocking blocking_for(int kx, int ky) {
     return b;
 }
 
+// Coarse cells of about kCellTarget rectangles of the larger input: a small
+// join on the K-only blocking spreads its entries over up to 32 x 32 coarse
+// cells of a few entries each, and every cell costs a level-2 chunk (its
+// tile histogram, scan and staging pass) however few entries it holds.
+// Never more cells per axis than the K-only blocking, never fewer than keep
+// B <= kStageB (the staged level-2 kernels take the cells).  Used by the
+// batches: of the targets 2048, 4096, 8192 and 16384 timed on a batch of 256
+// joins drawn like the benchmark batch from other seeds, 8192 replayed
+// fastest.
+constexpr int64_t kCellTarget = 8192;
+constexpr int kStageB = 64;
+static_assert(kStageB * kStageB == kStageMaxB2, "B <= kStageB keeps a cell in the staged kernels");
+
+static void axis_blocking_sized(int K, int64_t m, int& G, int& B) {
+    axis_blocking(K, G, B);
+    int gs = 1;
+    while ((int64_t)gs * gs * kCellTarget < m && gs < G) ++gs;
+    const int gmin = (K + kStageB - 1) / kStageB;
+    int g = gs > gmin ? gs : gmin;
+    if (g >= G) return;
+    B = (K + g - 1) / g;
+    G = (K + B - 1) / B;
+}
+
+Blocking blocking_for(int kx, int ky, int64_t m_side) {
+    if (kx <= 1 || ky <= 1) return blocking_for(kx, ky);  // stripes: the K-only blocking
+    Blocking b;
+    axis_blocking_sized(kx, m_side, b.Gx, b.Bx);
+    axis_blocking_sized(ky, m_side, b.Gy, b.By);
+    return b;
+}
+
 // The staged level-1 scatter takes chunks of kL1StageChunk rectangles; its
 // level-1 histogram has G1 counters per chunk, so very large inputs keep the
 // direct scatter with at most kL1Blocks chunks.

@@ -238,6 +238,7 @@ sj_status join_prepare(JoinWork& w, JoinParams& p, int64_t C, int64_t mR, int64_
         if ((e = grow(w.uspan, w.cap_uspan, w.cap_units)) != hipSuccess) return from_hip(e);
         if ((e = grow(w.med, w.cap_med, p.med_bound)) != hipSuccess) return from_hip(e);
         if ((e = grow(w.medt, w.cap_medt, w.cap_med)) != hipSuccess) return from_hip(e);
+        if ((e = grow(w.med_lpt, w.cap_med_lpt, w.cap_med)) != hipSuccess) return from_hip(e);
     }
     if ((e = grow(w.dense, w.cap_dense, ndense)) != hipSuccess) return from_hip(e);
     // dense units: ceil(list / tau) per tile; with GBDA ceil per mini-join,

@@ -88,6 +88,9 @@ struct Blocking {
 };
 
 Blocking blocking_for(int kx, int ky);
+// The same grid with coarse cells sized for inputs of about m_side
+// rectangles (both inputs of a join must use one blocking).
+Blocking blocking_for(int kx, int ky, int64_t m_side);
 int64_t l1_chunk(int64_t n, int64_t G1);
 
 // ---------------------------------------------------------------------------
@@ -256,6 +259,8 @@ struct JoinWork {
     int64_t cap_med = 0;
     uint32_t* medt = nullptr;       // [cap_medt] blocked tile index of each medium tile
     int64_t cap_medt = 0;
+    uint4* med_lpt = nullptr;       // [cap_med_lpt] medium records, largest first
+    int64_t cap_med_lpt = 0;
     uint4* dense = nullptr;         // [cap_dense] (tile, base in dense buffer, nr, ns)
     uint32_t* dense_unit_prefix = nullptr;  // [cap_dense+1]
     uint32_t* dgrp = nullptr;       // [cap_dgrp] GBDA class group starts, 10 per dense tile

@@ -57,6 +57,9 @@ def test_batch_pairs_match_oracle_and_replays(joins):
     b = sj.Batch(dev, capacities=caps)
     k, tau = b.grids()
     assert np.all(k >= 1)
+    # chosen grids keep K^2 <= (nR + nS) / 4
+    for (R, S), kj in zip(js, k):
+        assert kj <= max(1, int(np.floor(np.sqrt((len(R) + len(S)) / 4)))), (len(R), len(S), kj)
     for rep in range(3):
         st, n = b.run()
         _check_batch(b, js, refs, st, n)
