@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1908_11740_amd", "tune_cache.txt"),
                     help="autotuner cache file read before tuning (a class it holds is not re-tuned)")
     ap.add_argument("--save-tune", action="store_true", help="write the autotuner cache file afterwards")
+    ap.add_argument("--tune-reps", type=int, default=2,
+                    help="timed runs per candidate schedule when a class is tuned (not in the cache)")
     ap.add_argument("--stripes", action="store_true",
                     help="one-dimensional partitioning: K vertical stripes swept along y")
     ap.add_argument("--sweep-x", action="store_true",
@@ -347,7 +349,7 @@ def bench_distance(args, pk, sj, torch):
     if not args.no_tune:
         # autotuner on the join of the squares: cached for this grid and size class
         tg = sj.make_grid(state["g"].k, state["g"].split_tau, flags=state["g"].flags)
-        tuning = sj.distance_tune(Pd, Qd, eps, tg, reps=2)
+        tuning = sj.distance_tune(Pd, Qd, eps, tg, reps=args.tune_reps)
         log("autotuned", tuning)
         step()
         torch.cuda.synchronize()
@@ -450,7 +452,10 @@ def main():
     if args.workload == "batch256":
         return bench_batch(args, pk, sj, torch)
     if args.workload == "distance10m":
-        return bench_distance(args, pk, sj, torch)
+        bench_distance(args, pk, sj, torch)
+        if not args.no_tune and args.save_tune:
+            sj.tune_save(args.tune_cache)
+        return
     log("generating", args.workload)
     R, S = inputs(args.workload)
     Rd = torch.from_numpy(R).cuda()
@@ -513,7 +518,7 @@ def main():
                 state["tuning"] = dict(cached, source="cache file")
             else:
                 state["tuning"] = sj.tune(state["PR"], state["PS"],
-                                          None if args.count else state["out"], reps=2)
+                                          None if args.count else state["out"], reps=args.tune_reps)
             log("autotuned", mode, state["tuning"])
             step(mode)
             torch.cuda.synchronize()

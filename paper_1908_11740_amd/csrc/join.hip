@@ -62,7 +62,9 @@ enum Ctr : int {
     kAxisY = 9,         // ... and those of them swept along y
     kMedTaken = 10,     // single join: medium tiles claimed (counting or single pass) ...
     kMedTaken2 = 11,    // ... and by the writing pass
-    kNumCtr = 12
+    kDenseTaken = 12,   // single join: dense units claimed (counting or single pass) ...
+    kDenseTaken2 = 13,  // ... and by the writing pass
+    kNumCtr = 14
 };
 static_assert(kNumCtr <= 16, "the join's counter array holds 16 words");
 // k_classify adds to each of these pairs of counters with one 64-bit atomic
@@ -2054,6 +2056,54 @@ __global__ __launch_bounds__(kDenseSortNT) void k_dense_sort(Args a) {
             __syncthreads();
             bitonic_lds(keys, P);
             fin = keys;
+        } else if (L <= 2u * (uint32_t)kDenseSortMax) {
+            // two sorted runs: the first kDenseSortMax keys, kept in global
+            // memory, and the rest, kept in LDS.  A key's place in the merged
+            // order is its index in its run plus the number of smaller keys
+            // in the other run (keys are distinct: they carry the position),
+            // and its entry is written there at once: a list of up to twice
+            // the LDS size needs no merge pass through global memory.
+            unsigned long long* A = a.dtmp + 2ull * dst;
+            const uint32_t n2 = L - (uint32_t)kDenseSortMax;
+            for (int i = threadIdx.x; i < kDenseSortMax; i += blockDim.x) keys[i] = key_of((uint32_t)i);
+            __syncthreads();
+            bitonic_lds(keys, kDenseSortMax);
+            for (int i = threadIdx.x; i < kDenseSortMax; i += blockDim.x) A[i] = keys[i];
+            __syncthreads();
+            int P = 1;
+            while (P < (int)n2) P <<= 1;
+            for (int i = threadIdx.x; i < P; i += blockDim.x)
+                keys[i] = i < (int)n2 ? key_of((uint32_t)kDenseSortMax + (uint32_t)i) : ~0ull;
+            __syncthreads();
+            bitonic_lds(keys, P);
+            auto place = [&](unsigned long long v, uint32_t at) {
+                const uint32_t q = (uint32_t)(v & pos_mask);
+                const float4 b = ent[src + q];
+                a.dbox[dst + at] = swap ? make_float4(b.y, b.x, b.w, b.z) : b;
+                a.didf[dst + at] = eid[src + q];
+            };
+            for (uint32_t i = threadIdx.x; i < (uint32_t)kDenseSortMax; i += blockDim.x) {
+                const unsigned long long v = A[i];
+                uint32_t b0 = 0, b1 = n2;  // keys of the LDS run below v
+                while (b0 < b1) {
+                    const uint32_t m = (b0 + b1) >> 1;
+                    if (keys[m] < v) b0 = m + 1;
+                    else b1 = m;
+                }
+                place(v, i + b0);
+            }
+            for (uint32_t j = threadIdx.x; j < n2; j += blockDim.x) {
+                const unsigned long long v = keys[j];
+                uint32_t b0 = 0, b1 = (uint32_t)kDenseSortMax;  // keys of the global run below v
+                while (b0 < b1) {
+                    const uint32_t m = (b0 + b1) >> 1;
+                    if (A[m] < v) b0 = m + 1;
+                    else b1 = m;
+                }
+                place(v, j + b0);
+            }
+            __syncthreads();
+            continue;
         } else {
             // sorted runs of kDenseSortMax in LDS, then merge passes in global
             // memory (rank of each key in the partner run by binary search;
@@ -2234,7 +2284,22 @@ __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
     const uint32_t nd = min(a.ctr[kDenseCount], (uint32_t)a.cap_dense);
     const uint32_t nu = min(a.ctr[kDenseUnits], (uint32_t)a.cap_dunits);
     const uint32_t G = gridDim.x, SP = a.batch ? kDenseStripe : 1u;
-    for (uint32_t i = 0, u = unit_of(0, blockIdx.x, G, SP); u < nu; ++i, u = unit_of(i, blockIdx.x, G, SP)) {
+    // a single join's workgroups claim the units from a counter (their scans
+    // differ widely in length); thread 0 claims the next one as a unit starts
+    __shared__ uint32_t s_u;
+    const bool dyn = !a.batch;
+    uint32_t* taken = &a.ctr[MODE == kWrite ? kDenseTaken2 : kDenseTaken];
+    uint32_t u;
+    if (dyn) {
+        if (threadIdx.x == 0) s_u = atomicAdd(taken, 1u);
+        __syncthreads();
+        u = s_u;
+    } else {
+        u = unit_of(0, blockIdx.x, G, SP);
+    }
+    for (uint32_t i = 0; u < nu; ++i) {
+        uint32_t nx = 0;
+        if (dyn && threadIdx.x == 0) nx = atomicAdd(taken, 1u);
         // dense tile of unit u: last d with dprefix[d] <= u
         uint32_t lo = 0, hi = nd;
         while (hi - lo > 1) {
@@ -2273,7 +2338,14 @@ __global__ __launch_bounds__(kDenseNT) void k_dense_sweep(Args a) {
             GlobAcc acc{a.dbox, a.didf, (int)dd.y, (int)dd.z, (int)dd.w};
             sweep_pivots<MODE, true>(a, acc, p0, p1, &s_next, sk, jf.dist, jf.e2);
         }
-        sk.end(a, slot);
+        sk.end(a, slot);  // ends with a workgroup barrier: s_u is free
+        if (dyn) {
+            if (threadIdx.x == 0) s_u = nx;
+            __syncthreads();
+            u = s_u;
+        } else {
+            u = unit_of(i + 1, blockIdx.x, G, SP);
+        }
     }
     sk.finish(a, wg);
 }

@@ -103,6 +103,26 @@ def test_dense_single_tile_large():
         assert np.array_equal(gpu_join(R, S, 1, **SCHEDULES[sched]), ref)
 
 
+def test_dense_lists_of_two_lds_runs():
+    """Lists of 8192 < L <= 16384 entries are sorted as two runs (one kept
+    in global memory, one in LDS) merged by rank: one tile of 12,000 R and
+    9,000 S rectangles, on every dense-tile schedule, with GBDA, with the
+    sweep along x and along the axis model's choice, and with elongated
+    boxes that the model sweeps along y."""
+    R = datagen.uniform(12000, 0.004, 73)
+    S = datagen.uniform(9000, 0.004, 74)
+    ref = oracle.pbsm(R, S, 16)
+    for name, kw in (("tuned", {}), ("tau1", dict(split_tau=1)), ("twopass", dict(flags=sj.SJ_TWO_PASS)),
+                     ("gbda", dict(flags=sj.SJ_GBDA)), ("sweepx", dict(flags=sj.SJ_SWEEP_X))):
+        say("two-run dense sort", name)
+        assert np.array_equal(gpu_join(R, S, 1, **kw), ref), name
+    tall = R.copy()
+    tall[:, 3] = np.minimum(tall[:, 1] + 20 * (tall[:, 3] - tall[:, 1]), 1.0).astype(np.float32)
+    ref = oracle.pbsm(tall, S, 16)
+    say("two-run dense sort, tall boxes")
+    assert np.array_equal(gpu_join(tall, S, 1), ref)
+
+
 def test_caller_domain():
     R, S, _ = datagen.small_case()
     ref = oracle.bruteforce(R, S)
