@@ -240,7 +240,11 @@ constexpr int kChunkP = 512;    // pairs per scratch chunk
 constexpr int kTotals = 64;     // spread counters of the per-wave hit totals
 constexpr int kTotalsPer = 16;  // ... per work class (small, medium, dense)
 
-template <int MODE, bool BLOCK>
+// ROTATE: every new chunk from the next region (else a wave keeps its
+// region); the single-join small-tile kernel keeps its region, since its
+// many waves of modest output fill the regions evenly and the kernel's
+// register allocation is tighter without the rotation.
+template <int MODE, bool BLOCK, bool ROTATE = true>
 struct Sink {
     unsigned long long* buf;  // this wave's LDS staging buffer
     uint32_t* s_acc;          // LDS word: pair count (kCount) or fill counter (kWrite)
@@ -322,6 +326,10 @@ struct Sink {
                 if (!have || cfill == (uint32_t)kChunkP) {
                     if (have && lane_id() == 0)
                         a.sc_fills[(size_t)region * a.sc_nch + chunk] = (uint32_t)kChunkP;
+                    // each new chunk from the next region in turn: waves differ
+                    // widely in output, and a wave that kept one region could
+                    // fill it while others have room
+                    if (ROTATE && have) region = (region + 1u) % (uint32_t)kRegions;
                     uint32_t k = 0;
                     if (lane_id() == 0) {
                         k = atomicAdd(&a.sc_ctr[region], 1u);
@@ -1112,7 +1120,7 @@ __global__ __launch_bounds__(NT, span_waves(NT, Q)) void k_span_units(Args a) {
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const uint32_t nu = min(a.ctr[kUnitsWritten], (uint32_t)a.cap_units);
     const uint32_t G = gridDim.x;
-    Sink<MODE, true> sk;
+    Sink<MODE, true, BATCH> sk;
     sk.buf = L.wbuf + w * kSpanWaveBuf;
     sk.s_acc = L.acc;
     sk.bufcap = kSpanWaveBuf;

@@ -221,14 +221,16 @@ def test_capacity_reports_required_count():
 
 def test_scratch_overflow_falls_back_to_two_passes(uniform1m, monkeypatch):
     """One scratch chunk per region cannot hold the pairs of the uniform 1M
-    join: the single pass must detect it and the call join again in two
-    passes, with the same pair set."""
+    join, even with waves moving on to other regions' chunks: the single
+    pass must detect it and the call join again in two passes, with the same
+    pair set."""
     R, S, ref = uniform1m
     K = 1024
     say("scratch overflow fallback, uniform 1M K", K)
     monkeypatch.setenv("SJ_DEBUG_SCRATCH_CHUNKS", "1")
     got = gpu_join(R, S, K)
     assert np.array_equal(got, ref)
+    assert sj.last_join_stats()["single_pass"] == 0
     PR, PS = sj.partition(to_dev(R), K), sj.partition(to_dev(S), K)
     out = torch.empty((10, 2), dtype=torch.int32, device="cuda")
     st, n = sj.join_into(PR, PS, out)
