@@ -38,6 +38,7 @@
 namespace sj {
 int64_t classify_chunk_tiles();
 int lds_medium_entries();
+int batch_medium_entries();
 int scratch_totals();
 int scratch_regions();
 int scratch_chunk_pairs();
@@ -103,7 +104,7 @@ JoinParams batch_join_params(const sj_grid& g, bool count_only) {
     p.small_cap = E / 4;
     p.unit_cap = E - p.small_cap;
     p.unit_tiles = lds_unit_tiles(p.block);
-    p.med_cap = lds_medium_entries();
+    p.med_cap = batch_medium_entries();
     return p;
 }
 
@@ -634,7 +635,7 @@ sj_status sj_batch_stats(const sj_batch* b, sj_join_stats* o) {
     const int E = 4 * batch_block();  // entries of a span unit
     o->single_pass = 1;
     o->small_cap = E / 4;
-    o->med_cap = lds_medium_entries();
+    o->med_cap = batch_medium_entries();
     return SJ_OK;
 }
 

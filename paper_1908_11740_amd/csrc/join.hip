@@ -79,6 +79,8 @@ constexpr int kSpanTQ = 2;           // tile-table words per thread: span units 
 constexpr int kMedNT = 512;          // workgroup of the medium-tile kernel
 constexpr int kBatchBlock = 256;     // small-tile workgroup of a batch of joins
 constexpr int kMedE = 2048;          // LDS entries of a medium tile
+constexpr int kBatchMedNT = 256;     // medium tiles of a batch: the half-size slab, whose
+constexpr int kBatchMedE = 1024;     // ... 4 workgroups per CU beat the full slab's 2
 constexpr int kDenseSortMax = 8192;  // entries sorted in LDS by the dense sort
 constexpr int kDenseSortNT = 1024;
 constexpr int kDenseNT = 256;
@@ -2560,6 +2562,7 @@ int lds_unit_entries(int block) { return block == 128 ? 1024 : block * 4; }
 int batch_block() { return kBatchBlock; }
 int lds_unit_tiles(int block) { return kSpanTQ * block - 1; }
 int lds_medium_entries() { return kMedE; }
+int batch_medium_entries() { return kBatchMedE; }
 int64_t classify_blocks(int64_t C) { return (C + kClassChunk - 1) / kClassChunk; }
 int64_t classify_chunk_tiles() { return kClassChunk; }
 
@@ -2848,8 +2851,8 @@ hipError_t batch_join(BatchWork& b, int n_jobs, bool any_axis, bool pairs, int64
     {
         ProfRange pr("k_lds_medium_batch", s);
         a.cls = 1;
-        e = pairs ? launch_medium<kMedNT, kMedE / kMedNT, kSingle>(a, mb, ncu, s)
-                  : launch_medium<kMedNT, kMedE / kMedNT, kAppend>(a, mb, ncu, s);
+        e = pairs ? launch_medium<kBatchMedNT, kBatchMedE / kBatchMedNT, kSingle>(a, mb, ncu, s)
+                  : launch_medium<kBatchMedNT, kBatchMedE / kBatchMedNT, kAppend>(a, mb, ncu, s);
         if (e != hipSuccess) return e;
     }
     {
